@@ -1,0 +1,594 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test names what fixes the expected value: a published test vector, the
+paper's worked example, a closed form, an invariant, a library routine, a
+brute-force count, the paper's dense tensor form, or central differences of
+the frozen surrogate.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ST_EXITED, ST_ON, ST_QUEUED, ST_WAIT, Oracle
+from paper_2603_25068_amd import workloads as W
+from tests import dense_paper
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10: known-answer vectors published with the generator (Random123
+# distribution, kat_vectors; Salmon et al., SC'11).
+# ---------------------------------------------------------------------------
+def _load_kat():
+    rows = []
+    with open("tests/golden/philox4x32_10_kat.txt") as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,expect", _load_kat())
+def test_philox_known_answers(ctr, key, expect):
+    out = oracle.philox(ctr, key)
+    assert [int(x) for x in out] == expect
+
+
+def test_uniform_exact_and_in_open_interval():
+    # U = (top 24 bits + 0.5) * 2^-24 = odd / 2^25: exact in double, never 0 or 1
+    us = np.array([oracle.uniform(123, a, t, 0, w) for a in range(50) for t in range(20) for w in range(4)])
+    assert np.all(us > 0) and np.all(us < 1)
+    k = us * 2 ** 25
+    assert np.all(k == np.round(k)) and np.all(k % 2 == 1)
+
+
+def test_uniform_chi_square():
+    n, bins = 40000, 20
+    us = np.array([oracle.uniform(7, a, 3, 0, 0) for a in range(n)])
+    h, _ = np.histogram(us, bins=bins, range=(0, 1))
+    chi2 = ((h - n / bins) ** 2 / (n / bins)).sum()
+    # 19 dof: P(chi2 > 43.8) ~ 1e-3
+    assert chi2 < 43.8
+
+
+# ---------------------------------------------------------------------------
+# Trajectory-grafting toy (SI-C): the paper reports that gradient descent
+# with lr 1e-2 from (u1, u2) = (2, 1) ends near (1.5, 0.9) with TG and near
+# (2.0, 0) without it.  Iterates worked out by hand from the model:
+# (2, 1): the agent is capped at x'=16 on link 1 in its 8th step and sits at
+# x = 2 on link 2 at t = 10; dl/du1 = 2x*8 = 32, dl/du2 = 2x*2 = 8.
+# ---------------------------------------------------------------------------
+def _toy(u1, u2, transfer_graft=True, variant="f64"):
+    w = W.tg_toy(u1, u2)
+    o = Oracle(w, log=True, variant=variant)
+    o.place([0], [0], [0.0])
+    o.run(10)
+    st = o.state()
+    assert st["link"][0] == 1 and st["status"][0] == ST_ON
+    x = st["pos"][0]
+    g = o.backward(gx=np.array([2.0 * x]), transfer_graft=transfer_graft)["free_speed"]
+    return x, g
+
+
+def test_tg_toy_first_iterates():
+    x, g = _toy(2.0, 1.0)
+    assert x == 2.0
+    assert g[0] == pytest.approx(32.0, abs=1e-9) and g[1] == pytest.approx(8.0, abs=1e-9)
+    u1, u2 = np.float32(2.0 - 0.01 * 32.0), np.float32(1.0 - 0.01 * 8.0)
+    x, g = _toy(u1, u2)
+    assert x == pytest.approx(0.92, abs=1e-6)
+    assert g[0] == pytest.approx(2 * 0.92 * 9, rel=1e-6) and g[1] == pytest.approx(2 * 0.92, rel=1e-6)
+
+
+def test_tg_toy_descent_with_and_without_graft():
+    # with TG: converges to (1.5144, 0.9016) ~ (1.5, 0.9), loss 0
+    u = np.array([2.0, 1.0])
+    for _ in range(20):
+        x, g = _toy(*u)
+        if x == 0.0:
+            break
+        u = (u - 0.01 * g).astype(np.float32).astype(np.float64)
+    assert x == 0.0
+    assert u[0] == pytest.approx(1.5144, abs=1e-5) and u[1] == pytest.approx(0.9016, abs=1e-5)
+    # without TG: dl/du1 == 0, u1 stays at 2.0 and u2 decays towards 0
+    u = np.array([2.0, 1.0])
+    for _ in range(60):
+        x, g = _toy(*u, transfer_graft=False)
+        assert g[0] == 0.0
+        u = (u - 0.01 * g).astype(np.float32).astype(np.float64)
+    assert u[0] == 2.0 and u[1] < 0.02
+
+
+# ---------------------------------------------------------------------------
+# Closed forms of the forward
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["f32", "f64"])
+@pytest.mark.parametrize("length,speed", [(200.0, 13.9), (150.0, 11.1), (333.0, 16.7)])
+def test_lone_vehicle_free_flow_travel_time(variant, length, speed):
+    """One vehicle on an empty 3-link corridor: it needs ceil((L-0.01)/(u dt))
+    steps per link (the arrival mask uses x >= L - 1e-2), enters link 0 in
+    step 0 and leaves the network in step 3k."""
+    n = 3
+    w = W.line(n_links=n, length=length, speed=speed, steps=400)
+    o = Oracle(w, variant=variant)
+    k = math.ceil((np.float32(length) - 0.01) / np.float32(speed))
+    exit_step = None
+    for t in range(400):
+        o.step()
+        if o.state()["status"][0] == ST_EXITED:
+            exit_step = t
+            break
+    assert exit_step == n * k
+    _, ttt = o.counts()
+    assert ttt == n * k * 1.0
+
+
+def test_throughput_at_capacity_token_bucket():
+    """Saturated upstream, free downstream, capacity 0.25 veh/s on one lane:
+    after the first departure at step t0 the link releases one vehicle each
+    time the bucket reaches 1, so E(t0+k) = 1 + floor((k+1)/4)."""
+    w = W.line(n_links=2, length=200.0, capacity=0.25, n_agents=60, steps=200)
+    o = Oracle(w)
+    E = []
+    for t in range(200):
+        o.step()
+        E.append(int(o.link_state()["E"][0]))
+    E = np.array(E)
+    t0 = int(np.argmax(E > 0))
+    k = np.arange(0, 200 - t0)
+    expect = 1 + np.floor((k + 1) / 4)
+    # saturation holds while vehicles remain queued on link 0
+    until = int(np.searchsorted(E, 60)) - t0
+    assert np.array_equal(E[t0:t0 + until], expect[:until])
+
+
+def test_newell_leader_constraint_on_a_corridor():
+    """Methods eq. newell_model with tau = dn = 1: a follower never ends a
+    step ahead of (its leader's position at the start of the step) - dn/kappa,
+    and never ahead of its free-flow reach x + u dt."""
+    w = W.line(n_links=2, length=200.0, capacity=0.4, n_agents=80, steps=260)
+    o = Oracle(w, variant="f64")
+    s = 1.0 / float(np.float32(0.2))
+    u = float(np.float32(13.9))
+    checked = 0
+    for t in range(260):
+        st0 = o.state()
+        o.step()
+        st1 = o.state()
+        for j in (0, 1):
+            on = np.where((st0["status"] == ST_ON) & (st0["link"] == j))[0]
+            order = on[np.lexsort((st0["seq"][on], -st0["pos"][on]))]
+            for r in range(1, len(order)):
+                a, lead = order[r], order[r - 1]
+                if st1["link"][a] != j:
+                    continue
+                assert st1["pos"][a] <= st0["pos"][lead] - s + 1e-9
+                assert st1["pos"][a] <= st0["pos"][a] + u + 1e-9
+                checked += 1
+    assert checked > 1000
+
+
+def test_jam_spacing_closed_form():
+    """Vehicles behind a head that can never leave (capacity 0) stand at
+    L - k * dn/kappa, the jam spacing of Newell's model."""
+    w = W.line(n_links=2, length=200.0, capacity=0.0, n_agents=12, steps=200)
+    o = Oracle(w, variant="f64")
+    o.run(200)
+    st = o.state()
+    on0 = np.sort(st["pos"][(st["status"] == ST_ON) & (st["link"] == 0)])[::-1]
+    assert len(on0) >= 10
+    s = 1.0 / np.float32(0.2)
+    assert np.allclose(on0, 200.0 - s * np.arange(len(on0)), atol=1e-9)
+
+
+def test_departure_release_closed_form():
+    """Constant rate r from one origin: releases by the end of step t are
+    floor(r (t+1) dt) (the accumulator crosses k+1 at t*_k = (k+1)/r)."""
+    w = W.line(n_links=2, length=200.0, n_agents=500, steps=300)
+    w.dem.ready_time = None
+    w.dem.rates = np.full((1, 3), 0.3, np.float32)
+    w.dem.rate_bin_s = 100.0
+    o = Oracle(w)
+    r = float(np.float32(0.3))
+    for t in range(300):
+        o.step()
+        rel = o.origin_state()["released"][0]
+        assert rel == min(500, math.floor(r * (t + 1) + 1e-12))
+
+
+# ---------------------------------------------------------------------------
+# Invariants: conservation, bounds, monotone positions, FIFO, jam spacing
+# ---------------------------------------------------------------------------
+def _check_invariants(w, o, steps, check_every=1):
+    net = w.net
+    L = net.length.astype(np.float64)
+    s = 1.0 / net.jam_density.astype(np.float32)
+    prev = o.state()
+    for t in range(steps):
+        o.step()
+        if t % check_every:
+            continue
+        st = o.state()
+        c = o.counters()
+        ls = o.link_state()
+        status = st["status"]
+        # conservation, integer-exact
+        assert c["released"] == np.sum(status != ST_WAIT)
+        assert c["departed"] == np.sum((status == ST_ON) | (status == ST_EXITED))
+        assert c["exited"] == np.sum(status == ST_EXITED)
+        assert ls["E"].sum() == c["transfers"] + c["exited"]
+        on = status == ST_ON
+        x, lk, sq = st["pos"][on], st["link"][on], st["seq"][on]
+        # bounds
+        assert np.all(x >= 0) and np.all(x <= L[lk])
+        # positions never decrease while on the same link
+        same = on & (prev["status"] == ST_ON) & (prev["link"] == st["link"]) & (prev["seq"] == st["seq"])
+        assert np.all(st["pos"][same] >= prev["pos"][same])
+        # FIFO and spacing per link
+        for j in np.unique(lk):
+            m = lk == j
+            order = np.argsort(sq[m])
+            xs = x[m][order]
+            assert np.all(np.diff(xs) <= 0), "entry order and position order disagree"
+            ln = net.lanes[j]
+            if len(xs) > ln:
+                gap = xs[:-ln] - xs[ln:]
+                assert np.all(gap >= s[j] - 1e-3)
+        assert c["order_viol"] == 0
+        prev = st
+
+
+def test_invariants_small_grid():
+    w = W.small_grid_fixed()
+    _check_invariants(w, Oracle(w), 900, check_every=3)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_invariants_random_small(seed):
+    w = W.random_small(seed, n_agents=120, rates=(seed % 2 == 0))
+    _check_invariants(w, Oracle(w), w.cfg.steps)
+
+
+def test_invariants_congested_diamond():
+    w = W.diamond(n_agents=300, lanes=2, capacity=0.3)
+    _check_invariants(w, Oracle(w), w.cfg.steps)
+
+
+# ---------------------------------------------------------------------------
+# Shortest free-flow times: against scipy's Dijkstra (a library routine)
+# ---------------------------------------------------------------------------
+def test_shortest_times_match_scipy():
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra
+    w = W.random_small(5, nx=5, ny=4, n_agents=80)
+    o = Oracle(w)
+    net = w.net
+    wgt = net.length.astype(np.float64) / net.free_speed.astype(np.float64)
+    G = csr_matrix((wgt, (net.tail, net.head)), shape=(net.n_nodes, net.n_nodes))
+    dests = np.unique(w.dem.agent_dest)
+    ref = dijkstra(G.T, indices=dests)          # distances *to* each destination
+    got = o.dist_table()
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Gumbel-max (SI-B): the hard choice is a draw from softmax(V); the merge
+# winner is a draw from softmax(alpha_from)
+# ---------------------------------------------------------------------------
+def _star(betas, n_agents, alphas=None):
+    """Origin 0 with out-links to 1..k, each continuing to sink k+1; three
+    lanes everywhere so an entry slot is always free and no choice is
+    rejected (a rejected chooser would redraw next step)."""
+    k = len(betas)
+    tail = [0] * k + list(range(1, k + 1))
+    head = list(range(1, k + 1)) + [k + 1] * k
+    Lk = 2 * k
+    net = W.Network(
+        n_nodes=k + 2, tail=np.int32(tail), head=np.int32(head), lanes=np.full(Lk, 3, np.int32),
+        length=np.full(Lk, 100.0, np.float32), free_speed=np.full(Lk, 13.9, np.float32),
+        jam_density=np.full(Lk, 0.2, np.float32), capacity=np.full(Lk, 10.0, np.float32),
+        beta=np.float32(list(betas) + [0] * k), alpha=np.ones(Lk, np.float32) if alphas is None else np.float32(alphas),
+        cost=np.ones(Lk, np.float32), origin_node=np.int32([0]),
+        detector_link=np.int32([0]), detector_pos=np.float32([50.0]))
+    dem = W.Demand(agent_origin=np.zeros(n_agents, np.int32), agent_dest=np.full(n_agents, k + 1, np.int32),
+                   ready_time=np.zeros(n_agents, np.float32))
+    cfg = W.Config(dt=1.0, steps=n_agents + 200, count_bin_steps=10 ** 6, dest_logit_coef=0.0, seed=11)
+    return W.Workload("star", net, dem, cfg)
+
+
+def test_route_choice_frequencies_are_softmax():
+    betas = [0.0, 0.7, 1.5]
+    n = 3000
+    w = _star(betas, n)
+    o = Oracle(w)
+    o.run()
+    E = o.link_state()["E"][:3]
+    assert E.sum() == n
+    p = np.exp(betas) / np.exp(betas).sum()
+    chi2 = ((E - n * p) ** 2 / (n * p)).sum()
+    assert chi2 < 13.8   # 2 dof, P ~ 1e-3
+
+
+def test_merge_winner_frequencies_are_softmax_alpha():
+    """Two one-lane links merge into one; both heads always want it.  The
+    first winner of each contested step is drawn with P ~ exp(alpha)."""
+    alphas = [0.2, 1.4]
+    # nodes: 0 -> 2 (link 0), 1 -> 2 (link 1), 2 -> 3 (link 2, the merge target)
+    net = W.Network(
+        n_nodes=4, tail=np.int32([0, 1, 2]), head=np.int32([2, 2, 3]), lanes=np.ones(3, np.int32),
+        length=np.float32([30.0, 30.0, 30.0]), free_speed=np.full(3, 30.0, np.float32),
+        jam_density=np.full(3, 0.2, np.float32), capacity=np.full(3, 10.0, np.float32),
+        beta=np.zeros(3, np.float32), alpha=np.float32(alphas + [1.0]), cost=np.ones(3, np.float32),
+        origin_node=np.int32([0, 1]), detector_link=np.int32([2]), detector_pos=np.float32([15.0]))
+    n = 4000
+    dem = W.Demand(agent_origin=np.int32(np.arange(n) % 2), agent_dest=np.full(n, 3, np.int32),
+                   ready_time=np.zeros(n, np.float32))
+    cfg = W.Config(dt=1.0, steps=n + 60, count_bin_steps=10 ** 6, seed=5)
+    w = W.Workload("merge", net, dem, cfg)
+    o = Oracle(w)
+    wins = np.zeros(2)
+    prevE = np.zeros(3, np.int64)
+    for t in range(2000):
+        before = o.link_state()["E"].copy()
+        o.step()
+        E = o.link_state()["E"]
+        d = E - before
+        # contested steps: exactly one of the two links released (target slot 1)
+        if d[0] + d[1] == 1:
+            wins += d[:2]
+        prevE = E
+    p = np.exp(alphas) / np.exp(alphas).sum()
+    n_w = wins.sum()
+    assert n_w > 1000
+    chi2 = ((wins - n_w * p) ** 2 / (n_w * p)).sum()
+    assert chi2 < 10.8   # 1 dof, P ~ 1e-3
+    del prevE
+
+
+def test_forward_is_independent_of_tau():
+    """The hard choice is argmax(V + g), which the temperature does not move."""
+    w = W.random_small(4, n_agents=100)
+    a = Oracle(w).run()
+    w.cfg.gumbel_tau = 0.01
+    b = Oracle(w).run()
+    sa, sb = a.state(), b.state()
+    for k in ("status", "link", "seq"):
+        assert np.array_equal(sa[k], sb[k])
+    assert np.array_equal(sa["pos"], sb["pos"])
+
+
+# ---------------------------------------------------------------------------
+# Sparse oracle == the paper's dense formulation, step by step (one lane,
+# capacity not binding, no destination term, agents placed on links)
+# ---------------------------------------------------------------------------
+def _dense_case(seed):
+    rng = np.random.default_rng(seed)
+    # diamond with reverse links plus a long one-way link 3 -> 4 (a far sink)
+    roads = [(0, 1), (0, 2), (1, 3), (2, 3)]
+    tail, head = [], []
+    for a, b in roads:
+        tail += [a, b]
+        head += [b, a]
+    tail.append(3)
+    head.append(4)
+    Lk = len(tail)
+    length = np.float32(list(np.repeat(rng.uniform(60, 120, 4), 2)) + [1e6])
+    net = W.Network(
+        n_nodes=5, tail=np.int32(tail), head=np.int32(head), lanes=np.ones(Lk, np.int32),
+        length=length, free_speed=np.float32(rng.choice([11.1, 13.9, 16.7], Lk)),
+        jam_density=np.float32(rng.uniform(0.15, 0.25, Lk)), capacity=np.full(Lk, 10.0, np.float32),
+        beta=np.float32(rng.uniform(0, 2, Lk)), alpha=np.float32(rng.uniform(0.5, 3, Lk)),
+        cost=np.float32(rng.uniform(0.5, 2, Lk)), origin_node=np.int32([0]),
+        detector_link=np.int32([0]), detector_pos=np.float32([length[0] / 2]))
+    n = 14
+    dem = W.Demand(agent_origin=np.zeros(n, np.int32), agent_dest=np.full(n, 4, np.int32),
+                   ready_time=np.full(n, 1e9, np.float32))
+    cfg = W.Config(dt=1.0, steps=80, count_bin_steps=10 ** 6, dest_logit_coef=0.0, seed=seed)
+    w = W.Workload("dense", net, dem, cfg)
+    # place agents on the 8 diamond links, spaced more than a jam spacing apart
+    agents, links, pos = [], [], []
+    a = 0
+    for j in range(8):
+        k = rng.integers(0, 3)
+        xs = np.sort(rng.uniform(0, float(length[j]) - 1, size=k))[::-1]
+        ok = [x for i, x in enumerate(xs) if i == 0 or xs[i - 1] - x > 8.0]
+        for x in ok:
+            if a < n:
+                agents.append(a); links.append(j); pos.append(np.float32(x)); a += 1
+    return w, np.array(agents[:a]), np.array(links[:a]), np.array(pos[:a])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_sparse_equals_dense_paper_form(seed):
+    w, agents, links, pos = _dense_case(seed)
+    net = w.net
+    n_ag, Lk = len(agents), net.n_links
+    o = Oracle(w, variant="f64", seed=seed)
+    o.place(agents, links, pos)
+    M = 99999.0
+    X = np.full((n_ag, Lk), -M)
+    X[np.arange(n_ag), links] = pos.astype(np.float64)
+    A = (net.head[:, None] == net.tail[None, :]).astype(float)
+    outs = {v: [j for j in range(Lk) if net.tail[j] == v] for v in range(net.n_nodes)}
+    cidx = np.zeros(Lk, int)
+    for v, js in outs.items():
+        for c, j in enumerate(js):
+            cidx[j] = c
+    u = net.free_speed.astype(np.float64)
+    kap = net.jam_density.astype(np.float64)
+    Ln = net.length.astype(np.float64)
+    for t in range(w.cfg.steps):
+        Xf = dense_paper.car_following(X, u, kap, Ln, 1.0, 1.0, M)
+        G = np.array([[oracle.gumbel(seed, int(agents[i]), t, 0, int(cidx[m])) for m in range(Lk)]
+                      for i in range(n_ag)])
+        Gm = np.array([[oracle.gumbel(seed, int(agents[i]), t, 1, 0) for i in range(n_ag)] for m in range(Lk)])
+        X = dense_paper.node_model(Xf, A, net.alpha.astype(float), net.beta.astype(float),
+                                   net.cost.astype(float), kap, Ln, 1.0, M, G, Gm)
+        o.step()
+        st = o.state()
+        dl = np.argmax(X > -1.0, axis=1)
+        dx = X[np.arange(n_ag), dl]
+        assert np.array_equal(st["link"][agents], dl), f"step {t}"
+        np.testing.assert_allclose(st["pos"][agents], dx, rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Float-position oracle == double-position oracle on the integer state
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mk", [W.small_grid_fixed, lambda: W.diamond(200, lanes=2)])
+def test_position_precision_does_not_move_decisions(mk):
+    w = mk()
+    a = Oracle(w, variant="f32").run()
+    b = Oracle(w, variant="f64").run()
+    sa, sb = a.state(), b.state()
+    for k in ("status", "link", "seq"):
+        assert np.array_equal(sa[k], sb[k])
+    np.testing.assert_allclose(sa["pos"], sb["pos"], rtol=1e-5, atol=1e-4)
+    ca, ta = a.counts()
+    cb, tb = b.counts()
+    assert np.array_equal(ca, cb) and ta == tb
+
+
+# ---------------------------------------------------------------------------
+# Adjoint == exact derivative of the frozen surrogate (central differences in
+# FP64), and closed-form gradients
+# ---------------------------------------------------------------------------
+def _fd_directional(o, base, direction, which, h):
+    kw_p = {k: v.copy() for k, v in base.items()}
+    kw_m = {k: v.copy() for k, v in base.items()}
+    kw_p[which] = kw_p[which] + h * direction
+    kw_m[which] = kw_m[which] - h * direction
+    cp, tp, xp = o.frozen(**kw_p)
+    cm, tm, xm = o.frozen(**kw_m)
+    return (cp - cm) / (2 * h), (tp - tm) / (2 * h), (xp - xm) / (2 * h)
+
+
+@pytest.mark.parametrize("seed", [2, 6, 8])
+def test_adjoint_matches_frozen_surrogate_fd(seed):
+    w = W.random_small(seed, nx=3, ny=3, n_agents=150, rates=True, steps=240)
+    o = Oracle(w, variant="f64", log=True)
+    o.run()
+    net = w.net
+    base = {"u": net.free_speed.astype(np.float64), "kappa": net.jam_density.astype(np.float64),
+            "rates": w.dem.rates.astype(np.float64)}
+    c0, t0, x0 = o.frozen(**base, record_base=True)
+    cnt, ttt = o.counts()
+    np.testing.assert_allclose(c0, cnt, atol=1e-9)    # surrogate value == forward value
+    assert t0 == pytest.approx(ttt, abs=1e-9)
+    rng = np.random.default_rng(seed)
+    gQ = rng.normal(size=c0.shape)
+    gT = 0.37
+    st = o.state()
+    gx = rng.normal(size=x0.shape) * (st["status"] == ST_ON)
+    g = o.backward(gQ=gQ, gT=gT, gx=gx)
+    for which, key in (("u", "free_speed"), ("kappa", "jam_density"), ("rates", "rates")):
+        d = rng.normal(size=base[which].shape)
+        h = 1e-6 * max(1.0, float(np.abs(base[which]).max()))
+        if which == "rates":
+            h = 1e-7
+        dc, dt_, dx = _fd_directional(o, base, d, which, h)
+        fd = (gQ * dc).sum() + gT * dt_ + (gx * dx).sum()
+        ad = (g[key] * d).sum()
+        assert ad == pytest.approx(fd, rel=1e-6, abs=1e-8), which
+
+
+def test_free_flow_gradient_closed_form():
+    """Lone vehicle: dx(T)/du_j = dt x (steps spent on link j), carried across
+    the transfer by the graft."""
+    w = W.line(n_links=3, length=100.0, speed=13.9, steps=20)
+    o = Oracle(w, variant="f64", log=True)
+    o.place([0], [0], [0.0])
+    o.run(20)
+    st = o.state()
+    assert st["link"][0] == 2
+    g = o.backward(gx=np.array([1.0]))["free_speed"]
+    k = math.ceil((100.0 - 0.01) / np.float32(13.9))
+    assert g[0] == k and g[1] == k and g[2] == 20 - 2 * k
+
+
+def test_jam_gradient_closed_form():
+    """k-th vehicle behind a head that never leaves stands at L - k dn/kappa:
+    d x_k / d kappa = k dn / kappa^2 (plus whatever the head carries, which
+    is d/du only)."""
+    w = W.line(n_links=2, length=200.0, capacity=0.0, n_agents=6, steps=120)
+    o = Oracle(w, variant="f64", log=True)
+    o.run(120)
+    st = o.state()
+    on0 = np.where((st["status"] == ST_ON) & (st["link"] == 0))[0]
+    order = on0[np.argsort(-st["pos"][on0])]
+    kap = float(np.float32(0.2))
+    for k, a in enumerate(order):
+        gx = np.zeros(w.dem.n_agents)
+        gx[a] = 1.0
+        g = o.backward(gx=gx)["jam_density"]
+        assert g[0] == pytest.approx(k / kap ** 2, rel=1e-12)
+
+
+def test_departure_gradient_lone_origin_closed_form():
+    """One origin at constant rate r feeding a long link with a midpoint
+    detector.  Departures are spaced u/r apart, far closer than the sigmoid
+    width L/5 of SI-D, so the sum over agents becomes the continuum integral
+    dC(T)/dr = int s*sigma'(s(x - o)) (T - x/u) dx over the occupied stretch,
+    which is T - o/u when the stretch covers the whole sigmoid."""
+    from scipy.integrate import quad
+    length, u, r, T = 2000.0, 10.0, 0.5, 200
+    o_ = 1000.0
+    w = W.line(n_links=1, length=length, speed=u, n_agents=400, steps=T, capacity=10.0)
+    w.net.detector_pos = np.float32([o_])
+    w.dem.ready_time = None
+    w.dem.rates = np.full((1, 1), r, np.float32)
+    w.dem.rate_bin_s = float(T)
+    w.cfg.count_bin_steps = T
+    o = Oracle(w, variant="f64", log=True)
+    o.run(T)
+    st = o.state()
+    xs = st["pos"][st["status"] == ST_ON]
+    g = o.backward(gQ=np.ones((1, 1)))["rates"][0, 0]
+    sc = 5.0 / length
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    f = lambda x: sc * sig(sc * (x - o_)) * (1 - sig(sc * (x - o_))) * (T - x / u)
+    expect, _ = quad(f, xs.min(), xs.max())
+    assert g == pytest.approx(expect, rel=0.03)
+    # and the full-coverage limit of the same integral is T - o/u
+    full, _ = quad(f, -1e5, 1e5, limit=200)
+    assert full == pytest.approx(T - o_ / u, rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+def test_empty_and_never_released():
+    w = W.line(n_links=2, n_agents=5, ready=np.full(5, 1e9), steps=50)
+    o = Oracle(w)
+    o.run()
+    c = o.counters()
+    assert c["released"] == 0 and c["departed"] == 0
+    cnt, ttt = o.counts()
+    assert ttt == 0.0 and np.all(cnt == 0)
+
+
+def test_dead_end_without_uturn_is_stuck():
+    """A head whose node has no admissible out-link cannot move: it is
+    counted as stuck and blocks its link (connectivity mask, SI-B)."""
+    w = W.line(n_links=2, n_agents=1, steps=80)
+    # destination = node 0: only reachable by turning back, which is forbidden
+    w.net.tail = np.int32([0, 1, 2, 1])
+    w.net.head = np.int32([1, 2, 1, 0])
+    for k in ("lanes",):
+        setattr(w.net, k, np.ones(4, np.int32))
+    for k in ("length", "free_speed", "jam_density", "capacity", "beta", "alpha", "cost"):
+        v = getattr(w.net, k)
+        setattr(w.net, k, np.float32(list(v) + list(v)))
+    w.cfg.allow_uturn = 0
+    w.dem.agent_dest = np.int32([0])
+    o = Oracle(w)
+    o.place([0], [1], [0.0])       # on link 1 (1 -> 2), must turn back at node 2
+    o.run(80)
+    c = o.counters()
+    assert c["stuck"] > 0
+    assert o.state()["link"][0] == 1
