@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the differentiable agent-based traffic step on one MI355X.
+
+One benchmark step = one pass of the whole hot path over the synthetic
+1M-agent metro workload (12k nodes, ~35k links, 1,800 simulated steps of
+1 s): departures, per-link ordering and car-following, route choice, merge
+and FIFO transfer, detector counts, a checkpoint every 60 steps, then the
+reverse-mode adjoint with checkpointed replay.  `value` is vehicle-steps per
+second of that forward+adjoint pass (vehicle-steps = sum over simulated
+steps of agents on the network; the replay is not counted again).  The
+forward-only rate is reported beside it.
+
+Inputs are generated and uploaded before the timed region.  The oracle (a
+plain single-threaded C implementation) is timed on a bounded sample of the
+same workload as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def byte_model(kind: str, S: int, L: int, Nn: int, O: int, T: int, vs: int, moves: int, launches: int) -> float:
+    """Algorithmic (compulsory) bytes per launch of each kernel kind, from the
+    structure-of-arrays layout; each array counted once per launch.
+      link: per segment 72 B (ring counters, link constants, bucket r/w,
+            entry slots, head count), per agent on the network 8 B (position
+            read + write), per head 140 B (agent, destination, candidate links
+            with shortest-time entries, merge key, head record); in the
+            recorded replay also 8 B per agent and 8 B per segment of tape.
+      node: per node 24 B (CSR offsets), per link 64 B (in-link head count,
+            bucket, outflow, ring head; out-link ring tail and entry slots),
+            per head candidate 16 B, per mover 12 B, per origin 40 B.
+      reverse: per segment 40 B, per agent 24 B (tape position and agent id,
+            adjoint read + write, departure step).
+    `vs` = vehicle-steps of the forward, `moves` = transfers + exits + departures."""
+    if kind == "link":
+        per_step = 72.0 * S * L
+        total = 2 * T * per_step + 2 * 8.0 * vs + 2 * 140.0 * moves + 8.0 * vs + 8.0 * S * L * T
+    elif kind == "node":
+        total = 2 * T * (24.0 * S * Nn + 64.0 * S * L + 40.0 * S * O) + 2 * (16.0 + 12.0) * moves
+    elif kind == "reverse":
+        total = T * 40.0 * S * L + 24.0 * vs
+    else:
+        raise ValueError(kind)
+    return total / max(launches, 1)
+
+
+def make_workload(name: str, sim_steps=None):
+    from paper_2603_25068_amd import workloads as W
+    if name == "metro":
+        w = W.metro()
+    elif name == "grid":
+        w = W.grid_rates()
+    elif name == "small":
+        w = W.random_small(3, nx=6, ny=6, n_agents=3000, rates=True, steps=600)
+    else:
+        raise ValueError(name)
+    if sim_steps:
+        w.cfg.steps = int(sim_steps)
+    return w
+
+
+def cpu_baseline(w, n_steps: int, budget_s: float):
+    """The oracle as it stands on the first n_steps of the workload: logged
+    forward then the reverse sweep, single thread."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(w, log=True, steps=n_steps)
+    vs = 0
+    t0 = time.perf_counter()
+    done = 0
+    for k in range(n_steps):
+        o.step()
+        vs += o.counters()["on_net"]
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    cnt, _ = o.counts()
+    o.backward(gQ=np.ones(cnt.shape) if cnt.size else None, gT=1.0)
+    el = time.perf_counter() - t0
+    return {"value": vs / el, "unit": "vehicle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {w.cfg.steps} steps of {w.name}, forward with decision log + "
+                      f"reverse sweep, single thread, {vs} vehicle-steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed forward+adjoint passes")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="metro", choices=["metro", "grid", "small"])
+    ap.add_argument("--sim-steps", type=int, default=None, help="override simulated steps per pass")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the simulator runs every scenario on a single device; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2603_25068_amd.sim import Simulator
+
+    t_gen = time.perf_counter()
+    w = make_workload(args.workload, args.sim_steps)
+    T = w.cfg.steps
+    gen_s = time.perf_counter() - t_gen
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sim = Simulator(w, record=True, max_steps=T)
+    fwd = Simulator(w, record=False)
+    S, L, Nn, O = 1, w.net.n_links, w.net.n_nodes, w.net.n_origins
+    nb = sim.n_count_bins
+    gQ = torch.ones((S, w.net.n_detectors, nb), dtype=torch.float32, device=dev)
+    gT = torch.ones(S, dtype=torch.float64, device=dev)
+
+    def fwd_adj(s):
+        s.reset()
+        s.step(T)
+        s.backward_device(gQ=gQ, gT=gT)
+
+    def fwd_only(s):
+        s.reset()
+        s.step(T)
+
+    for _ in range(args.warmup):
+        fwd_adj(sim)
+        fwd_only(fwd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd_adj(sim)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    vs = int(sim.vehicle_steps()[0])
+    st = sim.state()["counters"][0]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd_only(fwd)
+    torch.cuda.synchronize()
+    el_f = time.perf_counter() - t1
+    vs_f = int(fwd.vehicle_steps()[0])
+    assert vs_f == vs
+
+    ms_per_step = 1000.0 * el / args.steps
+    value = vs * args.steps / el
+    fwd_value = vs_f * args.steps / el_f
+
+    # per-kernel device time with HIP events on the library's stream (one extra pass)
+    sim.set_timing(True)
+    sim.timing(reset=True)
+    fwd_adj(sim)
+    tm = sim.timing(reset=True)
+    sim.set_timing(False)
+    moves = st["transfers"] + st["exited"] + st["departed"]
+    kinds = {k: v for k, v in tm.items() if k in ("link", "node", "reverse") and v[1] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms_tot, launches = kinds[dom]
+    avg_ms = ms_tot / launches
+    bytes_launch = byte_model(dom, S, L, Nn, O, T, vs, moves, launches)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None, "kernel": f"k_{dom}",
+                "avg_launch_us": round(1000.0 * avg_ms, 3), "alg_bytes_per_launch": int(bytes_launch),
+                "kernel_ms": {k: [round(v[0], 3), v[1]] for k, v in tm.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(make_workload(args.workload, args.sim_steps), args.cpu_steps, args.cpu_budget_s)
+
+    line = {
+        "metric": "vehicle-steps/s fwd & fwd+adjoint at 1M agents; nowcast p50/p99 latency",
+        "value": round(value, 1), "unit": "vehicle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "agents": w.dem.n_agents, "links": L, "nodes": Nn, "origins": O,
+                   "sim_steps": T, "ckpt_every": w.cfg.ckpt_every, "pass": "forward+adjoint",
+                   "vehicle_steps_per_pass": vs, "forward_only_vehicle_steps_per_s": round(fwd_value, 1),
+                   "forward_only_ms": round(1000.0 * el_f / args.steps, 3),
+                   "counters": st, "generate_s": round(gen_s, 2)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * sim.h - C-ABI of the MI355X differentiable agent-based traffic simulator.
+ *
+ * One step phi = g(f(x)) of the paper (Results, "Differentiable agent-based
+ * traffic simulation"): departures from origin queues, Newell car-following
+ * on every link with the trajectory-grafted link cap (Methods eq.
+ * newell_model; SI-A), Gumbel-softmax link choice with straight-through
+ * estimator, merge choice and FIFO transfer with trajectory grafting (SI-B,
+ * SI-C), and differentiable midpoint counting (SI-D); plus its reverse-mode
+ * adjoint with checkpointed replay (Methods, "Optimization").
+ *
+ * Conventions for every entry point:
+ *  - return value: SIM_OK (0) or a negative SIM_E* code; no C++ exception
+ *    crosses this boundary.  sim_last_error() then holds a message.
+ *  - inputs are copied (host or device memory as stated); the caller keeps
+ *    ownership of everything it passes in.
+ *  - outputs go into caller buffers; `on_device` = 1 means the pointer is
+ *    device memory on the handle's device (e.g. a torch tensor's data_ptr),
+ *    written in order on the handle's stream; 0 means host memory, and the
+ *    call synchronises the stream before returning.
+ *  - a handle is not thread-safe; calls on one handle are serialised by the
+ *    caller.  All device work of a handle is ordered on its stream.
+ *  - scenario batching: S scenarios share the network and agent pool; each
+ *    has its own parameters (scenario-major [S x n]) and Philox key.
+ */
+#ifndef SIM_H
+#define SIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,        /* argument out of range or inconsistent */
+    SIM_ENOMEM = -2,        /* device or host allocation failed (nothing leaked) */
+    SIM_EDEVICE = -3,       /* a HIP call failed */
+    SIM_ESTATE = -4,        /* call not valid in the current state */
+    SIM_EUNSUPPORTED = -5   /* valid input the kernels do not handle */
+};
+
+/* Parameter groups (sim_set_params / sim_backward).  Per link: [S x n_links];
+ * rates: [S x n_origins x n_rate_bins]. */
+enum sim_param {
+    SIM_P_U = 0,         /* free-flow speed u (m/s), Methods eq. newell_model */
+    SIM_P_KAPPA = 1,     /* jam density kappa per lane (veh/m), same */
+    SIM_P_BETA = 2,      /* route-choice weight beta, SI-B link utility */
+    SIM_P_ALPHA = 3,     /* merge priority alpha, SI-B merge choice */
+    SIM_P_COST = 4,      /* link cost c, SI-B link utility */
+    SIM_P_RATES = 5,     /* departure rate per (origin, time bin), veh/s */
+    SIM_P_CAP_MULT = 6,  /* outflow capacity multiplier per link */
+    SIM_P_COUNT = 7
+};
+
+/* Counters per scenario (sim_get_state): */
+enum {
+    SIM_C_RELEASED = 0, SIM_C_DEPARTED = 1, SIM_C_ON_NET = 2, SIM_C_EXITED = 3,
+    SIM_C_TRANSFERS = 4, SIM_C_TIES = 5, SIM_C_STUCK = 6, SIM_C_ORDER_VIOL = 7,
+    SIM_C_COUNT = 8
+};
+
+/* Agent status codes (sim_get_state). */
+enum { SIM_WAIT = 0, SIM_QUEUED = 1, SIM_ON = 2, SIM_EXITED = 3 };
+
+/* Road network.  Host pointers; copied by sim_create.
+ * tail/head: node ids in [0, n_nodes); lanes in [1, 8]; length, free_speed,
+ * jam_density > 0; capacity >= 0 (veh/s/lane); beta/alpha/cost may be NULL
+ * (defaults 0, 1, 1), cost > 0.  Origins are nodes with a FIFO departure
+ * queue (the paper's virtual inflow links).  Detectors count crossings of
+ * position detector_pos (0 < pos <= length - 0.01) on detector_link (SI-D). */
+typedef struct {
+    int32_t n_nodes, n_links;
+    const int32_t *tail, *head, *lanes;
+    const float *length, *free_speed, *jam_density, *capacity;
+    const float *beta, *alpha, *cost;
+    int32_t n_origins;
+    const int32_t *origin_node;
+    int32_t n_detectors;
+    const int32_t *detector_link;
+    const float *detector_pos;
+} sim_network;
+
+/* Agent pool and demand.  Host pointers; copied by sim_create.
+ * agent_origin: index into origin_node; agent_dest: node id, reachable
+ * from the origin.  Either ready_time (fixed departure times, seconds) or
+ * rates [n_origins x n_rate_bins] (departure-rate mode; rate_bin_s must be a
+ * whole number of steps).  In rate mode agents of an origin are released in
+ * agent-index order when the integrated rate crosses their queue index + 1. */
+typedef struct {
+    int32_t n_agents;
+    const int32_t *agent_origin, *agent_dest;
+    const float *ready_time;
+    int32_t n_rate_bins;
+    double rate_bin_s;
+    const float *rates;
+} sim_demand;
+
+typedef struct {
+    double dt;                /* step length (s); the paper ties dt = tau * platoon, tau = 1 */
+    int32_t platoon;          /* platoon size dn (vehicles per agent) */
+    double gumbel_tau;        /* Gumbel-softmax temperature (gradient only) */
+    double dest_logit_coef;   /* theta: utility -= theta * (free-flow time to destination) */
+    double big_m;             /* M of SI-A/SI-B (enters straight-through gradients only) */
+    uint64_t seed;            /* Philox key of scenario 0 */
+    const uint64_t *scenario_seed; /* NULL -> scenario s uses seed + s */
+    int32_t n_scenarios;      /* S >= 1 */
+    int32_t ckpt_every;       /* checkpoint interval of the recorded rollout (steps) */
+    int32_t count_bin_steps;  /* detector sampling interval (steps) */
+    int32_t n_count_bins;     /* number of samples kept per detector */
+    int32_t max_steps;        /* longest recorded rollout (sizes the checkpoints) */
+    int32_t allow_uturn;      /* 1: a head may take the reverse of its link */
+    int32_t record_for_backward; /* 1: sim_rollout keeps checkpoints for sim_backward */
+    size_t mem_budget_bytes;  /* 0 = no limit; sim_create fails with SIM_ENOMEM beyond it */
+} sim_config;
+
+typedef struct sim_t sim_t;
+
+/* Validate, copy the inputs, compute shortest free-flow times to every
+ * destination (route-choice term), allocate device state on `hip_device`.
+ * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all
+ * later device work.  On error *out is NULL and nothing is leaked. */
+int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *cfg,
+               int hip_device, void *hip_stream, sim_t **out);
+
+/* Free everything the handle owns.  NULL is accepted. */
+int sim_destroy(sim_t *h);
+
+/* Message for the last failing call on this handle (or the last failing
+ * sim_create if h is NULL).  Valid until the next call on the handle. */
+const char *sim_last_error(const sim_t *h);
+
+/* Set one parameter group for all scenarios: values [S x n] scenario-major,
+ * n = n_links (per-link groups) or n_origins*n_rate_bins (rates).  Takes
+ * effect from the next step; SIM_P_KAPPA must keep dn/kappa >= the jam
+ * spacing the link rings were sized for (SIM_EINVAL otherwise). */
+int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_device);
+
+/* Back to t = 0: empty network, all agents waiting, counters, buckets and
+ * observables cleared.  Parameters are kept. */
+int sim_reset(sim_t *h);
+
+/* At t = 0 only: put agents on links at given positions (every scenario),
+ * in the given order per link (which fixes their entry sequence), and drop
+ * them from their origin queues.  Host arrays of length n. */
+int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, const float *pos);
+
+/* Advance one step / T steps.  With record_for_backward, sim_rollout from
+ * t = 0 stores a checkpoint every ckpt_every steps. */
+int sim_step(sim_t *h);
+int sim_rollout(sim_t *h, int32_t T);
+
+/* Five-minute style counts: counts [S x n_detectors x n_count_bins] (float,
+ * vehicles crossing each detector in each sampling interval; SI-D value
+ * part) and total travel time ttt [S] (double, seconds agents spent queued
+ * or on the network). */
+int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device);
+
+/* Reverse-mode adjoint of the recorded rollout (record_for_backward, rollout
+ * from t = 0): the exact derivative of the step with every discrete decision
+ * held fixed and every stop_gradient a constant, i.e. the gradient of the
+ * paper's straight-through / trajectory-grafting construction (SI-A..SI-D).
+ * Cotangents (each may be NULL): dL_dcounts [S x det x bins] float,
+ * dL_dttt [S] double, dL_dpos [S x n_agents] float (final positions of
+ * agents on the network).  grads[k] (for each bit k set in param_mask,
+ * SIM_P_U, SIM_P_KAPPA, SIM_P_RATES supported) receives dL/d(group k),
+ * overwritten, float, same layout as sim_set_params.  Other groups:
+ * SIM_EUNSUPPORTED. */
+int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const float *dL_dpos,
+                 uint32_t param_mask, float *const *grads, int on_device);
+
+/* Agent state, host arrays [S x n_agents] (any may be NULL): status
+ * (SIM_WAIT..SIM_EXITED), link (-1 when not on a link), pos, seq (entry
+ * sequence on its link); counters [S x SIM_C_COUNT]. */
+int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t *seq,
+                  int64_t *counters);
+
+/* Vehicle-steps per scenario [S] (host): the sum over completed steps of
+ * the number of agents on the network after the step. */
+int sim_get_stats(sim_t *h, int64_t *vehicle_steps);
+
+/* Per (scenario, link) state, host arrays [S x n_links] (any may be NULL):
+ * token bucket B, cumulative outflow E, next entry sequence number. */
+int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq);
+
+/* Shortest free-flow time (s) from every node to every destination node,
+ * host [n_dest x n_nodes] in increasing destination-node order; *n_dest
+ * receives the count.  Pass out = NULL to query n_dest only. */
+int sim_get_dist(sim_t *h, double *out, int32_t *n_dest);
+
+/* Current step index. */
+int sim_time(const sim_t *h, int32_t *t);
+
+/* Philox4x32-10 (Salmon et al., SC'11) evaluated on the device: n counters
+ * ctr [n x 4] with keys key [n x 2], host arrays; out [n x 4] host. */
+int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
+
+/* Segmented sort of n keys (segment id, position, sequence) into segment
+ * order, position descending, sequence ascending; writes the permutation
+ * perm [n] and segment offsets seg_off [n_segments + 1].  Device pointers,
+ * ordered on the handle's stream.  Used to build the per-link layout from an
+ * arbitrary agent list; exposed for testing. */
+int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
+                const int32_t *seq, int32_t *perm, int32_t *seg_off);
+
+/* Device time (ms) and launch count of each kernel kind accumulated since
+ * the last call with reset = 1, measured with HIP events on the handle's
+ * stream when timing is enabled (sim_set_timing). kinds: 0 link phase,
+ * 1 node phase, 2 reverse, 3 tape/checkpoint copies. */
+int sim_set_timing(sim_t *h, int enable);
+int sim_get_timing(sim_t *h, double *ms, int64_t *launches, int n_kinds, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIM_H */

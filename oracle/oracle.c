@@ -276,25 +276,27 @@ static void build_queues(orc_t *o)
     int32_t O = o->in.n_origins, N = o->in.n_agents;
     free(o->q_off); free(o->q_list);
     o->q_off = calloc((size_t)O + 1, sizeof(int32_t));
-    int32_t *cnt = calloc((size_t)O, sizeof(int32_t));
+    int32_t *cnt = calloc((size_t)O + 1, sizeof(int32_t));
     for (int32_t i = 0; i < N; ++i) if (o->status[i] == ST_WAIT) cnt[o->agent_origin[i]]++;
     for (int32_t k = 0; k < O; ++k) o->q_off[k + 1] = o->q_off[k] + cnt[k];
     o->q_list = malloc(sizeof(int32_t) * (size_t)(o->q_off[O] + 1));
     /* queue order: fixed-time mode by (release step, agent id); rate mode by agent id */
     int64_t *key = malloc(sizeof(int64_t) * 2 * (size_t)(o->q_off[O] + 1));
     memset(cnt, 0, sizeof(int32_t) * (size_t)O);
+    for (int32_t i = 0; i < N; ++i) {
+        if (o->status[i] != ST_WAIT) continue;
+        int32_t k = o->agent_origin[i];
+        int64_t at = (int64_t)o->q_off[k] + cnt[k]++;
+        key[2 * at] = o->ready ? o->rstep[i] : 0;
+        key[2 * at + 1] = i;
+    }
     for (int32_t k = 0; k < O; ++k) {
-        int32_t n = 0;
-        for (int32_t i = 0; i < N; ++i) {
-            if (o->status[i] != ST_WAIT || o->agent_origin[i] != k) continue;
-            key[2 * n] = o->ready ? o->rstep[i] : 0;
-            key[2 * n + 1] = i;
-            ++n;
-        }
-        qsort(key, (size_t)n, 2 * sizeof(int64_t), cmp_i64pair);
+        int32_t n = o->q_off[k + 1] - o->q_off[k];
+        int64_t *kk = key + 2 * (int64_t)o->q_off[k];
+        qsort(kk, (size_t)n, 2 * sizeof(int64_t), cmp_i64pair);
         for (int32_t a = 0; a < n; ++a) {
-            o->q_list[o->q_off[k] + a] = (int32_t)key[2 * a + 1];
-            o->qidx[key[2 * a + 1]] = a;
+            o->q_list[o->q_off[k] + a] = (int32_t)kk[2 * a + 1];
+            o->qidx[kk[2 * a + 1]] = a;
         }
         o->rel_ptr[k] = 0;
         o->dep_ptr[k] = 0;

@@ -1,0 +1,99 @@
+// Internal layout of the simulator's device state (library-private).
+//
+// Layout (scenario s, link j, node v, agent i; S scenarios, L links, N agents):
+//  - every (s, j) "segment" seg = s*L + j owns a ring of cap[j] slots at
+//    ring_base[j] + s*ring_total holding (agent id, position) of the agents on
+//    the link in entry order; rhead/rtail are monotone counters, the agent in
+//    counter q sits in slot q % cap[j] and its entry sequence number is q.
+//    Entry order equals the order by (position desc, sequence asc): the
+//    update rule is monotone in the leader's and the agent's own position,
+//    so it never reorders a link (checked every step).
+//  - per-agent arrays are [S*N]; per-origin [S*O]; per-segment [S*L].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sim {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxLanes = 8;     // lanes per link accepted by sim_create
+constexpr int kMaxDetPerLink = 4;
+enum : int32_t { CH_STUCK = -1, CH_EXIT = -2, CH_NONE = -3 };
+enum : uint8_t { AG_WAIT = 0, AG_QUEUED = 1, AG_ON = 2, AG_EXITED = 3 };
+enum { CTR_RELEASED = 0, CTR_DEPARTED, CTR_ON_NET, CTR_EXITED, CTR_TRANSFERS, CTR_TIES, CTR_STUCK,
+       CTR_ORDER_VIOL, CTR_N };
+enum { ERR_RING_OVERFLOW = 0, ERR_CAND_OVERFLOW = 1, ERR_N = 4 };
+
+struct Dev {
+    // sizes
+    int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
+    int64_t ring_total;
+    double dt, theta, rate_bin_s;
+
+    // network (shared by scenarios)
+    const int32_t *tail, *head, *lanes, *cap, *ring_base;
+    const float *length, *thr;
+    const int32_t *out_off, *out_lnk, *in_off, *in_lnk, *org_off, *org_list;
+    const int32_t *det_off, *det_list;
+    const float *det_pos;
+    const double *tff;      // route-choice free-flow time per link
+    const double *dist;     // [n_dest x Nn] shortest free-flow time to destination
+    const int32_t *agent_didx, *agent_dest, *agent_origin;
+    const int32_t *q_off, *q_list;   // origin queues (agent ids in release order)
+    const int64_t *q_rstep;          // fixed mode: release step of each queue entry
+    const uint64_t *seed;            // [S]
+
+    // parameters [S x L] / [S x O x B]
+    const float *u, *kappa, *alpha, *rates;
+    const float *vfree, *spacing;    // derived: u*dt, platoon/kappa
+    const double *util;              // beta / cost
+    const double *acc;               // cap_mult * capacity * lanes * dt
+
+    // state
+    float *ring_pos;
+    int32_t *ring_agent;
+    int32_t *rhead, *rtail;          // [S*L]
+    double *B;                       // token bucket [S*L]
+    int64_t *E;                      // cumulative outflow [S*L]
+    int32_t *slots, *nheads;         // [S*L]
+    int32_t *head_agent, *head_choice;  // [S*L*maxl]
+    double *head_key;                // [S*L*maxl]
+    uint8_t *status;                 // [S*N]
+    double *tstar;                   // [S*N] release time (rate mode)
+    int32_t *rel_t, *dep_t, *exit_t; // [S*N]
+    double *Dacc;                    // [S*O] integrated departures
+    int32_t *rel_ptr, *dep_ptr;      // [S*O]
+    int64_t *ctr;                    // [S*CTR_N]
+    int32_t *cum;                    // [S*D*nb] cumulative detector counts
+    int32_t *err;                    // [ERR_N]
+
+    // tape (replay window) and adjoint
+    float *tape_pos;                 // [(W+1) * S * ring_total]
+    int32_t *tape_agent;             // same
+    int32_t *tape_head, *tape_tail;  // [(W+1) * S * L]
+    float *adj;                      // [S*N] adjoint of the agent's current position
+    float *depg;                     // [S*N] adjoint reaching a departure graft, times u of the first link
+    double *gu, *gk;                 // [S*L] accumulated parameter gradients
+    const float *gQ;                 // [S*D*nb] dL/dcounts (device copy)
+    const double *gT;                // [S]
+    const float *gx;                 // [S*N]
+};
+
+// kernel launchers (sim_kernels.hip)
+void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st);
+void launch_node(const Dev &d, int t, hipStream_t st);
+void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st);
+void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st);
+void launch_rate_grad(const Dev &d, float *g_rates, hipStream_t st);
+void launch_philox(int n, const uint32_t *ctr, const uint32_t *key, uint32_t *out, hipStream_t st);
+int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
+                   int32_t *perm, int32_t *seg_off, int32_t *scratch, hipStream_t st);
+void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
+                   const float *cost, double *util, double *acc, float *vfree, float *spacing,
+                   hipStream_t st);
+void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, hipStream_t st);
+void launch_counts(const Dev &d, float *out, hipStream_t st);
+void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st);
+
+}  // namespace sim

@@ -1,0 +1,1024 @@
+// Host runtime behind the C-ABI of include/sim.h: input validation, network
+// preprocessing (CSR adjacency, per-link rings, origin queues, shortest
+// free-flow times), device memory, the step loop, checkpoints and the
+// checkpointed replay that feeds the adjoint kernels.
+#include "sim.h"
+#include "sim_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <queue>
+#include <string>
+#include <thread>
+#include <vector>
+
+using sim::Dev;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipError {
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_)};             \
+    } while (0)
+
+struct InvalidArg {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &m) { throw InvalidArg{code, m}; }
+
+// checkpoint of everything the replay reads
+struct Ckpt {
+    float *ring_pos = nullptr;
+    int32_t *ring_agent = nullptr;
+    int32_t *rhead = nullptr, *rtail = nullptr;
+    double *B = nullptr;
+    int64_t *E = nullptr;
+    double *Dacc = nullptr;
+    int32_t *rel_ptr = nullptr, *dep_ptr = nullptr;
+    int64_t *ctr = nullptr;
+    uint8_t *status = nullptr;
+    int t = -1;
+};
+
+}  // namespace
+
+struct sim_t {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // copies of the inputs
+    int32_t S = 1, L = 0, Nn = 0, O = 0, N = 0, D = 0, nb = 0, cbs = 0, B = 0, maxl = 1;
+    bool fixed_mode = true;
+    double dt = 1.0, rate_bin_s = 0.0;
+    int32_t platoon = 1, ckpt_every = 60, max_steps = 0, record = 0;
+    std::vector<int32_t> tail, head, lanes, origin_node, det_link, agent_origin, agent_dest;
+    std::vector<float> length, free_speed, jam_density, capacity, beta, alpha, cost, det_pos, ready, rates;
+    std::vector<uint64_t> seeds;
+
+    // derived host structures
+    std::vector<int32_t> cap, ring_base, out_off, out_lnk, in_off, in_lnk, org_off, org_list, det_off, det_list;
+    std::vector<int32_t> dest_nodes, agent_didx;
+    std::vector<double> dist, tff;
+    std::vector<int32_t> q_off, q_list;  // full queues (as built at create)
+    std::vector<int64_t> q_rstep;
+    std::vector<float> min_spacing;      // jam spacing the rings were sized for
+    int64_t ring_total = 0;
+
+    Dev d{};
+    std::vector<void *> allocs;
+    // mutable parameter buffers
+    float *p_u = nullptr, *p_kappa = nullptr, *p_beta = nullptr, *p_alpha = nullptr, *p_cost = nullptr,
+          *p_rates = nullptr, *p_capm = nullptr, *capacity_dev = nullptr;
+    float *vfree = nullptr, *spacing = nullptr;
+    double *util = nullptr, *acc = nullptr;
+    // mutable queue buffers
+    int32_t *q_off_dev = nullptr, *q_list_dev = nullptr;
+    int64_t *q_rstep_dev = nullptr;
+    // adjoint buffers
+    float *gQ_dev = nullptr, *gx_dev = nullptr;
+    double *gT_dev = nullptr, *ttt_dev = nullptr;
+    float *counts_dev = nullptr, *grad_tmp = nullptr;
+    int64_t *vsteps_dev = nullptr;
+    int64_t *dalloc_scratch_i64(size_t n) {
+        if (!vsteps_dev) vsteps_dev = dalloc<int64_t>(n);
+        return vsteps_dev;
+    }
+
+    int t = 0;
+    std::vector<Ckpt> ckpts;  // [n_ckpt] + final
+    int W = 0;                // tape window (= ckpt_every)
+    bool rec_valid = false;
+
+    // timing
+    bool timing = false;
+    struct Ev { hipEvent_t a, b; int kind; };
+    std::vector<Ev> evs;
+    std::vector<hipEvent_t> ev_pool;
+    double ms_acc[4] = {0, 0, 0, 0};
+    int64_t n_acc[4] = {0, 0, 0, 0};
+
+    template <class T>
+    T *dalloc(size_t n) {
+        if (n == 0) n = 1;
+        void *p = nullptr;
+        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(SIM_ENOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+        }
+        allocs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    template <class T>
+    T *upload(const std::vector<T> &v) {
+        T *p = dalloc<T>(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+        return p;
+    }
+    ~sim_t() {
+        if (device >= 0) (void)hipSetDevice(device);
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (auto &e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+
+    hipEvent_t get_event() {
+        if (!ev_pool.empty()) { hipEvent_t e = ev_pool.back(); ev_pool.pop_back(); return e; }
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        return e;
+    }
+    void time_begin(int kind, hipEvent_t *a) {
+        (void)kind;
+        if (!timing) return;
+        *a = get_event();
+        HIPCHK(hipEventRecord(*a, stream));
+    }
+    void time_end(int kind, hipEvent_t a) {
+        if (!timing) return;
+        hipEvent_t b = get_event();
+        HIPCHK(hipEventRecord(b, stream));
+        evs.push_back({a, b, kind});
+    }
+    void resolve_timing() {
+        if (evs.empty()) return;
+        HIPCHK(hipEventSynchronize(evs.back().b));
+        for (auto &e : evs) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+            ms_acc[e.kind] += ms;
+            n_acc[e.kind] += 1;
+            ev_pool.push_back(e.a);
+            ev_pool.push_back(e.b);
+        }
+        evs.clear();
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// shortest free-flow time to each destination: Dijkstra on the reversed
+// graph, weights length / free speed in double, one destination per task.
+// ---------------------------------------------------------------------------
+void shortest_times(sim_t *h)
+{
+    const int Nn = h->Nn;
+    const int nd = (int)h->dest_nodes.size();
+    h->dist.assign((size_t)nd * Nn, std::numeric_limits<double>::infinity());
+    std::vector<double> w(h->L);
+    for (int m = 0; m < h->L; ++m) w[m] = (double)h->length[m] / (double)h->free_speed[m];
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        std::vector<char> done(Nn);
+        using QE = std::pair<double, int>;
+        for (;;) {
+            const int k = next.fetch_add(1);
+            if (k >= nd) break;
+            double *dist = h->dist.data() + (size_t)k * Nn;
+            std::fill(done.begin(), done.end(), 0);
+            std::priority_queue<QE, std::vector<QE>, std::greater<QE>> pq;
+            dist[h->dest_nodes[k]] = 0.0;
+            pq.push({0.0, h->dest_nodes[k]});
+            while (!pq.empty()) {
+                const int x = pq.top().second;
+                pq.pop();
+                if (done[x]) continue;
+                done[x] = 1;
+                for (int e = h->in_off[x]; e < h->in_off[x + 1]; ++e) {
+                    const int m = h->in_lnk[e];
+                    const double cand = w[m] + dist[x];
+                    const int y = h->tail[m];
+                    if (cand < dist[y]) { dist[y] = cand; pq.push({cand, y}); }
+                }
+            }
+        }
+    };
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i + 1 < nt && (int)i < nd; ++i) th.emplace_back(worker);
+    worker();
+    for (auto &x : th) x.join();
+}
+
+void build_csr(int n, const std::vector<int32_t> &key, std::vector<int32_t> &off, std::vector<int32_t> &lst)
+{
+    off.assign(n + 1, 0);
+    for (int32_t k : key) off[k + 1]++;
+    for (int i = 0; i < n; ++i) off[i + 1] += off[i];
+    lst.assign(key.size(), 0);
+    std::vector<int32_t> fill(n, 0);
+    for (size_t i = 0; i < key.size(); ++i) lst[off[key[i]] + fill[key[i]]++] = (int32_t)i;
+}
+
+// origin queues, excluding agents not waiting (placed agents)
+void build_queues(sim_t *h, const std::vector<uint8_t> *skip)
+{
+    const int O = h->O, N = h->N;
+    std::vector<int32_t> cnt(O, 0);
+    for (int i = 0; i < N; ++i)
+        if (!skip || !(*skip)[i]) cnt[h->agent_origin[i]]++;
+    h->q_off.assign(O + 1, 0);
+    for (int k = 0; k < O; ++k) h->q_off[k + 1] = h->q_off[k] + cnt[k];
+    h->q_list.assign(h->q_off[O], 0);
+    h->q_rstep.assign(h->q_off[O], 0);
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> per(O);
+    for (int i = 0; i < N; ++i) {
+        if (skip && (*skip)[i]) continue;
+        int64_t rs = 0;
+        if (h->fixed_mode) {
+            double r = std::floor((double)h->ready[i] / h->dt);
+            if (r < 0) r = 0;
+            if (r > 4e18) r = 4e18;
+            rs = (int64_t)r;
+        }
+        per[h->agent_origin[i]].push_back({rs, i});
+    }
+    for (int k = 0; k < O; ++k) {
+        std::sort(per[k].begin(), per[k].end());
+        for (size_t a = 0; a < per[k].size(); ++a) {
+            h->q_list[h->q_off[k] + a] = per[k][a].second;
+            h->q_rstep[h->q_off[k] + a] = per[k][a].first;
+        }
+    }
+}
+
+void zero_state(sim_t *h)
+{
+    Dev &d = h->d;
+    const hipStream_t st = h->stream;
+    const size_t SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
+    HIPCHK(hipMemsetAsync(d.rhead, 0, SL * 4, st));
+    HIPCHK(hipMemsetAsync(d.rtail, 0, SL * 4, st));
+    HIPCHK(hipMemsetAsync(d.B, 0, SL * 8, st));
+    HIPCHK(hipMemsetAsync(d.E, 0, SL * 8, st));
+    HIPCHK(hipMemsetAsync(d.slots, 0, SL * 4, st));
+    HIPCHK(hipMemsetAsync(d.nheads, 0, SL * 4, st));
+    HIPCHK(hipMemsetAsync(d.status, 0, SN, st));
+    HIPCHK(hipMemsetAsync(d.tstar, 0, SN * 8, st));
+    HIPCHK(hipMemsetAsync(d.rel_t, 0xff, SN * 4, st));
+    HIPCHK(hipMemsetAsync(d.dep_t, 0xff, SN * 4, st));
+    HIPCHK(hipMemsetAsync(d.exit_t, 0xff, SN * 4, st));
+    HIPCHK(hipMemsetAsync(d.Dacc, 0, SO * 8, st));
+    HIPCHK(hipMemsetAsync(d.rel_ptr, 0, SO * 4, st));
+    HIPCHK(hipMemsetAsync(d.dep_ptr, 0, SO * 4, st));
+    HIPCHK(hipMemsetAsync(d.ctr, 0, (size_t)h->S * sim::CTR_N * 8, st));
+    if (h->D * h->nb) HIPCHK(hipMemsetAsync(d.cum, 0, (size_t)h->S * h->D * h->nb * 4, st));
+    HIPCHK(hipMemsetAsync(d.err, 0, sim::ERR_N * 4, st));
+    h->t = 0;
+    h->rec_valid = h->record != 0;
+}
+
+void upload_queues(sim_t *h)
+{
+    // queue buffers are sized for the full pool at create; copy the current lists
+    HIPCHK(hipMemcpyAsync(h->q_off_dev, h->q_off.data(), h->q_off.size() * 4, hipMemcpyHostToDevice, h->stream));
+    if (!h->q_list.empty()) {
+        HIPCHK(hipMemcpyAsync(h->q_list_dev, h->q_list.data(), h->q_list.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->q_rstep_dev, h->q_rstep.data(), h->q_rstep.size() * 8, hipMemcpyHostToDevice, h->stream));
+    }
+}
+
+void derive(sim_t *h)
+{
+    sim::launch_derive(h->d, h->p_capm, h->capacity_dev, h->p_beta, h->p_cost, h->util, h->acc, h->vfree, h->spacing,
+                       h->stream);
+    HIPCHK(hipGetLastError());
+}
+
+void check_device_errors(sim_t *h)
+{
+    int32_t e[sim::ERR_N];
+    HIPCHK(hipMemcpyAsync(e, h->d.err, sizeof(e), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (e[sim::ERR_RING_OVERFLOW]) fail(SIM_ESTATE, "a link ring overflowed (agents closer than the jam spacing)");
+    if (e[sim::ERR_CAND_OVERFLOW]) fail(SIM_EUNSUPPORTED, "more than 64 merge candidates at a node");
+}
+
+// --- checkpoints ---
+void ckpt_alloc(sim_t *h, Ckpt &c)
+{
+    const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
+    c.ring_pos = h->dalloc<float>(SR);
+    c.ring_agent = h->dalloc<int32_t>(SR);
+    c.rhead = h->dalloc<int32_t>(SL);
+    c.rtail = h->dalloc<int32_t>(SL);
+    c.B = h->dalloc<double>(SL);
+    c.E = h->dalloc<int64_t>(SL);
+    c.Dacc = h->dalloc<double>(SO);
+    c.rel_ptr = h->dalloc<int32_t>(SO);
+    c.dep_ptr = h->dalloc<int32_t>(SO);
+    c.ctr = h->dalloc<int64_t>((size_t)h->S * sim::CTR_N);
+    c.status = h->dalloc<uint8_t>((size_t)h->S * h->N);
+}
+
+void ckpt_copy(sim_t *h, Ckpt &c, bool save)
+{
+    Dev &d = h->d;
+    const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
+    const hipStream_t st = h->stream;
+    auto cp = [&](void *ck, void *live, size_t bytes) {
+        if (save) HIPCHK(hipMemcpyAsync(ck, live, bytes, hipMemcpyDeviceToDevice, st));
+        else HIPCHK(hipMemcpyAsync(live, ck, bytes, hipMemcpyDeviceToDevice, st));
+    };
+    cp(c.ring_pos, d.ring_pos, SR * 4);
+    cp(c.ring_agent, d.ring_agent, SR * 4);
+    cp(c.rhead, d.rhead, SL * 4);
+    cp(c.rtail, d.rtail, SL * 4);
+    cp(c.B, d.B, SL * 8);
+    cp(c.E, d.E, SL * 8);
+    cp(c.Dacc, d.Dacc, SO * 8);
+    cp(c.rel_ptr, d.rel_ptr, SO * 4);
+    cp(c.dep_ptr, d.dep_ptr, SO * 4);
+    cp(c.ctr, d.ctr, (size_t)h->S * sim::CTR_N * 8);
+    cp(c.status, d.status, (size_t)h->S * h->N);
+}
+
+void do_step(sim_t *h, int tape_k)
+{
+    const int t = h->t;
+    int sb = -1;
+    if (h->cbs > 0 && (t + 1) % h->cbs == 0 && (t + 1) / h->cbs <= h->nb) sb = (t + 1) / h->cbs - 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    h->time_begin(0, &e0);
+    sim::launch_link(h->d, t, sb, tape_k, h->stream);
+    h->time_end(0, e0);
+    h->time_begin(1, &e1);
+    sim::launch_node(h->d, t, h->stream);
+    h->time_end(1, e1);
+    HIPCHK(hipGetLastError());
+    h->t = t + 1;
+}
+
+int record_error(sim_t *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+template <class F>
+int guarded(sim_t *h, F &&f)
+{
+    if (!h) return record_error(nullptr, SIM_EINVAL, "null handle");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        f();
+        return SIM_OK;
+    } catch (const InvalidArg &e) {
+        return record_error(h, e.code, e.msg);
+    } catch (const HipError &e) {
+        return record_error(h, SIM_EDEVICE, e.msg);
+    } catch (const std::bad_alloc &) {
+        return record_error(h, SIM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return record_error(h, SIM_EDEVICE, "unexpected failure");
+    }
+}
+
+void copy_out(sim_t *h, void *dst, const void *src_dev, size_t bytes, int on_device)
+{
+    if (bytes == 0) return;
+    HIPCHK(hipMemcpyAsync(dst, src_dev, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char *sim_last_error(const sim_t *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *cfg, int hip_device,
+               void *hip_stream, sim_t **out)
+{
+    if (!out) return record_error(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!net || !dem || !cfg) return record_error(nullptr, SIM_EINVAL, "null input struct");
+    sim_t *h = nullptr;
+    try {
+        h = new sim_t();
+        h->device = hip_device;
+        h->stream = (hipStream_t)hip_stream;
+        int ndev = 0;
+        HIPCHK(hipGetDeviceCount(&ndev));
+        if (hip_device < 0 || hip_device >= ndev) fail(SIM_EINVAL, "bad device index");
+        HIPCHK(hipSetDevice(hip_device));
+
+        // ---------------- validate and copy ----------------
+        const int L = net->n_links, Nn = net->n_nodes;
+        if (L <= 0 || Nn <= 0) fail(SIM_EINVAL, "network needs nodes and links");
+        if (!net->tail || !net->head || !net->lanes || !net->length || !net->free_speed || !net->jam_density ||
+            !net->capacity)
+            fail(SIM_EINVAL, "missing link array");
+        h->L = L; h->Nn = Nn;
+        h->tail.assign(net->tail, net->tail + L);
+        h->head.assign(net->head, net->head + L);
+        h->lanes.assign(net->lanes, net->lanes + L);
+        h->length.assign(net->length, net->length + L);
+        h->free_speed.assign(net->free_speed, net->free_speed + L);
+        h->jam_density.assign(net->jam_density, net->jam_density + L);
+        h->capacity.assign(net->capacity, net->capacity + L);
+        h->beta = net->beta ? std::vector<float>(net->beta, net->beta + L) : std::vector<float>(L, 0.f);
+        h->alpha = net->alpha ? std::vector<float>(net->alpha, net->alpha + L) : std::vector<float>(L, 1.f);
+        h->cost = net->cost ? std::vector<float>(net->cost, net->cost + L) : std::vector<float>(L, 1.f);
+        int maxl = 1;
+        for (int j = 0; j < L; ++j) {
+            if (h->tail[j] < 0 || h->tail[j] >= Nn || h->head[j] < 0 || h->head[j] >= Nn)
+                fail(SIM_EINVAL, "link " + std::to_string(j) + ": node index out of range");
+            if (h->lanes[j] < 1 || h->lanes[j] > sim::kMaxLanes) fail(SIM_EINVAL, "lanes must be in [1, 8]");
+            if (!(h->length[j] > 0.02f) || !(h->free_speed[j] > 0.f) || !(h->jam_density[j] > 0.f) ||
+                !(h->capacity[j] >= 0.f) || !(h->cost[j] > 0.f) || !std::isfinite(h->length[j]) ||
+                !std::isfinite(h->free_speed[j]) || !std::isfinite(h->capacity[j]))
+                fail(SIM_EINVAL, "link " + std::to_string(j) + ": non-positive or non-finite length/speed/density/cost");
+            maxl = std::max(maxl, h->lanes[j]);
+        }
+        h->maxl = maxl;
+        h->O = net->n_origins;
+        if (h->O < 0 || (h->O > 0 && !net->origin_node)) fail(SIM_EINVAL, "bad origins");
+        h->origin_node.assign(net->origin_node, net->origin_node + h->O);
+        for (int k = 0; k < h->O; ++k)
+            if (h->origin_node[k] < 0 || h->origin_node[k] >= Nn) fail(SIM_EINVAL, "origin node out of range");
+        h->D = net->n_detectors;
+        if (h->D < 0 || (h->D > 0 && (!net->detector_link || !net->detector_pos))) fail(SIM_EINVAL, "bad detectors");
+        h->det_link.assign(net->detector_link, net->detector_link + h->D);
+        h->det_pos.assign(net->detector_pos, net->detector_pos + h->D);
+        for (int k = 0; k < h->D; ++k) {
+            const int j = h->det_link[k];
+            if (j < 0 || j >= L) fail(SIM_EINVAL, "detector link out of range");
+            if (!(h->det_pos[k] > 0.f) || !(h->det_pos[k] <= h->length[j] - 0.01f))
+                fail(SIM_EINVAL, "detector position must lie in (0, length - 0.01]");
+        }
+        h->N = dem->n_agents;
+        if (h->N < 0 || (h->N > 0 && (!dem->agent_origin || !dem->agent_dest))) fail(SIM_EINVAL, "bad agents");
+        h->agent_origin.assign(dem->agent_origin, dem->agent_origin + h->N);
+        h->agent_dest.assign(dem->agent_dest, dem->agent_dest + h->N);
+        h->fixed_mode = dem->ready_time != nullptr;
+        if (h->fixed_mode) h->ready.assign(dem->ready_time, dem->ready_time + h->N);
+        else {
+            h->B = dem->n_rate_bins;
+            h->rate_bin_s = dem->rate_bin_s;
+            if (h->B <= 0 || !dem->rates || !(dem->rate_bin_s > 0)) fail(SIM_EINVAL, "rate mode needs rates and bins");
+            h->rates.assign(dem->rates, dem->rates + (size_t)h->O * h->B);
+            for (float r : h->rates)
+                if (!(r >= 0.f) || !std::isfinite(r)) fail(SIM_EINVAL, "rates must be finite and >= 0");
+        }
+        for (int i = 0; i < h->N; ++i) {
+            if (h->agent_origin[i] < 0 || h->agent_origin[i] >= h->O) fail(SIM_EINVAL, "agent origin out of range");
+            if (h->agent_dest[i] < 0 || h->agent_dest[i] >= Nn) fail(SIM_EINVAL, "agent destination out of range");
+            if (h->agent_dest[i] == h->origin_node[h->agent_origin[i]])
+                fail(SIM_EINVAL, "agent destination equals its origin node");
+        }
+        h->dt = cfg->dt;
+        h->platoon = cfg->platoon;
+        if (!(cfg->dt > 0) || cfg->platoon < 1) fail(SIM_EINVAL, "dt > 0 and platoon >= 1 required");
+        if (!h->fixed_mode) {
+            const double k = h->rate_bin_s / h->dt;
+            if (std::fabs(k - std::round(k)) > 1e-9) fail(SIM_EINVAL, "rate bins must be a whole number of steps");
+        }
+        h->S = cfg->n_scenarios;
+        if (h->S < 1) fail(SIM_EINVAL, "n_scenarios >= 1");
+        h->cbs = cfg->count_bin_steps;
+        h->nb = cfg->n_count_bins;
+        if (h->nb < 0 || (h->nb > 0 && h->cbs < 1)) fail(SIM_EINVAL, "count bins need count_bin_steps >= 1");
+        h->ckpt_every = cfg->ckpt_every > 0 ? cfg->ckpt_every : 60;
+        h->max_steps = cfg->max_steps;
+        h->record = cfg->record_for_backward;
+        if (h->record && h->max_steps <= 0) fail(SIM_EINVAL, "record_for_backward needs max_steps > 0");
+        h->seeds.resize(h->S);
+        for (int s = 0; s < h->S; ++s) h->seeds[s] = cfg->scenario_seed ? cfg->scenario_seed[s] : cfg->seed + (uint64_t)s;
+
+        // ---------------- graph ----------------
+        build_csr(Nn, h->tail, h->out_off, h->out_lnk);
+        build_csr(Nn, h->head, h->in_off, h->in_lnk);
+        build_csr(Nn, h->origin_node, h->org_off, h->org_list);
+        build_csr(L, h->det_link, h->det_off, h->det_list);
+        for (int v = 0; v < Nn; ++v) {
+            const int nc = (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]);
+            if (nc > sim::kWave) fail(SIM_EUNSUPPORTED, "node " + std::to_string(v) + ": more than 64 merge candidates");
+            if (h->out_off[v + 1] - h->out_off[v] > sim::kWave) fail(SIM_EUNSUPPORTED, "node out-degree above 64");
+        }
+        for (int j = 0; j < L; ++j)
+            if (h->det_off[j + 1] - h->det_off[j] > sim::kMaxDetPerLink) fail(SIM_EUNSUPPORTED, "more than 4 detectors on a link");
+        // rings: a link holds at most lanes * (floor(L / spacing) + 1) agents; two extra rows of slack
+        h->cap.resize(L);
+        h->ring_base.resize(L);
+        h->min_spacing.resize(L);
+        int64_t tot = 0;
+        for (int j = 0; j < L; ++j) {
+            const float sp = (float)h->platoon / h->jam_density[j];
+            h->min_spacing[j] = sp;
+            const double rows = std::floor((double)h->length[j] / (double)sp) + 3.0;
+            const double c = rows * h->lanes[j];
+            if (c > 1e8) fail(SIM_EUNSUPPORTED, "link too long for its jam spacing");
+            h->cap[j] = (int32_t)c;
+            h->ring_base[j] = (int32_t)tot;
+            tot += h->cap[j];
+            if (tot > (int64_t)1 << 30) fail(SIM_EUNSUPPORTED, "ring storage above 2^30 slots");
+        }
+        h->ring_total = tot;
+        // destinations, numbered in node order
+        std::vector<int32_t> didx(Nn, -1);
+        for (int i = 0; i < h->N; ++i) didx[h->agent_dest[i]] = 0;
+        for (int v = 0; v < Nn; ++v)
+            if (didx[v] == 0) { didx[v] = (int32_t)h->dest_nodes.size(); h->dest_nodes.push_back(v); }
+        h->agent_didx.resize(h->N);
+        for (int i = 0; i < h->N; ++i) h->agent_didx[i] = didx[h->agent_dest[i]];
+        shortest_times(h);
+        for (int i = 0; i < h->N; ++i) {
+            const double dd = h->dist[(size_t)h->agent_didx[i] * Nn + h->origin_node[h->agent_origin[i]]];
+            if (!(dd < std::numeric_limits<double>::infinity()))
+                fail(SIM_EINVAL, "agent " + std::to_string(i) + ": destination unreachable from its origin");
+        }
+        h->tff.resize(L);
+        for (int m = 0; m < L; ++m) h->tff[m] = (double)h->length[m] / (double)h->free_speed[m];
+        build_queues(h, nullptr);
+
+        // ---------------- memory budget ----------------
+        const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
+        const size_t SR = (size_t)h->S * h->ring_total;
+        size_t bytes = SR * 8 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
+                       h->dist.size() * 8 + (size_t)h->S * h->D * h->nb * 8;
+        int n_ck = 0;
+        if (h->record) {
+            n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
+            h->W = h->ckpt_every;
+            bytes += (size_t)n_ck * (SR * 8 + SL * 24 + SO * 16 + SN);
+            bytes += (size_t)(h->W + 1) * (SR * 8 + SL * 8) + SN * 8 + SL * 16;
+        }
+        if (cfg->mem_budget_bytes && bytes > cfg->mem_budget_bytes)
+            fail(SIM_ENOMEM, "footprint " + std::to_string(bytes) + " B exceeds the memory budget");
+
+        // ---------------- device ----------------
+        Dev &d = h->d;
+        d.S = h->S; d.L = L; d.Nn = Nn; d.O = h->O; d.N = h->N; d.D = h->D; d.nb = h->nb; d.cbs = h->cbs;
+        d.n_dest = (int)h->dest_nodes.size(); d.maxl = maxl; d.n_rate_bins = h->B;
+        d.fixed_mode = h->fixed_mode; d.allow_uturn = cfg->allow_uturn; d.platoon = h->platoon;
+        d.ring_total = h->ring_total; d.dt = h->dt; d.theta = cfg->dest_logit_coef; d.rate_bin_s = h->rate_bin_s;
+        d.tail = h->upload(h->tail); d.head = h->upload(h->head); d.lanes = h->upload(h->lanes);
+        d.cap = h->upload(h->cap); d.ring_base = h->upload(h->ring_base);
+        d.length = h->upload(h->length);
+        std::vector<float> thr(L);
+        for (int j = 0; j < L; ++j) thr[j] = h->length[j] - 0.01f;
+        d.thr = h->upload(thr);
+        d.out_off = h->upload(h->out_off); d.out_lnk = h->upload(h->out_lnk);
+        d.in_off = h->upload(h->in_off); d.in_lnk = h->upload(h->in_lnk);
+        d.org_off = h->upload(h->org_off); d.org_list = h->upload(h->org_list);
+        d.det_off = h->upload(h->det_off); d.det_list = h->upload(h->det_list);
+        d.det_pos = h->upload(h->det_pos);
+        d.tff = h->upload(h->tff); d.dist = h->upload(h->dist);
+        d.agent_didx = h->upload(h->agent_didx); d.agent_dest = h->upload(h->agent_dest);
+        d.agent_origin = h->upload(h->agent_origin);
+        h->q_off_dev = h->upload(h->q_off);
+        h->q_list_dev = h->dalloc<int32_t>(h->q_list.size());
+        h->q_rstep_dev = h->dalloc<int64_t>(h->q_rstep.size());
+        upload_queues(h);
+        d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
+        d.seed = h->upload(h->seeds);
+        // parameters, scenario-major
+        auto rep = [&](const std::vector<float> &v) {
+            std::vector<float> r((size_t)h->S * v.size());
+            for (int s = 0; s < h->S; ++s) std::copy(v.begin(), v.end(), r.begin() + (size_t)s * v.size());
+            return r;
+        };
+        h->p_u = h->upload(rep(h->free_speed)); h->p_kappa = h->upload(rep(h->jam_density));
+        h->p_beta = h->upload(rep(h->beta)); h->p_alpha = h->upload(rep(h->alpha)); h->p_cost = h->upload(rep(h->cost));
+        h->p_capm = h->upload(rep(std::vector<float>(L, 1.f)));
+        h->p_rates = h->fixed_mode ? h->dalloc<float>(1) : h->upload(rep(h->rates));
+        h->capacity_dev = h->upload(h->capacity);
+        d.u = h->p_u; d.kappa = h->p_kappa; d.alpha = h->p_alpha; d.rates = h->p_rates;
+        h->vfree = h->dalloc<float>(SL); h->spacing = h->dalloc<float>(SL);
+        h->util = h->dalloc<double>(SL); h->acc = h->dalloc<double>(SL);
+        d.vfree = h->vfree; d.spacing = h->spacing; d.util = h->util; d.acc = h->acc;
+        // state
+        d.ring_pos = h->dalloc<float>(SR); d.ring_agent = h->dalloc<int32_t>(SR);
+        d.rhead = h->dalloc<int32_t>(SL); d.rtail = h->dalloc<int32_t>(SL);
+        d.B = h->dalloc<double>(SL); d.E = h->dalloc<int64_t>(SL);
+        d.slots = h->dalloc<int32_t>(SL); d.nheads = h->dalloc<int32_t>(SL);
+        d.head_agent = h->dalloc<int32_t>(SL * maxl); d.head_choice = h->dalloc<int32_t>(SL * maxl);
+        d.head_key = h->dalloc<double>(SL * maxl);
+        d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
+        d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
+        d.Dacc = h->dalloc<double>(SO); d.rel_ptr = h->dalloc<int32_t>(SO); d.dep_ptr = h->dalloc<int32_t>(SO);
+        d.ctr = h->dalloc<int64_t>((size_t)h->S * sim::CTR_N);
+        d.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
+        d.err = h->dalloc<int32_t>(sim::ERR_N);
+        h->ttt_dev = h->dalloc<double>(h->S);
+        h->counts_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
+        if (h->record) {
+            h->ckpts.resize(n_ck + 1);
+            for (auto &c : h->ckpts) ckpt_alloc(h, c);
+            d.tape_pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
+            d.tape_agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
+            d.tape_head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+            d.tape_tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+            d.adj = h->dalloc<float>(SN); d.depg = h->dalloc<float>(SN);
+            d.gu = h->dalloc<double>(SL); d.gk = h->dalloc<double>(SL);
+            h->gQ_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
+            h->gx_dev = h->dalloc<float>(SN);
+            h->gT_dev = h->dalloc<double>(h->S);
+            h->grad_tmp = h->dalloc<float>(std::max(SL, (size_t)h->S * h->O * std::max(h->B, 1)));
+        }
+        derive(h);
+        zero_state(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        *out = h;
+        return SIM_OK;
+    } catch (const InvalidArg &e) {
+        delete h;
+        return record_error(nullptr, e.code, e.msg);
+    } catch (const HipError &e) {
+        delete h;
+        return record_error(nullptr, SIM_EDEVICE, e.msg);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return record_error(nullptr, SIM_ENOMEM, "host allocation failed");
+    }
+}
+
+int sim_destroy(sim_t *h)
+{
+    delete h;
+    return SIM_OK;
+}
+
+int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_device)
+{
+    return guarded(h, [&] {
+        if (!values) fail(SIM_EINVAL, "values is NULL");
+        float *dst = nullptr;
+        int64_t per = h->L;
+        switch (which) {
+        case SIM_P_U: dst = h->p_u; break;
+        case SIM_P_KAPPA: dst = h->p_kappa; break;
+        case SIM_P_BETA: dst = h->p_beta; break;
+        case SIM_P_ALPHA: dst = h->p_alpha; break;
+        case SIM_P_COST: dst = h->p_cost; break;
+        case SIM_P_CAP_MULT: dst = h->p_capm; break;
+        case SIM_P_RATES:
+            if (h->fixed_mode) fail(SIM_EINVAL, "rates need departure-rate mode");
+            dst = h->p_rates; per = (int64_t)h->O * h->B; break;
+        default: fail(SIM_EINVAL, "unknown parameter group");
+        }
+        if (n != per * h->S) fail(SIM_EINVAL, "expected " + std::to_string(per * h->S) + " values");
+        std::vector<float> host;
+        if (!on_device || which == SIM_P_KAPPA || which == SIM_P_U || which == SIM_P_COST || which == SIM_P_RATES) {
+            host.resize(n);
+            HIPCHK(hipMemcpyAsync(host.data(), values, n * 4, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            for (int64_t i = 0; i < n; ++i) {
+                const float v = host[i];
+                if (!std::isfinite(v)) fail(SIM_EINVAL, "non-finite parameter");
+                if ((which == SIM_P_U || which == SIM_P_KAPPA || which == SIM_P_COST) && !(v > 0.f))
+                    fail(SIM_EINVAL, "u, kappa and cost must be > 0");
+                if (which == SIM_P_RATES && !(v >= 0.f)) fail(SIM_EINVAL, "rates must be >= 0");
+                if (which == SIM_P_KAPPA) {
+                    const int j = (int)(i % h->L);
+                    if ((float)h->platoon / v < h->min_spacing[j])
+                        fail(SIM_EINVAL, "kappa above the value the link rings were sized for");
+                }
+            }
+            HIPCHK(hipMemcpyAsync(dst, host.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+        } else {
+            HIPCHK(hipMemcpyAsync(dst, values, n * 4, hipMemcpyDeviceToDevice, h->stream));
+        }
+        derive(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_reset(sim_t *h)
+{
+    return guarded(h, [&] {
+        build_queues(h, nullptr);
+        upload_queues(h);
+        zero_state(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, const float *pos)
+{
+    return guarded(h, [&] {
+        if (h->t != 0) fail(SIM_ESTATE, "sim_place is only allowed at t = 0");
+        if (n < 0 || (n > 0 && (!agent || !link || !pos))) fail(SIM_EINVAL, "bad placement arrays");
+        std::vector<uint8_t> placed(h->N, 0);
+        std::vector<int32_t> cnt(h->L, 0);
+        for (int k = 0; k < n; ++k) {
+            if (agent[k] < 0 || agent[k] >= h->N || placed[agent[k]]) fail(SIM_EINVAL, "bad or repeated agent");
+            if (link[k] < 0 || link[k] >= h->L) fail(SIM_EINVAL, "bad link");
+            if (!(pos[k] >= 0.f) || !(pos[k] <= h->length[link[k]])) fail(SIM_EINVAL, "position outside the link");
+            placed[agent[k]] = 1;
+            if (++cnt[link[k]] > h->cap[link[k]]) fail(SIM_EINVAL, "too many agents placed on a link");
+        }
+        // current (empty, t = 0) rings and per-agent arrays
+        const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
+        std::vector<float> rp(SR, 0.f);
+        std::vector<int32_t> ra(SR, 0), rt(SL, 0), rh(SL, 0);
+        HIPCHK(hipMemcpyAsync(rh.data(), h->d.rhead, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(rt.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(rp.data(), h->d.ring_pos, SR * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ra.data(), h->d.ring_agent, SR * 4, hipMemcpyDeviceToHost, h->stream));
+        std::vector<uint8_t> st(SN);
+        std::vector<int32_t> relt(SN), dept(SN);
+        HIPCHK(hipMemcpyAsync(st.data(), h->d.status, SN, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(relt.data(), h->d.rel_t, SN * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(dept.data(), h->d.dep_t, SN * 4, hipMemcpyDeviceToHost, h->stream));
+        std::vector<int64_t> ctr((size_t)h->S * sim::CTR_N);
+        HIPCHK(hipMemcpyAsync(ctr.data(), h->d.ctr, ctr.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int s = 0; s < h->S; ++s) {
+            for (int k = 0; k < n; ++k) {
+                const int j = link[k];
+                const size_t seg = (size_t)s * h->L + j;
+                const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (rt[seg] % h->cap[j]);
+                ra[slot] = agent[k];
+                rp[slot] = pos[k];
+                rt[seg] += 1;
+                const size_t ga = (size_t)s * h->N + agent[k];
+                st[ga] = sim::AG_ON;
+                relt[ga] = 0;
+                dept[ga] = -2;   // placed, not departed: no departure graft
+            }
+            ctr[(size_t)s * sim::CTR_N + sim::CTR_RELEASED] += n;
+            ctr[(size_t)s * sim::CTR_N + sim::CTR_DEPARTED] += n;
+        }
+        HIPCHK(hipMemcpyAsync(h->d.rtail, rt.data(), SL * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.ring_pos, rp.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.ring_agent, ra.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.status, st.data(), SN, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.rel_t, relt.data(), SN * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.dep_t, dept.data(), SN * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.ctr, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice, h->stream));
+        build_queues(h, &placed);
+        upload_queues(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_step(sim_t *h)
+{
+    return sim_rollout(h, 1);
+}
+
+int sim_rollout(sim_t *h, int32_t T)
+{
+    return guarded(h, [&] {
+        if (T < 0) fail(SIM_EINVAL, "T < 0");
+        for (int k = 0; k < T; ++k) {
+            if (h->record && h->rec_valid) {
+                if (h->t >= h->max_steps) h->rec_valid = false;
+                else if (h->t % h->ckpt_every == 0) {
+                    Ckpt &c = h->ckpts[h->t / h->ckpt_every];
+                    hipEvent_t e = nullptr;
+                    h->time_begin(3, &e);
+                    ckpt_copy(h, c, true);
+                    h->time_end(3, e);
+                    c.t = h->t;
+                }
+            }
+            do_step(h, -1);
+        }
+        if (h->timing) h->resolve_timing();
+        check_device_errors(h);
+    });
+}
+
+int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device)
+{
+    return guarded(h, [&] {
+        if (counts && h->D * h->nb > 0) {
+            sim::launch_counts(h->d, h->counts_dev, h->stream);
+            copy_out(h, counts, h->counts_dev, (size_t)h->S * h->D * h->nb * 4, on_device);
+        }
+        if (ttt) {
+            sim::launch_ttt(h->d, h->t, h->ttt_dev, nullptr, h->stream);
+            copy_out(h, ttt, h->ttt_dev, (size_t)h->S * 8, on_device);
+        }
+        HIPCHK(hipGetLastError());
+        if (!on_device) HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const float *dL_dpos,
+                 uint32_t param_mask, float *const *grads, int on_device)
+{
+    return guarded(h, [&] {
+        if (!h->record) fail(SIM_ESTATE, "handle was created without record_for_backward");
+        if (!h->rec_valid || h->t == 0 || h->ckpts[0].t != 0)
+            fail(SIM_ESTATE, "sim_backward needs a recorded rollout from t = 0 (at most max_steps)");
+        const uint32_t ok = (1u << SIM_P_U) | (1u << SIM_P_KAPPA) | (1u << SIM_P_RATES);
+        if (param_mask & ~ok) fail(SIM_EUNSUPPORTED, "gradient groups supported: u, kappa, rates");
+        if ((param_mask & (1u << SIM_P_RATES)) && h->fixed_mode) fail(SIM_EINVAL, "rates need departure-rate mode");
+        if (param_mask && !grads) fail(SIM_EINVAL, "grads is NULL");
+        Dev d = h->d;
+        const hipStream_t st = h->stream;
+        const size_t SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
+        const size_t nQ = (size_t)h->S * h->D * h->nb;
+        const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        d.gQ = nullptr; d.gT = nullptr; d.gx = nullptr;
+        if (dL_dcounts && nQ) { HIPCHK(hipMemcpyAsync(h->gQ_dev, dL_dcounts, nQ * 4, kin, st)); d.gQ = h->gQ_dev; }
+        if (dL_dttt) { HIPCHK(hipMemcpyAsync(h->gT_dev, dL_dttt, h->S * 8, kin, st)); d.gT = h->gT_dev; }
+        if (dL_dpos) { HIPCHK(hipMemcpyAsync(h->gx_dev, dL_dpos, SN * 4, kin, st)); d.gx = h->gx_dev; }
+        HIPCHK(hipMemsetAsync(d.adj, 0, SN * 4, st));
+        HIPCHK(hipMemsetAsync(d.depg, 0, SN * 4, st));
+        HIPCHK(hipMemsetAsync(d.gu, 0, SL * 8, st));
+        HIPCHK(hipMemsetAsync(d.gk, 0, SL * 8, st));
+        const int T = h->t;
+        Ckpt &fin = h->ckpts.back();
+        ckpt_copy(h, fin, true);
+        const int nw = (T + h->ckpt_every - 1) / h->ckpt_every;
+        for (int w = nw - 1; w >= 0; --w) {
+            const int t0 = w * h->ckpt_every;
+            const int Ww = std::min(h->ckpt_every, T - t0);
+            hipEvent_t e = nullptr;
+            h->time_begin(3, &e);
+            ckpt_copy(h, h->ckpts[w], false);
+            h->time_end(3, e);
+            h->t = t0;
+            h->d.gQ = d.gQ; h->d.gT = d.gT; h->d.gx = d.gx;
+            for (int k = 0; k < Ww; ++k) do_step(h, k);
+            sim::launch_tape_snapshot(d, Ww, st);
+            if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
+            for (int k = Ww - 1; k >= 0; --k) {
+                hipEvent_t e2 = nullptr;
+                h->time_begin(2, &e2);
+                sim::launch_reverse(d, t0 + k, k, 0, st);
+                h->time_end(2, e2);
+            }
+            HIPCHK(hipGetLastError());
+        }
+        ckpt_copy(h, fin, false);
+        h->t = T;
+        h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
+        const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (param_mask & (1u << SIM_P_U)) {
+            sim::launch_d2f(d.gu, h->grad_tmp, SL, st);
+            HIPCHK(hipMemcpyAsync(grads[SIM_P_U], h->grad_tmp, SL * 4, kout, st));
+        }
+        if (param_mask & (1u << SIM_P_KAPPA)) {
+            sim::launch_d2f(d.gk, h->grad_tmp, SL, st);
+            HIPCHK(hipMemcpyAsync(grads[SIM_P_KAPPA], h->grad_tmp, SL * 4, kout, st));
+        }
+        if (param_mask & (1u << SIM_P_RATES)) {
+            const size_t nr = (size_t)h->S * h->O * h->B;
+            sim::launch_rate_grad(d, h->grad_tmp, st);
+            HIPCHK(hipMemcpyAsync(grads[SIM_P_RATES], h->grad_tmp, nr * 4, kout, st));
+        }
+        HIPCHK(hipGetLastError());
+        if (h->timing) h->resolve_timing();
+        check_device_errors(h);
+    });
+}
+
+int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t *seq, int64_t *counters)
+{
+    return guarded(h, [&] {
+        const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
+        std::vector<float> rp(SR);
+        std::vector<int32_t> ra(SR), rh(SL), rt(SL);
+        std::vector<uint8_t> st(SN);
+        HIPCHK(hipMemcpyAsync(rp.data(), h->d.ring_pos, SR * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ra.data(), h->d.ring_agent, SR * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(rh.data(), h->d.rhead, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(rt.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(st.data(), h->d.status, SN, hipMemcpyDeviceToHost, h->stream));
+        std::vector<int64_t> ctr((size_t)h->S * sim::CTR_N);
+        HIPCHK(hipMemcpyAsync(ctr.data(), h->d.ctr, ctr.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (status) for (size_t i = 0; i < SN; ++i) status[i] = st[i];
+        if (link) std::fill(link, link + SN, -1);
+        if (pos) std::fill(pos, pos + SN, 0.f);
+        if (seq) std::fill(seq, seq + SN, 0);
+        for (int s = 0; s < h->S; ++s)
+            for (int j = 0; j < h->L; ++j) {
+                const size_t seg = (size_t)s * h->L + j;
+                for (int q = rh[seg]; q < rt[seg]; ++q) {
+                    const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (q % h->cap[j]);
+                    const size_t ga = (size_t)s * h->N + ra[slot];
+                    if (link) link[ga] = j;
+                    if (pos) pos[ga] = rp[slot];
+                    if (seq) seq[ga] = q;
+                }
+            }
+        if (counters) {
+            for (int s = 0; s < h->S; ++s) {
+                int64_t *c = counters + (size_t)s * SIM_C_COUNT;
+                const int64_t *g = ctr.data() + (size_t)s * sim::CTR_N;
+                for (int k = 0; k < SIM_C_COUNT; ++k) c[k] = g[k];
+                c[SIM_C_ON_NET] = g[sim::CTR_DEPARTED] - g[sim::CTR_EXITED];
+            }
+        }
+    });
+}
+
+int sim_get_stats(sim_t *h, int64_t *vehicle_steps)
+{
+    return guarded(h, [&] {
+        if (!vehicle_steps) fail(SIM_EINVAL, "null output");
+        int64_t *dv = h->dalloc_scratch_i64(h->S);
+        sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(vehicle_steps, dv, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq)
+{
+    return guarded(h, [&] {
+        const size_t SL = (size_t)h->S * h->L;
+        if (B) HIPCHK(hipMemcpyAsync(B, h->d.B, SL * 8, hipMemcpyDeviceToHost, h->stream));
+        if (E) HIPCHK(hipMemcpyAsync(E, h->d.E, SL * 8, hipMemcpyDeviceToHost, h->stream));
+        if (next_seq) HIPCHK(hipMemcpyAsync(next_seq, h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_get_dist(sim_t *h, double *out, int32_t *n_dest)
+{
+    return guarded(h, [&] {
+        if (n_dest) *n_dest = (int32_t)h->dest_nodes.size();
+        if (out) std::memcpy(out, h->dist.data(), h->dist.size() * 8);
+    });
+}
+
+int sim_time(const sim_t *h, int32_t *t)
+{
+    if (!h || !t) return SIM_EINVAL;
+    *t = h->t;
+    return SIM_OK;
+}
+
+int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    return guarded(h, [&] {
+        if (n < 0 || (n > 0 && (!ctr || !key || !out))) fail(SIM_EINVAL, "bad philox arrays");
+        if (n == 0) return;
+        uint32_t *dc = nullptr, *dk = nullptr, *dout = nullptr;
+        HIPCHK(hipMalloc(&dc, (size_t)n * 16));
+        HIPCHK(hipMalloc(&dk, (size_t)n * 8));
+        HIPCHK(hipMalloc(&dout, (size_t)n * 16));
+        HIPCHK(hipMemcpyAsync(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(dk, key, (size_t)n * 8, hipMemcpyHostToDevice, h->stream));
+        sim::launch_philox(n, dc, dk, dout, h->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        (void)hipFree(dc); (void)hipFree(dk); (void)hipFree(dout);
+    });
+}
+
+int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos, const int32_t *seq,
+                int32_t *perm, int32_t *seg_off)
+{
+    return guarded(h, [&] {
+        if (n < 0 || n_segments < 1) fail(SIM_EINVAL, "bad sizes");
+        if (n > 0 && (!seg || !pos || !seq || !perm || !seg_off)) fail(SIM_EINVAL, "null array");
+        int32_t *scratch = nullptr;
+        HIPCHK(hipMalloc(&scratch, ((size_t)n_segments + 1) * 4 * 2 + 64));
+        const int rc = sim::launch_segsort(n, n_segments, seg, pos, seq, perm, seg_off, scratch, h->stream);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        (void)hipFree(scratch);
+        if (rc != 0) fail(SIM_EUNSUPPORTED, "a segment exceeds the LDS sort capacity");
+    });
+}
+
+int sim_set_timing(sim_t *h, int enable)
+{
+    return guarded(h, [&] { h->timing = enable != 0; });
+}
+
+int sim_get_timing(sim_t *h, double *ms, int64_t *launches, int n_kinds, int reset)
+{
+    return guarded(h, [&] {
+        h->resolve_timing();
+        for (int k = 0; k < n_kinds && k < 4; ++k) {
+            if (ms) ms[k] = h->ms_acc[k];
+            if (launches) launches[k] = h->n_acc[k];
+        }
+        if (reset) for (int k = 0; k < 4; ++k) { h->ms_acc[k] = 0; h->n_acc[k] = 0; }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,366 @@
+"""Python binding of the HIP simulator library (include/sim.h).
+
+Argument marshalling only: every step of the simulation and of its adjoint
+runs in the HIP kernels of libsim.so.  PyTorch supplies the stream (and
+device tensors for on-device outputs).  There is no CPU fallback: without the
+built library every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsim.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PARAMS = {"free_speed": 0, "jam_density": 1, "beta": 2, "alpha": 3, "cost": 4, "rates": 5, "cap_mult": 6}
+PARAM_NAMES = {v: k for k, v in PARAMS.items()}
+COUNTER_NAMES = ("released", "departed", "on_net", "exited", "transfers", "ties", "stuck", "order_viol")
+WAIT, QUEUED, ON, EXITED = 0, 1, 2, 3
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Network(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_links", C.c_int32),
+                ("tail", C.c_void_p), ("head", C.c_void_p), ("lanes", C.c_void_p),
+                ("length", C.c_void_p), ("free_speed", C.c_void_p), ("jam_density", C.c_void_p),
+                ("capacity", C.c_void_p), ("beta", C.c_void_p), ("alpha", C.c_void_p), ("cost", C.c_void_p),
+                ("n_origins", C.c_int32), ("origin_node", C.c_void_p),
+                ("n_detectors", C.c_int32), ("detector_link", C.c_void_p), ("detector_pos", C.c_void_p)]
+
+
+class _Demand(C.Structure):
+    _fields_ = [("n_agents", C.c_int32), ("agent_origin", C.c_void_p), ("agent_dest", C.c_void_p),
+                ("ready_time", C.c_void_p), ("n_rate_bins", C.c_int32), ("rate_bin_s", C.c_double),
+                ("rates", C.c_void_p)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("dt", C.c_double), ("platoon", C.c_int32), ("gumbel_tau", C.c_double),
+                ("dest_logit_coef", C.c_double), ("big_m", C.c_double), ("seed", C.c_uint64),
+                ("scenario_seed", C.c_void_p), ("n_scenarios", C.c_int32), ("ckpt_every", C.c_int32),
+                ("count_bin_steps", C.c_int32), ("n_count_bins", C.c_int32), ("max_steps", C.c_int32),
+                ("allow_uturn", C.c_int32), ("record_for_backward", C.c_int32), ("mem_budget_bytes", C.c_size_t)]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libsim.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "sim_create": ([vp, vp, vp, C.c_int, vp, vp], C.c_int),
+        "sim_destroy": ([vp], C.c_int),
+        "sim_last_error": ([vp], C.c_char_p),
+        "sim_set_params": ([vp, C.c_int, vp, i64, C.c_int], C.c_int),
+        "sim_reset": ([vp], C.c_int),
+        "sim_place": ([vp, i32, vp, vp, vp], C.c_int),
+        "sim_step": ([vp], C.c_int),
+        "sim_rollout": ([vp, i32], C.c_int),
+        "sim_get_observables": ([vp, vp, vp, C.c_int], C.c_int),
+        "sim_backward": ([vp, vp, vp, vp, C.c_uint32, vp, C.c_int], C.c_int),
+        "sim_get_state": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "sim_get_link_state": ([vp, vp, vp, vp], C.c_int),
+        "sim_get_stats": ([vp, vp], C.c_int),
+        "sim_get_dist": ([vp, vp, vp], C.c_int),
+        "sim_time": ([vp, vp], C.c_int),
+        "sim_philox": ([vp, i32, vp, vp, vp], C.c_int),
+        "sim_segsort": ([vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "sim_set_timing": ([vp, C.c_int], C.c_int),
+        "sim_get_timing": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = L
+    return L
+
+
+def exported_symbols() -> list:
+    return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
+            "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
+            "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_segsort",
+            "sim_set_timing", "sim_get_timing"]
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, np.int32)
+
+
+class Simulator:
+    """A handle on the HIP simulator for one workload, batched over scenarios.
+
+    `params`: optional {group: array [S x n] or [n]} overrides (free_speed,
+    jam_density, beta, alpha, cost, cap_mult per link; rates per origin x bin).
+    `seeds`: optional per-scenario Philox keys (default cfg.seed + s)."""
+
+    def __init__(self, w, n_scenarios: int = 1, params: Optional[dict] = None, seeds: Optional[Sequence[int]] = None,
+                 record: bool = False, max_steps: Optional[int] = None, steps: Optional[int] = None,
+                 device: int = 0, stream=None, mem_budget_bytes: int = 0, ckpt_every: Optional[int] = None):
+        import torch
+        self._L = lib()
+        self.w = w
+        self.S = int(n_scenarios)
+        net, dem, cfg = w.net, w.dem, w.cfg
+        self.steps = int(steps if steps is not None else cfg.steps)
+        cbs = int(cfg.count_bin_steps)
+        self.n_count_bins = self.steps // cbs if cbs > 0 else 0
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        K = {
+            "tail": _i32(net.tail), "head": _i32(net.head), "lanes": _i32(net.lanes),
+            "length": _f32(net.length), "free_speed": _f32(net.free_speed), "jam_density": _f32(net.jam_density),
+            "capacity": _f32(net.capacity), "beta": _f32(net.beta), "alpha": _f32(net.alpha), "cost": _f32(net.cost),
+            "origin_node": _i32(net.origin_node), "detector_link": _i32(net.detector_link),
+            "detector_pos": _f32(net.detector_pos), "agent_origin": _i32(dem.agent_origin),
+            "agent_dest": _i32(dem.agent_dest),
+        }
+        if dem.ready_time is not None:
+            K["ready_time"] = _f32(dem.ready_time)
+        else:
+            K["rates"] = _f32(dem.rates)
+        if seeds is not None:
+            K["seeds"] = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+        self._keep = K
+        n = _Network(net.n_nodes, net.n_links, _p(K["tail"]), _p(K["head"]), _p(K["lanes"]), _p(K["length"]),
+                     _p(K["free_speed"]), _p(K["jam_density"]), _p(K["capacity"]), _p(K["beta"]), _p(K["alpha"]),
+                     _p(K["cost"]), net.n_origins, _p(K["origin_node"]), net.n_detectors, _p(K["detector_link"]),
+                     _p(K["detector_pos"]))
+        d = _Demand(dem.n_agents, _p(K["agent_origin"]), _p(K["agent_dest"]), _p(K.get("ready_time")),
+                    dem.n_rate_bins, float(dem.rate_bin_s), _p(K.get("rates")))
+        c = _Config(float(cfg.dt), int(cfg.platoon), float(cfg.gumbel_tau), float(cfg.dest_logit_coef),
+                    float(cfg.big_m), int(cfg.seed) & (2 ** 64 - 1), _p(K.get("seeds")), self.S,
+                    int(ckpt_every or cfg.ckpt_every), cbs, self.n_count_bins,
+                    int(max_steps if max_steps is not None else self.steps), int(cfg.allow_uturn), int(record),
+                    int(mem_budget_bytes))
+        h = C.c_void_p()
+        rc = self._L.sim_create(C.byref(n), C.byref(d), C.byref(c), device, C.c_void_p(stream.cuda_stream),
+                                C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, self._L.sim_last_error(None).decode())
+        self._h = h
+        for k, v in (params or {}).items():
+            self.set_params(k, v)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.sim_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != SIM_OK:
+            raise SimError(rc, self._L.sim_last_error(self._h).decode())
+
+    # -- sizes -----------------------------------------------------------
+    def n_per(self, group: str) -> int:
+        if group == "rates":
+            return self.w.net.n_origins * self.w.dem.n_rate_bins
+        return self.w.net.n_links
+
+    # -- control ----------------------------------------------------------
+    def set_params(self, group: str, values):
+        import torch
+        n = self.n_per(group)
+        if isinstance(values, torch.Tensor) and values.is_cuda:
+            v = values.detach().to(torch.float32).contiguous()
+            if v.numel() == n:
+                v = v.repeat(self.S)
+            self._chk(self._L.sim_set_params(self._h, PARAMS[group], C.c_void_p(v.data_ptr()), v.numel(), 1))
+            return
+        v = np.asarray(values, np.float32).reshape(-1)
+        if v.size == n:
+            v = np.tile(v, self.S)
+        v = np.ascontiguousarray(v)
+        self._chk(self._L.sim_set_params(self._h, PARAMS[group], _p(v), v.size, 0))
+
+    def reset(self):
+        self._chk(self._L.sim_reset(self._h))
+
+    def place(self, agents, links, pos):
+        a, l, p = _i32(agents), _i32(links), _f32(pos)
+        self._chk(self._L.sim_place(self._h, len(a), _p(a), _p(l), _p(p)))
+
+    def step(self, n: int = 1):
+        self._chk(self._L.sim_rollout(self._h, int(n)))
+
+    def rollout(self, T: Optional[int] = None):
+        self.step(self.steps if T is None else T)
+        return self
+
+    @property
+    def t(self) -> int:
+        t = C.c_int32(0)
+        self._chk(self._L.sim_time(self._h, C.byref(t)))
+        return t.value
+
+    # -- outputs ------------------------------------------------------------
+    def observables(self):
+        Dd, nb = self.w.net.n_detectors, self.n_count_bins
+        cnt = np.zeros((self.S, Dd, nb), np.float32)
+        ttt = np.zeros(self.S, np.float64)
+        self._chk(self._L.sim_get_observables(self._h, _p(cnt), _p(ttt), 0))
+        return cnt, ttt
+
+    def observables_device(self):
+        import torch
+        Dd, nb = self.w.net.n_detectors, self.n_count_bins
+        dev = torch.device("cuda", self.device)
+        cnt = torch.zeros((self.S, Dd, nb), dtype=torch.float32, device=dev)
+        ttt = torch.zeros(self.S, dtype=torch.float64, device=dev)
+        self._chk(self._L.sim_get_observables(self._h, C.c_void_p(cnt.data_ptr()), C.c_void_p(ttt.data_ptr()), 1))
+        return cnt, ttt
+
+    def backward(self, gQ=None, gT=None, gx=None, groups=("free_speed", "jam_density", "rates")):
+        S, net = self.S, self.w.net
+        gQ = None if gQ is None else _f32(np.broadcast_to(np.asarray(gQ, np.float32),
+                                                          (S, net.n_detectors, self.n_count_bins)))
+        gT = None if gT is None else np.ascontiguousarray(np.broadcast_to(np.asarray(gT, np.float64), (S,)))
+        gx = None if gx is None else _f32(np.asarray(gx, np.float32).reshape(S, -1))
+        mask = 0
+        bufs = {}
+        arr = (C.c_void_p * 7)()
+        for g in groups:
+            k = PARAMS[g]
+            mask |= 1 << k
+            bufs[g] = np.zeros((S, self.n_per(g)), np.float32)
+            arr[k] = bufs[g].ctypes.data
+        self._chk(self._L.sim_backward(self._h, _p(gQ), _p(gT), _p(gx), mask, arr, 0))
+        return bufs
+
+    def backward_device(self, gQ=None, gT=None, gx=None, groups=("free_speed", "jam_density", "rates")):
+        import torch
+        dev = torch.device("cuda", self.device)
+        mask = 0
+        out = {}
+        arr = (C.c_void_p * 7)()
+        for g in groups:
+            k = PARAMS[g]
+            mask |= 1 << k
+            out[g] = torch.zeros((self.S, self.n_per(g)), dtype=torch.float32, device=dev)
+            arr[k] = out[g].data_ptr()
+        ptr = lambda x: None if x is None else C.c_void_p(x.contiguous().data_ptr())
+        self._chk(self._L.sim_backward(self._h, ptr(gQ), ptr(gT), ptr(gx), mask, arr, 1))
+        return out
+
+    def state(self):
+        S, N = self.S, self.w.dem.n_agents
+        st, lk, sq = (np.zeros((S, N), np.int32) for _ in range(3))
+        ps = np.zeros((S, N), np.float32)
+        ctr = np.zeros((S, 8), np.int64)
+        self._chk(self._L.sim_get_state(self._h, _p(st), _p(lk), _p(ps), _p(sq), _p(ctr)))
+        return {"status": st, "link": lk, "pos": ps, "seq": sq,
+                "counters": [dict(zip(COUNTER_NAMES, c.tolist())) for c in ctr]}
+
+    def vehicle_steps(self) -> np.ndarray:
+        out = np.zeros(self.S, np.int64)
+        self._chk(self._L.sim_get_stats(self._h, _p(out)))
+        return out
+
+    def link_state(self):
+        S, L = self.S, self.w.net.n_links
+        B = np.zeros((S, L), np.float64)
+        E = np.zeros((S, L), np.int64)
+        ns = np.zeros((S, L), np.int32)
+        self._chk(self._L.sim_get_link_state(self._h, _p(B), _p(E), _p(ns)))
+        return {"B": B, "E": E, "next_seq": ns}
+
+    def dist_table(self):
+        nd = C.c_int32(0)
+        self._chk(self._L.sim_get_dist(self._h, None, C.byref(nd)))
+        out = np.zeros((nd.value, self.w.net.n_nodes), np.float64)
+        self._chk(self._L.sim_get_dist(self._h, _p(out), None))
+        return out
+
+    def philox(self, ctr, key):
+        c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+        k = np.ascontiguousarray(key, np.uint32).reshape(-1, 2)
+        out = np.zeros_like(c)
+        self._chk(self._L.sim_philox(self._h, c.shape[0], _p(c), _p(k), _p(out)))
+        return out
+
+    def segsort(self, seg, pos, seq, n_segments: int):
+        """seg/pos/seq: torch device tensors; returns (perm, seg_off) device tensors."""
+        import torch
+        n = seg.numel()
+        perm = torch.zeros(n, dtype=torch.int32, device=seg.device)
+        off = torch.zeros(n_segments + 1, dtype=torch.int32, device=seg.device)
+        self._chk(self._L.sim_segsort(self._h, n, n_segments, C.c_void_p(seg.data_ptr()), C.c_void_p(pos.data_ptr()),
+                                      C.c_void_p(seq.data_ptr()), C.c_void_p(perm.data_ptr()),
+                                      C.c_void_p(off.data_ptr())))
+        return perm, off
+
+    def set_timing(self, on: bool = True):
+        self._chk(self._L.sim_set_timing(self._h, int(on)))
+
+    def timing(self, reset: bool = True):
+        ms = np.zeros(4, np.float64)
+        n = np.zeros(4, np.int64)
+        self._chk(self._L.sim_get_timing(self._h, _p(ms), _p(n), 4, int(reset)))
+        names = ("link", "node", "reverse", "copy")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+
+
+def make_rollout_function():
+    """torch.autograd.Function around one recorded rollout: forward sets the
+    parameters and runs T steps, returning detector counts and total travel
+    time; backward runs the checkpointed adjoint."""
+    import torch
+
+    class SimRollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sim: Simulator, T: int, free_speed, jam_density, rates):
+            sim.set_params("free_speed", free_speed)
+            sim.set_params("jam_density", jam_density)
+            if rates is not None and rates.numel() > 0:
+                sim.set_params("rates", rates)
+            sim.reset()
+            sim.step(T)
+            counts, ttt = sim.observables_device()
+            ctx.sim = sim
+            ctx.has_rates = rates is not None and rates.numel() > 0
+            return counts, ttt
+
+        @staticmethod
+        def backward(ctx, g_counts, g_ttt):
+            sim = ctx.sim
+            groups = ("free_speed", "jam_density") + (("rates",) if ctx.has_rates else ())
+            g = sim.backward_device(gQ=g_counts.float() if g_counts is not None else None,
+                                    gT=g_ttt.double() if g_ttt is not None else None, groups=groups)
+            gr = g.get("rates")
+            return None, None, g["free_speed"], g["jam_density"], gr
+
+    return SimRollout
