@@ -205,6 +205,12 @@ int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, ui
 int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
                 const int32_t *seq, int32_t *perm, int32_t *seg_off);
 
+/* Launch schedule: lanes per work item of the link-phase, node-phase and
+ * reverse kernels (16, 32 or 64; the node group must hold the largest
+ * node's merge candidates and out-links).  Results do not depend on it. */
+int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev);
+int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
+
 /* Device time (ms) and launch count of each kernel kind accumulated since
  * the last call with reset = 1, measured with HIP events on the handle's
  * stream when timing is enabled (sim_set_timing). kinds: 0 link phase,

@@ -19,6 +19,7 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxLanes = 8;     // lanes per link accepted by sim_create
 constexpr int kMaxDetPerLink = 4;
+constexpr int kCtrSlots = 64;      // counters are spread over this many slots per scenario
 enum : int32_t { CH_STUCK = -1, CH_EXIT = -2, CH_NONE = -3 };
 enum : uint8_t { AG_WAIT = 0, AG_QUEUED = 1, AG_ON = 2, AG_EXITED = 3 };
 enum { CTR_RELEASED = 0, CTR_DEPARTED, CTR_ON_NET, CTR_EXITED, CTR_TRANSFERS, CTR_TIES, CTR_STUCK,
@@ -28,6 +29,11 @@ enum { ERR_RING_OVERFLOW = 0, ERR_CAND_OVERFLOW = 1, ERR_N = 4 };
 struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
+    int32_t g_link, g_node, g_rev;   // lanes per small segment / node / small reverse segment (16, 32 or 64)
+    const int32_t *lk_small, *lk_big;  // links by ring capacity for the link phase (small: cap <= 8 g_link)
+    int32_t lk_n_small, lk_n_big;
+    const int32_t *rv_small, *rv_big;  // same split for the reverse (small: cap <= 8 g_rev)
+    int32_t rv_n_small, rv_n_big;
     int64_t ring_total;
     double dt, theta, rate_bin_s;
 
@@ -41,6 +47,11 @@ struct Dev {
     const double *dist;     // [n_dest x Nn] shortest free-flow time to destination
     const int32_t *agent_didx, *agent_dest, *agent_origin;
     const int32_t *q_off, *q_list;   // origin queues (agent ids in release order)
+    const int32_t *q_dest, *q_didx;  // destination node / table row of each queue entry
+    const int32_t *node_cnt;         // per node: in-degree | out-degree << 8 | origins << 16
+    const int32_t *in_pad, *out_pad; // [Nn x max_in], [Nn x max_out] link ids in CSR order
+    const int2 *org_pad;             // [Nn x max_org] (origin, first queue entry)
+    int32_t max_in, max_out, max_org;
     const int64_t *q_rstep;          // fixed mode: release step of each queue entry
     const uint64_t *seed;            // [S]
 
@@ -57,14 +68,13 @@ struct Dev {
     double *B;                       // token bucket [S*L]
     int64_t *E;                      // cumulative outflow [S*L]
     int32_t *slots, *nheads;         // [S*L]
-    int32_t *head_agent, *head_choice;  // [S*L*maxl]
-    double *head_key;                // [S*L*maxl]
+    int4 *head_rec;                  // [S*L*maxl] (agent, destination, table row, -) of each head
     uint8_t *status;                 // [S*N]
     double *tstar;                   // [S*N] release time (rate mode)
     int32_t *rel_t, *dep_t, *exit_t; // [S*N]
     double *Dacc;                    // [S*O] integrated departures
     int32_t *rel_ptr, *dep_ptr;      // [S*O]
-    int64_t *ctr;                    // [S*CTR_N]
+    int64_t *ctr;                    // [S*kCtrSlots*CTR_N], summed on read
     int32_t *cum;                    // [S*D*nb] cumulative detector counts
     int32_t *err;                    // [ERR_N]
 

@@ -114,150 +114,307 @@ __device__ __forceinline__ double merge_noise(uint64_t seed, int a, int t)
 }
 
 // ---------------------------------------------------------------------------
+// Lane groups: a work item (segment or node) is served by G consecutive
+// lanes of a wavefront (G = 16, 32 or 64), 256/G items per workgroup.  All
+// cross-lane traffic stays inside the group (width-G shuffles, masked
+// ballots); loops that contain shuffles have group-uniform trip counts.
+// ---------------------------------------------------------------------------
+template <int G>
+struct Group {
+    int gl, gbase;
+    __device__ Group() {
+        const int l = threadIdx.x & (kWave - 1);
+        gl = l & (G - 1);
+        gbase = l & ~(G - 1);
+    }
+    // bits of the group's lanes (bit i = lane i of the group) where p holds
+    __device__ __forceinline__ unsigned long long mask(bool p) const {
+        const unsigned long long b = __ballot(p);
+        if (G == 64) return b;
+        return (b >> gbase) & ((1ull << G) - 1ull);
+    }
+    __device__ __forceinline__ int count(bool p) const {
+        const unsigned long long b = __ballot(p);
+        if (G == 64) return __popcll(b);
+        return __popcll((b >> gbase) & ((1ull << G) - 1ull));
+    }
+    template <class T>
+    __device__ __forceinline__ T sum(T v) const {
+        for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+        return v;
+    }
+};
+
+template <int G>
+__device__ __forceinline__ int group_item() { return xcd_tile() * (256 / G) + (int)threadIdx.x / G; }
+
+// Counter increments of one work item: summed over its lane group, then one
+// atomic per non-zero counter into one of kCtrSlots slots (spread by item) so
+// that concurrent items rarely hit the same address.
+template <int G>
+__device__ __forceinline__ void add_counters(Dev &d, const Group<G> &g, int s, int item, int (&inc)[CTR_N])
+{
+#pragma unroll
+    for (int k = 0; k < CTR_N; ++k) inc[k] = g.sum(inc[k]);
+    if (g.gl == 0) {
+        unsigned long long *c = (unsigned long long *)&d.ctr[((int64_t)s * kCtrSlots + (item % kCtrSlots)) * CTR_N];
+#pragma unroll
+        for (int k = 0; k < CTR_N; ++k)
+            if (inc[k]) atomicAdd(c + k, (unsigned long long)inc[k]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Link phase: per (scenario, link) segment, in place on the ring.
 //   Newell car-following with the link cap (Methods eq. newell_model; SI-A),
 //   position form x' = min(x + u dt, max(x, x_lead - dn/kappa)), x_hat =
 //   min(x', L); leader = rank - lanes; arrival (x_hat >= L - 0.01), vacancy
-//   (entry slots = lanes - #(x_hat <= dn/kappa)), token accrual, detector
-//   crossings, order check, and the route choice of the heads.
-// Chunks of 64 ranks are processed back to front so every leader is read
-// before its own update is written (all inputs are time-t positions).
+//   (entry slots = lanes - #(x_hat <= dn/kappa)), token accrual (the previous
+//   step's idle cap min(B, 1) is applied here, before the accrual), detector
+//   crossings, order check; records the heads (agent, destination) for the
+//   node phase.
+// Links are split by ring capacity: small rings (capacity <= 8G) are served
+// by G lanes, the others by a whole wavefront.  A segment is staged into LDS
+// (a piece of up to bufcap ranks plus the leader halo) with all loads in
+// flight at once, then updated from that snapshot: every input is a time-t
+// position, so the update is a pure gather.  Pieces of very long segments
+// go back to front, so a piece never reads ranks an earlier piece wrote.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int tape_k)
+constexpr int kBigLds = 1024;    // LDS floats per wavefront for big segments (link phase)
+
+__device__ __forceinline__ void wave_lds_sync()
 {
-    const int lane = lane_id();
-    const int seg = xcd_tile() * kWavesPerBlock + (threadIdx.x >> 6);
-    if (seg >= d.S * d.L) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ float cf_update(float x, float xl, bool has_leader, float vf, float sp, float Lj)
+{
+    const float xf = x + vf;
+    float xn = xf;
+    if (has_leader) {
+        const float xc = xl - sp;
+        const float cc = (x > xc) ? x : xc;
+        xn = (xf <= cc) ? xf : cc;
+    }
+    return (xn > Lj) ? Lj : xn;
+}
+
+template <int G>
+__device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg, int t, int sample_b, int tape_k,
+                                             float *buf, int bufcap)
+{
+    const int gl = g.gl;
     const int s = seg / d.L, j = seg - s * d.L;
-    const int h0 = d.rhead[seg], n = d.rtail[seg] - h0;
     const int cap = d.cap[j], ln = d.lanes[j];
+    const int h0 = d.rhead[seg], n_raw = d.rtail[seg] - h0;
+    const int n = min(n_raw, cap);   // an overflowing ring (flagged below) is never read past its end
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
     const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j], thr = d.thr[j];
     const int d0 = d.det_off[j], nd = d.det_off[j + 1] - d0;
+    const int hm = h0 % cap;
+    auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
+    // head records (speculatively, lanes below the lane count)
+    int hag = -1, hdst = -1, hdidx = 0;
+    if (gl < ln && gl < n) {
+        hag = d.ring_agent[base + slot_of(gl)];
+        hdst = d.agent_dest[hag];
+        hdidx = d.agent_didx[hag];
+    }
+    double Bv = 0.0, accv = 0.0;
+    int64_t Ev = 0;
+    if (gl == 0) {
+        Bv = d.B[seg];
+        accv = d.acc[seg];
+        if (sample_b >= 0) Ev = d.E[seg];
+    }
     int64_t tb = -1;
     if (tape_k >= 0) {
         tb = (int64_t)tape_k * d.S * d.ring_total + base;
-        if (lane == 0) {
+        if (gl == 0) {
             d.tape_head[(int64_t)tape_k * d.S * d.L + seg] = h0;
             d.tape_tail[(int64_t)tape_k * d.S * d.L + seg] = h0 + n;
         }
     }
-    if (lane == 0 && n > cap) atomicOr(&d.err[ERR_RING_OVERFLOW], 1);
-
-    int nh = 0, nocc = 0, viol = 0;
-    int dcnt[kMaxDetPerLink] = {0, 0, 0, 0};
+    if (gl == 0 && n_raw > cap) atomicOr(&d.err[ERR_RING_OVERFLOW], 1);
     float dpos[kMaxDetPerLink];
-    for (int k = 0; k < kMaxDetPerLink; ++k) dpos[k] = k < nd ? d.det_pos[d.det_list[d0 + k]] : 0.f;
-    float next_first = INFINITY;   // x_hat of rank 64(c+1), the chunk processed before
-    bool have_next = false;
-    for (int c = (n - 1) >> 6; c >= 0; --c) {
-        const int r = (c << 6) + lane;
-        const bool v = r < n;
-        float x = 0.f, xl = 0.f;
-        int slot = 0;
-        if (v) {
-            slot = (h0 + r) % cap;
-            x = d.ring_pos[base + slot];
-            if (r >= ln) xl = d.ring_pos[base + (h0 + r - ln) % cap];
-            if (tb >= 0) {
-                d.tape_pos[tb + slot] = x;
-                d.tape_agent[tb + slot] = d.ring_agent[base + slot];
-            }
-        }
-        const float xf = x + vf;
-        float xn = xf;
-        if (r >= ln) {
-            const float xc = xl - sp;
-            const float cc = (x > xc) ? x : xc;
-            xn = (xf <= cc) ? xf : cc;
-        }
-        const float xh = (xn > Lj) ? Lj : xn;
-        if (v) d.ring_pos[base + slot] = xh;
-        nh += __popcll(__ballot(v && xh >= thr));
-        nocc += __popcll(__ballot(v && xh <= sp));
+    int dcnt[kMaxDetPerLink];
 #pragma unroll
-        for (int k = 0; k < kMaxDetPerLink; ++k)
-            if (k < nd) dcnt[k] += __popcll(__ballot(v && xh >= dpos[k]));
-        // order check (rank r-1 must not be behind rank r)
-        const float up = __shfl_up(xh, 1);
-        bool bad = v && lane > 0 && up < xh;
-        if (v && lane == 63 && have_next && xh < next_first) bad = true;
-        viol += __popcll(__ballot(bad));
-        next_first = __shfl(xh, 0);
-        have_next = true;
+    for (int k = 0; k < kMaxDetPerLink; ++k) {
+        dpos[k] = k < nd ? d.det_pos[d.det_list[d0 + k]] : 0.f;
+        dcnt[k] = 0;
+    }
+    int nh = 0, nocc = 0, viol = 0;
+    const int piece = bufcap - kMaxLanes;
+    for (int hi = n; hi > 0; hi -= piece) {
+        const int lo = max(0, hi - piece);
+        const int slo = max(0, lo - ln);
+        // stage ranks [slo, hi): four loads in flight per lane per round
+        for (int r = slo + gl; r < hi; r += 4 * G) {
+            float v4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rr = r + q * G;
+                v4[q] = rr < hi ? d.ring_pos[base + slot_of(rr)] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (r + q * G < hi) buf[r + q * G - slo] = v4[q];
+        }
+        wave_lds_sync();
+        float prev_last = INFINITY;
+        for (int r0 = lo; r0 < hi; r0 += G) {
+            const int r = r0 + gl;
+            const bool v = r < hi;
+            float x = 0.f, xl = 0.f;
+            if (v) {
+                x = buf[r - slo];
+                if (r >= ln) xl = buf[r - ln - slo];
+            }
+            const float xh = cf_update(x, xl, r >= ln, vf, sp, Lj);
+            if (v) {
+                const int sl = slot_of(r);
+                if (tb >= 0) {
+                    d.tape_pos[tb + sl] = x;
+                    d.tape_agent[tb + sl] = d.ring_agent[base + sl];
+                }
+                d.ring_pos[base + sl] = xh;
+            }
+            nh += g.count(v && xh >= thr);
+            nocc += g.count(v && xh <= sp);
+#pragma unroll
+            for (int k = 0; k < kMaxDetPerLink; ++k)
+                if (k < nd) dcnt[k] += g.count(v && xh >= dpos[k]);
+            float up = __shfl_up(xh, 1, G);
+            if (gl == 0) up = prev_last;
+            viol += g.count(v && r > lo && up < xh);
+            prev_last = __shfl(xh, G - 1, G);
+        }
+        wave_lds_sync();
     }
     const int h = min(nh, min(ln, d.maxl));
-    if (lane == 0) {
-        d.B[seg] += d.acc[seg];
+    if (gl == 0) {
+        d.B[seg] = (Bv > 1.0 ? 1.0 : Bv) + accv;
         d.slots[seg] = max(0, ln - nocc);
         d.nheads[seg] = h;
-        if (viol) atomicAdd((unsigned long long *)&d.ctr[s * CTR_N + CTR_ORDER_VIOL], (unsigned long long)viol);
-        if (sample_b >= 0) {
-            const int64_t E = d.E[seg];
+        if (viol)
+            atomicAdd((unsigned long long *)&d.ctr[((int64_t)s * kCtrSlots) * CTR_N + CTR_ORDER_VIOL],
+                      (unsigned long long)viol);
+        if (sample_b >= 0)
             for (int k = 0; k < nd; ++k)
-                d.cum[((int64_t)s * d.D + d.det_list[d0 + k]) * d.nb + sample_b] = (int32_t)(E + dcnt[k]);
-        }
+                d.cum[((int64_t)s * d.D + d.det_list[d0 + k]) * d.nb + sample_b] = (int32_t)(Ev + dcnt[k]);
     }
-    // heads: route choice and merge key
-    int ties = 0;
-    if (lane < h) {
-        const int a = d.ring_agent[base + (h0 + lane) % cap];
-        const int vnode = d.head[j];
-        int ch;
-        if (d.agent_dest[a] == vnode) ch = CH_EXIT;
-        else ch = choose_link(d, s, a, vnode, j, t, &ties);
-        const int64_t hi = (int64_t)seg * d.maxl + lane;
-        d.head_agent[hi] = a;
-        d.head_choice[hi] = ch;
-        d.head_key[hi] = (double)d.alpha[seg] + merge_noise(d.seed[s], a, t);
+    if (gl < h) d.head_rec[(int64_t)seg * d.maxl + gl] = make_int4(hag, hdst, hdidx, 0);
+}
+
+// blocks [0, small_blocks): G lanes per small segment; the rest: one wavefront per big segment
+template <int G>
+__global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int tape_k)
+{
+    __shared__ float lds[4 * kBigLds];
+    constexpr int per = 256 / G;
+    constexpr int sbuf = 8 * G + kMaxLanes;
+    static_assert(per * sbuf <= 4 * kBigLds, "small-segment staging exceeds LDS");
+    const int small_items = d.S * d.lk_n_small;
+    const int small_blocks = (small_items + per - 1) / per;
+    if ((int)blockIdx.x < small_blocks) {
+        const Group<G> g;
+        const int item = blockIdx.x * per + (int)threadIdx.x / G;
+        if (item >= small_items) return;
+        const int s = item / d.lk_n_small;
+        const int seg = s * d.L + d.lk_small[item - s * d.lk_n_small];
+        link_segment<G>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
+    } else {
+        const Group<64> g;
+        const int item = ((int)blockIdx.x - small_blocks) * 4 + (int)threadIdx.x / 64;
+        if (item >= d.S * d.lk_n_big) return;
+        const int s = item / d.lk_n_big;
+        const int seg = s * d.L + d.lk_big[item - s * d.lk_n_big];
+        link_segment<64>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / 64) * kBigLds, kBigLds);
     }
-    if (ties) atomicAdd((unsigned long long *)&d.ctr[s * CTR_N + CTR_TIES], (unsigned long long)ties);
 }
 
 // ---------------------------------------------------------------------------
-// Node phase: per (scenario, node), one wavefront.
-//   Releases into the node's origin queues, the origin fronts' route choice,
-//   merge choice per out-link (top-k by alpha_from + Gumbel, k = entry slots;
-//   SI-B merge choice), FIFO resolve of each in-link's heads against its
-//   token bucket, and the grafted transfer: leavers pop from the in-link
-//   ring, entrants push at position 0 onto the out-link ring (SI-B eq.
-//   transfer; the graft itself lives in the adjoint).
+// Node phase: per (scenario, node), one lane group (G >= candidates).
+//   Releases into the node's origin queues; route choice of every candidate
+//   (heads of the in-links and origin fronts; SI-B link choice: utility
+//   beta/c - theta*(t_ff + shortest time from the link's head), hard choice
+//   argmax(V + Gumbel), ties to the lower candidate index; a head whose link
+//   ends at its destination leaves the network); merge per out-link (top-k
+//   by alpha_from + Gumbel, k = entry slots; SI-B merge choice); FIFO resolve
+//   of each in-link's heads against its token bucket; grafted transfer:
+//   leavers pop from the in-link ring, entrants push at position 0 onto the
+//   out-link ring (SI-B eq. transfer; the graft itself lives in the adjoint).
 // Candidate lanes: in-link q, head rank r -> lane q*maxl + r; then origins.
-// All cross-lane traffic goes through readlane/shuffles.
+// Out-link lanes k < out-degree hold the out-link's data, broadcast to the
+// candidates by shuffles; four shortest-time lookups are in flight at once.
+// Per-node link lists are padded node-major tables, so every lane finds its
+// link in the first load.
 // ---------------------------------------------------------------------------
+template <int G>
 __global__ __launch_bounds__(256) void k_node(Dev d, int t)
 {
-    const int lane = lane_id();
-    const int wid = xcd_tile() * kWavesPerBlock + (threadIdx.x >> 6);
-    if (wid >= d.S * d.Nn) return;
-    const int s = wid / d.Nn, v = wid - s * d.Nn;
+    const Group<G> g;
+    const int item = group_item<G>();
+    if (item >= d.S * d.Nn) return;
+    const int gl = g.gl;
+    const int s = item / d.Nn, v = item - s * d.Nn;
     const int maxl = d.maxl;
-    const int i0 = d.in_off[v], deg = d.in_off[v + 1] - i0;
-    const int o0 = d.org_off[v], norg = d.org_off[v + 1] - o0;
+    const int cnt = d.node_cnt[v];
+    const int deg = cnt & 0xff, dego = (cnt >> 8) & 0xff, norg = (cnt >> 16) & 0xff;
     const int nc = deg * maxl + norg;
-    const int oo = d.out_off[v], dego = d.out_off[v + 1] - oo;
-    const uint64_t seed = d.seed[s];
-    int ties = 0;
+    const int64_t sL = (int64_t)s * d.L;
+    int inc[CTR_N];
+#pragma unroll
+    for (int k = 0; k < CTR_N; ++k) inc[k] = 0;
 
+    // first-level loads issued together (padded tables need no offsets)
+    const int om_raw = d.out_pad[(int64_t)v * d.max_out + min(gl, d.max_out - 1)];
+    const int qi = (gl < deg * maxl) ? gl / maxl : 0;
+    const int jin_cand = d.in_pad[(int64_t)v * d.max_in + min(qi, d.max_in - 1)];
+    const int jin_res = d.in_pad[(int64_t)v * d.max_in + min(gl, d.max_in - 1)];
+    // ---- out-link lanes ----
+    int om = -1, ohead = -1, oslots = 0, otail = 0, obase = 0, ocap = 1;
+    double outil = 0.0, otff = 0.0;
+    if (gl < dego) {
+        om = om_raw;
+        ohead = d.head[om];
+        otff = d.tff[om];
+        outil = d.util[sL + om];
+        oslots = d.slots[sL + om];
+        otail = d.rtail[sL + om];
+        obase = d.ring_base[om];
+        ocap = d.cap[om];
+    }
+    // ---- in-link lanes (resolve) ----
+    int64_t sjq = -1;
+    double Bj = 0.0;
+    int nhq = 0;
+    if (gl < deg) {
+        sjq = sL + jin_res;
+        Bj = d.B[sjq];
+        nhq = d.nheads[sjq];
+    }
     // ---- candidate of this lane ----
-    int ch = CH_NONE, ag = -1;
-    double key = 0.0;
-    int origin = -1;
-    if (lane < deg * maxl) {
-        const int q = lane / maxl, r = lane - q * maxl;
-        const int sj = s * d.L + d.in_lnk[i0 + q];
-        if (r < d.nheads[sj]) {
-            const int64_t hi = (int64_t)sj * maxl + r;
-            ag = d.head_agent[hi];
-            ch = d.head_choice[hi];
-            key = d.head_key[hi];
-        }
-    } else if (lane < nc) {
-        origin = d.org_list[o0 + lane - deg * maxl];
+    int ag = -1, dst = -1, didx = 0, origin = -1, from = -1, ftail = -1;
+    double alpha = 1.0;
+    if (gl < deg * maxl) {
+        const int r = gl - qi * maxl;
+        const int jj = jin_cand;
+        const int64_t sj = sL + jj;
+        const int nh = d.nheads[sj];
+        const int4 hr = d.head_rec[sj * maxl + r];
+        const float al = d.alpha[sj];
+        const int tl = d.tail[jj];
+        if (r < nh) { ag = hr.x; dst = hr.y; didx = hr.z; from = jj; alpha = (double)al; ftail = tl; }
+    } else if (gl < nc) {
+        const int2 oq = d.org_pad[(int64_t)v * d.max_org + (gl - deg * maxl)];
+        origin = oq.x;
+        const int qb = oq.y, qn = d.q_off[origin + 1] - qb;
         const int so = s * d.O + origin;
-        const int qb = d.q_off[origin], qn = d.q_off[origin + 1] - qb;
-        // release (serial per origin; a handful of agents per step)
-        int rel = d.rel_ptr[so], newrel = rel;
+        const int rel = d.rel_ptr[so];
+        int newrel = rel;
         if (d.fixed_mode) {
             while (newrel < qn && d.q_rstep[qb + newrel] <= (int64_t)t) {
                 const int a = d.q_list[qb + newrel];
@@ -266,142 +423,165 @@ __global__ __launch_bounds__(256) void k_node(Dev d, int t)
                 ++newrel;
             }
         } else {
-            double inc = 0.0;
+            double incr = 0.0;
             const double t0 = t * d.dt, t1 = (t + 1) * d.dt;
             for (int b = 0; b < d.n_rate_bins; ++b) {
                 const double lo = fmax(b * d.rate_bin_s, t0), hi = fmin((b + 1) * d.rate_bin_s, t1);
-                if (hi > lo) inc += (double)d.rates[((int64_t)s * d.O + origin) * d.n_rate_bins + b] * (hi - lo);
+                if (hi > lo) incr += (double)d.rates[((int64_t)s * d.O + origin) * d.n_rate_bins + b] * (hi - lo);
             }
-            const double D = d.Dacc[so] + inc;
-            d.Dacc[so] = D;
-            const double r = inc / d.dt;
+            const double D = d.Dacc[so] + incr;
+            if (incr != 0.0) d.Dacc[so] = D;
+            const double rr = incr / d.dt;
             while (newrel < qn && (double)(newrel + 1) <= D) {
                 const int a = d.q_list[qb + newrel];
                 const int64_t ga = (int64_t)s * d.N + a;
                 d.status[ga] = AG_QUEUED;
-                d.tstar[ga] = t1 - (D - (double)(newrel + 1)) / r;
+                d.tstar[ga] = t1 - (D - (double)(newrel + 1)) / rr;
                 d.rel_t[ga] = t;
                 ++newrel;
             }
         }
-        if (newrel != rel) {
-            d.rel_ptr[so] = newrel;
-            atomicAdd((unsigned long long *)&d.ctr[s * CTR_N + CTR_RELEASED], (unsigned long long)(newrel - rel));
-        }
+        if (newrel != rel) d.rel_ptr[so] = newrel;
+        inc[CTR_RELEASED] += newrel - rel;
         const int dp = d.dep_ptr[so];
-        if (dp < newrel) {
-            ag = d.q_list[qb + dp];
-            ch = choose_link(d, s, ag, v, -1, t, &ties);
-            key = 1.0 + merge_noise(seed, ag, t);
+        if (dp < newrel) { ag = d.q_list[qb + dp]; dst = d.q_dest[qb + dp]; didx = d.q_didx[qb + dp]; }
+    }
+    if (g.count(ag >= 0) == 0) {   // nothing to move at this node this step
+        add_counters<G>(d, g, s, item, inc);
+        return;
+    }
+    const uint64_t seed = d.seed[s];
+
+    // ---- route choice (group-uniform loop over out-link blocks of 4) ----
+    const bool exiting = ag >= 0 && from >= 0 && dst == v;
+    const bool chooser = ag >= 0 && !exiting;
+    const double *dist = d.dist + (int64_t)didx * d.Nn;
+    double best = -INFINITY, second = -INFINITY;
+    int arg = CH_STUCK;
+    for (int b0 = 0; b0 < dego; b0 += 4) {
+        int hk[4], mk[4];
+        double tk[4], uk[4], dm[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int src = min(b0 + q, G - 1);
+            hk[q] = __shfl(ohead, src, G);
+            mk[q] = __shfl(om, src, G);
+            tk[q] = __shfl(otff, src, G);
+            uk[q] = __shfl(outil, src, G);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dm[q] = (chooser && b0 + q < dego) ? dist[hk[q]] : INFINITY;
+        if (chooser) {
+            uint32_t w[4];
+            draw4(seed, ag, t, 0, b0 >> 2, w);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (b0 + q >= dego) continue;
+                if (!d.allow_uturn && from >= 0 && hk[q] == ftail) continue;
+                if (!(dm[q] < INFINITY)) continue;
+                const double V = uk[q] - d.theta * (tk[q] + dm[q]);
+                const double sc = V + gumbel_of(w[q]);
+                if (sc > best) { second = best; best = sc; arg = mk[q]; }
+                else if (sc > second) second = sc;
+            }
         }
     }
-    if (nc > kWave) { if (lane == 0) atomicOr(&d.err[ERR_CAND_OVERFLOW], 1); return; }
+    int ch = CH_NONE;
+    if (chooser) {
+        ch = arg;
+        if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) inc[CTR_TIES] += 1;
+    } else if (exiting) {
+        ch = CH_EXIT;
+    }
+    double key = 0.0;
+    if (ag >= 0) key = alpha + merge_noise(seed, ag, t);
 
     // ---- merge: rank among candidates wanting the same link ----
-    int rank = 0, next_gap_tie = 0;
-    for (int src = 0; src < nc; ++src) {
-        const int c2 = readlane_i(ch, src);
-        const double k2 = readlane_d(key, src);
-        const int a2 = readlane_i(ag, src);
-        if (ch >= 0 && c2 == ch && src != lane) {
+    // the loops below visit only lanes that hold a candidate (group-uniform mask)
+    const unsigned long long cmask = g.mask(ag >= 0);
+    int rank = 0, close = 0;
+    for (unsigned long long mm = cmask; mm; mm &= mm - 1) {
+        const int src = __ffsll((long long)mm) - 1;
+        const int c2 = __shfl(ch, src, G);
+        const double k2 = __shfl(key, src, G);
+        const int a2 = __shfl(ag, src, G);
+        if (ch >= 0 && c2 == ch && src != gl) {
             if (k2 > key || (k2 == key && a2 < ag)) ++rank;
-            else if (key - k2 < 1e-12 * (1.0 + fabs(key))) next_gap_tie = 1;
+            else if (key - k2 < 1e-12 * (1.0 + fabs(key))) close = 1;
         }
     }
-    int won = 0;
-    if (ch >= 0) won = rank < d.slots[s * d.L + ch];
-    // one near-tie per candidate that has a close successor (as the oracle counts adjacent pairs)
-    ties += (ch >= 0) ? next_gap_tie : 0;
+    int sl = 0;
+    for (int k = 0; k < dego; ++k) {
+        const int mk = __shfl(om, k, G), sk = __shfl(oslots, k, G);
+        if (mk == ch) sl = sk;
+    }
+    const int won = (ch >= 0) && rank < sl;
+    if (ch >= 0) inc[CTR_TIES] += close;
 
     // ---- resolve: lane q < deg walks in-link q's heads in rank order ----
-    int np = 0, stuck = 0;
-    double Bj = 0.0;
-    int sjq = -1, nhq = 0;
-    if (lane < deg) {
-        sjq = s * d.L + d.in_lnk[i0 + lane];
-        Bj = d.B[sjq];
-        nhq = d.nheads[sjq];
-    }
-    bool stop = false;
+    int np = 0;
+    bool stop = false, consumed = false;
     for (int r = 0; r < maxl; ++r) {
-        const int src = min(lane * maxl + r, kWave - 1);
-        const int c2 = __shfl(ch, src);
-        const int w2 = __shfl(won, src);
-        if (lane < deg && !stop && r < nhq) {
+        const int src = min(gl * maxl + r, G - 1);
+        const int c2 = __shfl(ch, src, G);
+        const int w2 = __shfl(won, src, G);
+        if (gl < deg && !stop && r < nhq) {
             if (c2 == CH_EXIT) ++np;
-            else if (c2 >= 0 && w2 && Bj >= 1.0) { Bj -= 1.0; ++np; }
-            else { stop = true; if (c2 == CH_STUCK) ++stuck; }
+            else if (c2 >= 0 && w2 && Bj >= 1.0) { Bj -= 1.0; ++np; consumed = true; }
+            else { stop = true; if (c2 == CH_STUCK) inc[CTR_STUCK] += 1; }
         }
     }
-    if (lane < deg) {
-        d.B[sjq] = Bj > 1.0 ? 1.0 : Bj;
+    if (gl < deg) {
+        if (consumed) d.B[sjq] = Bj;   // the idle cap min(B, 1) is applied at the next accrual
         if (np) {
             d.E[sjq] += np;
             d.rhead[sjq] += np;
         }
     }
-    // did this lane's candidate pass?  (shuffles stay in uniform control flow)
-    const int q_of_lane = (lane < deg * maxl) ? lane / maxl : 0;
-    const int np_q = __shfl(np, q_of_lane);
+    const int q_of_lane = (gl < deg * maxl) ? gl / maxl : 0;
+    const int np_q = __shfl(np, q_of_lane, G);
     int passed = 0;
-    if (lane < deg * maxl) passed = (ag >= 0) && (lane - q_of_lane * maxl) < np_q;
+    if (gl < deg * maxl) passed = (ag >= 0) && (gl - q_of_lane * maxl) < np_q;
     else passed = (origin >= 0 && ag >= 0 && won);
 
-    // ---- out-links: count entrants, advance ring tails ----
-    const int my_m = (lane < dego) ? d.out_lnk[oo + lane] : -100;
-    int tail_old = 0, nent = 0;
-    if (lane < dego) tail_old = d.rtail[s * d.L + my_m];
-    for (int src = 0; src < nc; ++src) {
-        const int c2 = readlane_i(ch, src);
-        const int p2 = readlane_i(passed, src);
-        nent += (p2 && c2 == my_m);
+    // ---- entrants per out-link (lanes < dego) and each entrant's place in key order ----
+    int nent = 0, erank = 0;
+    for (unsigned long long mm = g.mask(passed != 0); mm; mm &= mm - 1) {
+        const int src = __ffsll((long long)mm) - 1;
+        const int c2 = __shfl(ch, src, G);
+        const int p2 = 1;
+        const double k2 = __shfl(key, src, G);
+        const int a2 = __shfl(ag, src, G);
+        nent += (p2 && c2 == om && om >= 0);
+        if (passed && ch >= 0 && p2 && c2 == ch && src != gl && (k2 > key || (k2 == key && a2 < ag))) ++erank;
     }
-    if (lane < dego && nent) d.rtail[s * d.L + my_m] = tail_old + nent;
-    // ---- entrants: position in key order among passed winners of the link ----
-    int erank = 0;
-    for (int src = 0; src < nc; ++src) {
-        const int c2 = readlane_i(ch, src);
-        const int p2 = readlane_i(passed, src);
-        const double k2 = readlane_d(key, src);
-        const int a2 = readlane_i(ag, src);
-        if (passed && ch >= 0 && p2 && c2 == ch && src != lane && (k2 > key || (k2 == key && a2 < ag))) ++erank;
+    if (gl < dego && nent) d.rtail[sL + om] = otail + nent;
+    int tbase = 0, rbase = 0, rcap = 1;
+    for (int k = 0; k < dego; ++k) {
+        const int mk = __shfl(om, k, G), tk = __shfl(otail, k, G), bk = __shfl(obase, k, G), ck = __shfl(ocap, k, G);
+        if (mk == ch) { tbase = tk; rbase = bk; rcap = ck; }
     }
-    int oidx = 0;
-    if (passed && ch >= 0)
-        for (int k = 0; k < dego; ++k)
-            if (d.out_lnk[oo + k] == ch) { oidx = k; break; }
-    const int tbase = __shfl(tail_old, oidx);
     const int64_t ga = (int64_t)s * d.N + (ag >= 0 ? ag : 0);
     if (passed) {
         if (ch >= 0) {
-            const int capm = d.cap[ch];
-            const int64_t slot = (int64_t)s * d.ring_total + d.ring_base[ch] + (tbase + erank) % capm;
+            const int64_t slot = (int64_t)s * d.ring_total + rbase + (tbase + erank) % rcap;
             d.ring_agent[slot] = ag;
             d.ring_pos[slot] = 0.f;
             if (origin >= 0) {
                 d.status[ga] = AG_ON;
                 d.dep_t[ga] = t;
                 d.dep_ptr[s * d.O + origin] += 1;
+                inc[CTR_DEPARTED] += 1;
+            } else {
+                inc[CTR_TRANSFERS] += 1;
             }
         } else {
             d.status[ga] = AG_EXITED;
             d.exit_t[ga] = t;
+            inc[CTR_EXITED] += 1;
         }
     }
-    // counters
-    const int n_dep = __popcll(__ballot(passed && origin >= 0));
-    const int n_exit = __popcll(__ballot(passed && ch == CH_EXIT));
-    const int n_tr = __popcll(__ballot(passed && ch >= 0 && origin < 0));
-    int tot_ties = ties, tot_stuck = stuck;
-    for (int o = 32; o > 0; o >>= 1) { tot_ties += __shfl_xor(tot_ties, o); tot_stuck += __shfl_xor(tot_stuck, o); }
-    if (lane == 0) {
-        unsigned long long *c = (unsigned long long *)&d.ctr[s * CTR_N];
-        if (n_dep) atomicAdd(c + CTR_DEPARTED, (unsigned long long)n_dep);
-        if (n_exit) atomicAdd(c + CTR_EXITED, (unsigned long long)n_exit);
-        if (n_tr) atomicAdd(c + CTR_TRANSFERS, (unsigned long long)n_tr);
-        if (tot_ties) atomicAdd(c + CTR_TIES, (unsigned long long)tot_ties);
-        if (tot_stuck) atomicAdd(c + CTR_STUCK, (unsigned long long)tot_stuck);
-    }
+    add_counters<G>(d, g, s, item, inc);
 }
 
 // Tape entry without an update (the state at the end of a replay window).
@@ -437,20 +617,27 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
 //   exit: total travel time falls by (x_hat - sg x_hat)/u of the last link;
 //   free: x' = x + u dt; congested: x' = x_lead - dn/kappa; stopped: x' = x.
 // Each agent has at most one follower (rank + lanes), so the leader term is
-// a gather: chunks go front to back so followers are read before they are
-// overwritten.  init = 1: adj = dL/dx(T) at the final state (no step).
+// a gather.  A piece of ranks [lo, hi) is staged in LDS with its leader and
+// follower halos (taped positions, agent ids, then the time-t+1 adjoints of
+// [lo, hi + lanes)); all reads of a piece finish before its writes, and
+// pieces go front to back, so no piece reads an adjoint another one wrote.
+// (Followers never leave in the step: only heads, rank < lanes, do.)
+// init = 1: adj = dL/dx(T) at the final state (no step).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int init)
+constexpr int kRevSmall = 8;        // small segments: capacity <= kRevSmall * G
+constexpr int kRevBigLds = 1728;    // LDS words per wavefront for big segments (three arrays)
+
+template <int G>
+__device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
+                                                float *buf, int bufcap)
 {
-    const int lane = lane_id();
-    const int seg = xcd_tile() * kWavesPerBlock + (threadIdx.x >> 6);
-    if (seg >= d.S * d.L) return;
+    const int gl = g.gl;
     const int s = seg / d.L, j = seg - s * d.L;
     const int64_t SL = (int64_t)d.S * d.L;
-    const int hk = d.tape_head[tape_k * SL + seg];
-    const int n = d.tape_tail[tape_k * SL + seg] - hk;
-    const int npass = init ? 0 : d.tape_head[(tape_k + 1) * SL + seg] - hk;
     const int cap = d.cap[j], ln = d.lanes[j], vhead = d.head[j];
+    const int hk = d.tape_head[tape_k * SL + seg];
+    const int n = min(d.tape_tail[tape_k * SL + seg] - hk, cap);
+    const int npass = init ? 0 : d.tape_head[(tape_k + 1) * SL + seg] - hk;
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
     const int64_t tb = (int64_t)tape_k * d.S * d.ring_total + base;
     const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j];
@@ -459,71 +646,132 @@ __global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int i
     const double gTs = d.gT ? d.gT[s] : 0.0;
     const float exit_adj = (float)(-gTs / (double)uj);
     const int64_t sN = (int64_t)s * d.N;
-    // counts sampled at time t
+    const int hm = hk % cap;
+    auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     int sb = -1;
     if (d.gQ && d.cbs > 0 && t > 0 && t % d.cbs == 0 && t / d.cbs <= d.nb) sb = t / d.cbs - 1;
     const int d0 = d.det_off[j], nd = d.det_off[j + 1] - d0;
     const float sc = 5.0f / Lj;
+    float gC[kMaxDetPerLink], dpos[kMaxDetPerLink];
+#pragma unroll
+    for (int k = 0; k < kMaxDetPerLink; ++k) {
+        gC[k] = 0.f;
+        dpos[k] = 0.f;
+        if (sb >= 0 && k < nd) {
+            const int det = d.det_list[d0 + k];
+            const int64_t qi = ((int64_t)s * d.D + det) * d.nb;
+            gC[k] = d.gQ[qi + sb] - (sb + 1 < d.nb ? d.gQ[qi + sb + 1] : 0.f);
+            dpos[k] = d.det_pos[det];
+        }
+    }
+    const int P = bufcap / 3;
+    float *xb = buf;
+    int *ab = reinterpret_cast<int *>(buf + P);
+    float *pb = buf + 2 * P;
+    const int piece = P - 2 * kMaxLanes;
     double gu = 0.0, gk = 0.0;
-    for (int c = 0; (c << 6) < n; ++c) {
-        const int r = (c << 6) + lane;
-        const bool v = r < n;
-        float x = 0.f;
-        int a = 0;
-        if (v) {
-            const int slot = (hk + r) % cap;
-            x = d.tape_pos[tb + slot];
-            a = d.tape_agent[tb + slot];
-        }
-        float anew = 0.f;
-        if (!init) {
-            // own branch
-            int br = 0;  // 0 free, 1 congested, 2 stopped
-            if (v && r >= ln) {
-                const float xl = d.tape_pos[tb + (hk + r - ln) % cap];
-                const float xf = x + vf, xc = xl - sp;
-                const float cc = (x > xc) ? x : xc;
-                br = (xf <= cc) ? 0 : ((x > xc) ? 2 : 1);
+    for (int lo = 0; lo < n; lo += piece) {
+        const int hi = min(n, lo + piece);
+        const int slo = max(0, lo - ln), shi = min(n, hi + ln);
+        // taped positions and agents of [slo, shi)
+        for (int r = slo + gl; r < shi; r += 2 * G) {
+            float x2[2];
+            int a2[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int rr = r + q * G;
+                x2[q] = 0.f; a2[q] = 0;
+                if (rr < shi) { const int sl = slot_of(rr); x2[q] = d.tape_pos[tb + sl]; a2[q] = d.tape_agent[tb + sl]; }
             }
-            float ap = 0.f;
-            if (v) ap = (r < npass && d.agent_dest[a] == vhead) ? exit_adj : d.adj[sN + a];
-            // follower (rank r + lanes) in the congested branch passes its adjoint to us
-            float af = 0.f;
-            const int fr = r + ln;
-            if (v && fr < n) {
-                const int fs = (hk + fr) % cap;
-                const float xfol = d.tape_pos[tb + fs];
-                const float ff = xfol + vf, xc = x - sp;
-                const float cc = (xfol > xc) ? xfol : xc;
-                const bool cong = !(ff <= cc) && !(xfol > xc);
-                if (cong) af = d.adj[sN + d.tape_agent[tb + fs]];
-            }
-            anew = (br != 1 ? ap : 0.f) + af;
-            if (v && br == 0) gu += d.dt * (double)ap;
-            if (v && br == 1) gk += dkap * (double)ap;
-        } else if (v && d.gx) {
-            anew = d.gx[sN + a];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (r + q * G < shi) { xb[r + q * G - slo] = x2[q]; ab[r + q * G - slo] = a2[q]; }
         }
-        if (sb >= 0 && v) {
-            for (int k = 0; k < nd; ++k) {
-                const int det = d.det_list[d0 + k];
-                const int64_t qi = ((int64_t)s * d.D + det) * d.nb;
-                const float gC = d.gQ[qi + sb] - (sb + 1 < d.nb ? d.gQ[qi + sb + 1] : 0.f);
-                const float z = sc * (x - d.det_pos[det]);
-                const float sg = 1.0f / (1.0f + expf(-z));
-                anew += gC * sc * sg * (1.0f - sg);
-            }
+        wave_lds_sync();
+        // time-t+1 adjoints of the x_hat of [lo, shi)
+        for (int r = lo + gl; r < shi; r += G) {
+            const int a = ab[r - slo];
+            float ap;
+            if (init) ap = d.gx ? d.gx[sN + a] : 0.f;
+            else ap = (r < npass && d.agent_dest[a] == vhead) ? exit_adj : d.adj[sN + a];
+            pb[r - slo] = ap;
         }
-        if (v) {
+        wave_lds_sync();
+        for (int r0 = lo; r0 < hi; r0 += G) {
+            const int r = r0 + gl;
+            const bool v = r < hi;
+            if (!v) continue;
+            const float x = xb[r - slo];
+            const float ap = pb[r - slo];
+            float anew;
+            if (!init) {
+                int br = 0;  // 0 free, 1 congested, 2 stopped
+                if (r >= ln) {
+                    const float xl = xb[r - ln - slo];
+                    const float xf = x + vf, xc = xl - sp;
+                    const float cc = (x > xc) ? x : xc;
+                    br = (xf <= cc) ? 0 : ((x > xc) ? 2 : 1);
+                }
+                float af = 0.f;
+                const int fr = r + ln;
+                if (fr < n) {
+                    const float xfol = xb[fr - slo];
+                    const float ff = xfol + vf, xc = x - sp;
+                    const float cc = (xfol > xc) ? xfol : xc;
+                    if (!(ff <= cc) && !(xfol > xc)) af = pb[fr - slo];
+                }
+                anew = (br != 1 ? ap : 0.f) + af;
+                if (br == 0) gu += d.dt * (double)ap;
+                if (br == 1) gk += dkap * (double)ap;
+            } else {
+                anew = ap;
+            }
+            if (sb >= 0) {
+#pragma unroll
+                for (int k = 0; k < kMaxDetPerLink; ++k) {
+                    if (k >= nd) break;
+                    const float z = sc * (x - dpos[k]);
+                    const float sg = 1.0f / (1.0f + expf(-z));
+                    anew += gC[k] * sc * sg * (1.0f - sg);
+                }
+            }
+            const int a = ab[r - slo];
             d.adj[sN + a] = anew;
             if (d.dep_t[sN + a] == t - 1) d.depg[sN + a] = anew * uj;
         }
+        wave_lds_sync();
     }
-    gu = wave_sum_d(gu);
-    gk = wave_sum_d(gk);
-    if (lane == 0 && !init) {
+    gu = g.sum(gu);
+    gk = g.sum(gk);
+    if (gl == 0 && !init) {
         d.gu[seg] += gu;
         d.gk[seg] += gk;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int init)
+{
+    __shared__ float lds[4 * kRevBigLds];
+    constexpr int per = 256 / G;
+    constexpr int sbuf = 3 * (kRevSmall * G + 2 * kMaxLanes);
+    static_assert(per * sbuf <= 4 * kRevBigLds, "small-segment staging exceeds LDS");
+    const int small_items = d.S * d.rv_n_small;
+    const int small_blocks = (small_items + per - 1) / per;
+    if ((int)blockIdx.x < small_blocks) {
+        const Group<G> g;
+        const int item = blockIdx.x * per + (int)threadIdx.x / G;
+        if (item >= small_items) return;
+        const int s = item / d.rv_n_small;
+        const int seg = s * d.L + d.rv_small[item - s * d.rv_n_small];
+        reverse_segment<G>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
+    } else {
+        const Group<64> g;
+        const int item = ((int)blockIdx.x - small_blocks) * 4 + (int)threadIdx.x / 64;
+        if (item >= d.S * d.rv_n_big) return;
+        const int s = item / d.rv_n_big;
+        const int seg = s * d.L + d.rv_big[item - s * d.rv_n_big];
+        reverse_segment<64>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / 64) * kRevBigLds, kRevBigLds);
     }
 }
 
@@ -748,14 +996,30 @@ int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const
 // launchers
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int64_t waves) { return (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock); }
+static inline int blocks_for(int64_t items, int G) { const int per = 256 / G; return (int)((items + per - 1) / per); }
+
+static inline int class_blocks(int S, int n_small, int n_big, int G)
+{
+    const int per = 256 / G;
+    return (S * n_small + per - 1) / per + (S * n_big + 3) / 4;
+}
 
 void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_link, dim3(blocks_for((int64_t)d.S * d.L)), dim3(256), 0, st, d, t, sample_b, tape_k);
+    switch (d.g_link) {
+    case 16: hipLaunchKernelGGL(k_link<16>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 16)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
+    case 32: hipLaunchKernelGGL(k_link<32>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 32)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
+    default: hipLaunchKernelGGL(k_link<64>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 64)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
+    }
 }
 void launch_node(const Dev &d, int t, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_node, dim3(blocks_for((int64_t)d.S * d.Nn)), dim3(256), 0, st, d, t);
+    const int64_t items = (int64_t)d.S * d.Nn;
+    switch (d.g_node) {
+    case 16: hipLaunchKernelGGL(k_node<16>, dim3(blocks_for(items, 16)), dim3(256), 0, st, d, t); break;
+    case 32: hipLaunchKernelGGL(k_node<32>, dim3(blocks_for(items, 32)), dim3(256), 0, st, d, t); break;
+    default: hipLaunchKernelGGL(k_node<64>, dim3(blocks_for(items, 64)), dim3(256), 0, st, d, t); break;
+    }
 }
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 {
@@ -763,7 +1027,11 @@ void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 }
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reverse, dim3(blocks_for((int64_t)d.S * d.L)), dim3(256), 0, st, d, t, tape_k, init);
+    switch (d.g_rev) {
+    case 16: hipLaunchKernelGGL(k_reverse<16>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 16)), dim3(256), 0, st, d, t, tape_k, init); break;
+    case 32: hipLaunchKernelGGL(k_reverse<32>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 32)), dim3(256), 0, st, d, t, tape_k, init); break;
+    default: hipLaunchKernelGGL(k_reverse<64>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 64)), dim3(256), 0, st, d, t, tape_k, init); break;
+    }
 }
 void launch_rate_grad(const Dev &d, float *g, hipStream_t st)
 {

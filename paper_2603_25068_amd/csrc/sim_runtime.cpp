@@ -69,6 +69,9 @@ struct sim_t {
     bool fixed_mode = true;
     double dt = 1.0, rate_bin_s = 0.0;
     int32_t platoon = 1, ckpt_every = 60, max_steps = 0, record = 0;
+    int32_t g_link = 16, g_node = 64, g_rev = 16;   // lanes per work item
+    int32_t *lk_small_dev = nullptr, *lk_big_dev = nullptr, *rv_small_dev = nullptr, *rv_big_dev = nullptr;
+    size_t lk_small_cap = 0, lk_big_cap = 0, rv_small_cap = 0, rv_big_cap = 0;
     std::vector<int32_t> tail, head, lanes, origin_node, det_link, agent_origin, agent_dest;
     std::vector<float> length, free_speed, jam_density, capacity, beta, alpha, cost, det_pos, ready, rates;
     std::vector<uint64_t> seeds;
@@ -78,6 +81,7 @@ struct sim_t {
     std::vector<int32_t> dest_nodes, agent_didx;
     std::vector<double> dist, tff;
     std::vector<int32_t> q_off, q_list;  // full queues (as built at create)
+    std::vector<int32_t> q_dest, q_didx;
     std::vector<int64_t> q_rstep;
     std::vector<float> min_spacing;      // jam spacing the rings were sized for
     int64_t ring_total = 0;
@@ -90,8 +94,11 @@ struct sim_t {
     float *vfree = nullptr, *spacing = nullptr;
     double *util = nullptr, *acc = nullptr;
     // mutable queue buffers
-    int32_t *q_off_dev = nullptr, *q_list_dev = nullptr;
+    int32_t *q_off_dev = nullptr, *q_list_dev = nullptr, *q_dest_dev = nullptr, *q_didx_dev = nullptr;
     int64_t *q_rstep_dev = nullptr;
+    int2 *org_pad_dev = nullptr;
+    std::vector<int32_t> node_cnt, in_pad, out_pad;
+    int32_t max_in = 1, max_out = 1, max_org = 1;
     // adjoint buffers
     float *gQ_dev = nullptr, *gx_dev = nullptr;
     double *gT_dev = nullptr, *ttt_dev = nullptr;
@@ -252,11 +259,16 @@ void build_queues(sim_t *h, const std::vector<uint8_t> *skip)
         }
         per[h->agent_origin[i]].push_back({rs, i});
     }
+    h->q_dest.assign(h->q_off[O], 0);
+    h->q_didx.assign(h->q_off[O], 0);
     for (int k = 0; k < O; ++k) {
         std::sort(per[k].begin(), per[k].end());
         for (size_t a = 0; a < per[k].size(); ++a) {
-            h->q_list[h->q_off[k] + a] = per[k][a].second;
+            const int32_t i = per[k][a].second;
+            h->q_list[h->q_off[k] + a] = i;
             h->q_rstep[h->q_off[k] + a] = per[k][a].first;
+            h->q_dest[h->q_off[k] + a] = h->agent_dest[i];
+            h->q_didx[h->q_off[k] + a] = h->agent_didx.empty() ? 0 : h->agent_didx[i];
         }
     }
 }
@@ -280,7 +292,7 @@ void zero_state(sim_t *h)
     HIPCHK(hipMemsetAsync(d.Dacc, 0, SO * 8, st));
     HIPCHK(hipMemsetAsync(d.rel_ptr, 0, SO * 4, st));
     HIPCHK(hipMemsetAsync(d.dep_ptr, 0, SO * 4, st));
-    HIPCHK(hipMemsetAsync(d.ctr, 0, (size_t)h->S * sim::CTR_N * 8, st));
+    HIPCHK(hipMemsetAsync(d.ctr, 0, (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8, st));
     if (h->D * h->nb) HIPCHK(hipMemsetAsync(d.cum, 0, (size_t)h->S * h->D * h->nb * 4, st));
     HIPCHK(hipMemsetAsync(d.err, 0, sim::ERR_N * 4, st));
     h->t = 0;
@@ -293,8 +305,41 @@ void upload_queues(sim_t *h)
     HIPCHK(hipMemcpyAsync(h->q_off_dev, h->q_off.data(), h->q_off.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (!h->q_list.empty()) {
         HIPCHK(hipMemcpyAsync(h->q_list_dev, h->q_list.data(), h->q_list.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->q_dest_dev, h->q_dest.data(), h->q_dest.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->q_didx_dev, h->q_didx.data(), h->q_didx.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->q_rstep_dev, h->q_rstep.data(), h->q_rstep.size() * 8, hipMemcpyHostToDevice, h->stream));
     }
+    // per-node origin table (origin, first queue entry) follows the queue offsets
+    std::vector<int2> op((size_t)h->Nn * h->max_org, make_int2(-1, 0));
+    for (int v = 0; v < h->Nn; ++v)
+        for (int k = h->org_off[v]; k < h->org_off[v + 1]; ++k) {
+            const int o = h->org_list[k];
+            op[(size_t)v * h->max_org + (k - h->org_off[v])] = make_int2(o, h->q_off[o]);
+        }
+    HIPCHK(hipMemcpyAsync(h->org_pad_dev, op.data(), op.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+}
+
+// links split by ring capacity for the link phase and the reverse
+void build_classes(sim_t *h)
+{
+    std::vector<int32_t> ls, lb, rs, rb;
+    for (int j = 0; j < h->L; ++j) {
+        (h->cap[j] <= 8 * h->g_link ? ls : lb).push_back(j);
+        (h->cap[j] <= 8 * h->g_rev ? rs : rb).push_back(j);
+    }
+    auto put = [&](int32_t *&dev, size_t &capn, const std::vector<int32_t> &v) {
+        if (!dev || capn < v.size() + 1) { dev = h->dalloc<int32_t>(v.size() + 1); capn = v.size() + 1; }
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(dev, v.data(), v.size() * 4, hipMemcpyHostToDevice, h->stream));
+    };
+    put(h->lk_small_dev, h->lk_small_cap, ls);
+    put(h->lk_big_dev, h->lk_big_cap, lb);
+    put(h->rv_small_dev, h->rv_small_cap, rs);
+    put(h->rv_big_dev, h->rv_big_cap, rb);
+    Dev &d = h->d;
+    d.lk_small = h->lk_small_dev; d.lk_big = h->lk_big_dev; d.lk_n_small = (int)ls.size(); d.lk_n_big = (int)lb.size();
+    d.rv_small = h->rv_small_dev; d.rv_big = h->rv_big_dev; d.rv_n_small = (int)rs.size(); d.rv_n_big = (int)rb.size();
+    HIPCHK(hipStreamSynchronize(h->stream));
 }
 
 void derive(sim_t *h)
@@ -326,7 +371,7 @@ void ckpt_alloc(sim_t *h, Ckpt &c)
     c.Dacc = h->dalloc<double>(SO);
     c.rel_ptr = h->dalloc<int32_t>(SO);
     c.dep_ptr = h->dalloc<int32_t>(SO);
-    c.ctr = h->dalloc<int64_t>((size_t)h->S * sim::CTR_N);
+    c.ctr = h->dalloc<int64_t>((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
     c.status = h->dalloc<uint8_t>((size_t)h->S * h->N);
 }
 
@@ -348,7 +393,7 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save)
     cp(c.Dacc, d.Dacc, SO * 8);
     cp(c.rel_ptr, d.rel_ptr, SO * 4);
     cp(c.dep_ptr, d.dep_ptr, SO * 4);
-    cp(c.ctr, d.ctr, (size_t)h->S * sim::CTR_N * 8);
+    cp(c.ctr, d.ctr, (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8);
     cp(c.status, d.status, (size_t)h->S * h->N);
 }
 
@@ -520,6 +565,29 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
         }
         for (int j = 0; j < L; ++j)
             if (h->det_off[j + 1] - h->det_off[j] > sim::kMaxDetPerLink) fail(SIM_EUNSUPPORTED, "more than 4 detectors on a link");
+        // lanes per node: the smallest group that holds every node's candidates and out-links
+        int need = 1;
+        for (int v = 0; v < Nn; ++v) {
+            need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]));
+            need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
+        }
+        h->g_node = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
+        for (int v = 0; v < Nn; ++v) {
+            h->max_in = std::max(h->max_in, h->in_off[v + 1] - h->in_off[v]);
+            h->max_out = std::max(h->max_out, h->out_off[v + 1] - h->out_off[v]);
+            h->max_org = std::max(h->max_org, h->org_off[v + 1] - h->org_off[v]);
+        }
+        if (h->max_in > 255 || h->max_out > 255 || h->max_org > 255) fail(SIM_EUNSUPPORTED, "node degree above 255");
+        h->node_cnt.resize(Nn);
+        h->in_pad.assign((size_t)Nn * h->max_in, -1);
+        h->out_pad.assign((size_t)Nn * h->max_out, -1);
+        for (int v = 0; v < Nn; ++v) {
+            const int di = h->in_off[v + 1] - h->in_off[v], dout = h->out_off[v + 1] - h->out_off[v];
+            const int no = h->org_off[v + 1] - h->org_off[v];
+            h->node_cnt[v] = di | (dout << 8) | (no << 16);
+            for (int k = 0; k < di; ++k) h->in_pad[(size_t)v * h->max_in + k] = h->in_lnk[h->in_off[v] + k];
+            for (int k = 0; k < dout; ++k) h->out_pad[(size_t)v * h->max_out + k] = h->out_lnk[h->out_off[v] + k];
+        }
         // rings: a link holds at most lanes * (floor(L / spacing) + 1) agents; two extra rows of slack
         h->cap.resize(L);
         h->ring_base.resize(L);
@@ -574,6 +642,7 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
         d.S = h->S; d.L = L; d.Nn = Nn; d.O = h->O; d.N = h->N; d.D = h->D; d.nb = h->nb; d.cbs = h->cbs;
         d.n_dest = (int)h->dest_nodes.size(); d.maxl = maxl; d.n_rate_bins = h->B;
         d.fixed_mode = h->fixed_mode; d.allow_uturn = cfg->allow_uturn; d.platoon = h->platoon;
+        d.g_link = h->g_link; d.g_node = h->g_node; d.g_rev = h->g_rev;
         d.ring_total = h->ring_total; d.dt = h->dt; d.theta = cfg->dest_logit_coef; d.rate_bin_s = h->rate_bin_s;
         d.tail = h->upload(h->tail); d.head = h->upload(h->head); d.lanes = h->upload(h->lanes);
         d.cap = h->upload(h->cap); d.ring_base = h->upload(h->ring_base);
@@ -591,9 +660,15 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
         d.agent_origin = h->upload(h->agent_origin);
         h->q_off_dev = h->upload(h->q_off);
         h->q_list_dev = h->dalloc<int32_t>(h->q_list.size());
+        h->q_dest_dev = h->dalloc<int32_t>(h->q_list.size());
+        h->q_didx_dev = h->dalloc<int32_t>(h->q_list.size());
         h->q_rstep_dev = h->dalloc<int64_t>(h->q_rstep.size());
+        h->org_pad_dev = h->dalloc<int2>((size_t)Nn * h->max_org);
         upload_queues(h);
         d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
+        d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev; d.org_pad = h->org_pad_dev;
+        d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
+        d.max_in = h->max_in; d.max_out = h->max_out; d.max_org = h->max_org;
         d.seed = h->upload(h->seeds);
         // parameters, scenario-major
         auto rep = [&](const std::vector<float> &v) {
@@ -615,12 +690,11 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
         d.rhead = h->dalloc<int32_t>(SL); d.rtail = h->dalloc<int32_t>(SL);
         d.B = h->dalloc<double>(SL); d.E = h->dalloc<int64_t>(SL);
         d.slots = h->dalloc<int32_t>(SL); d.nheads = h->dalloc<int32_t>(SL);
-        d.head_agent = h->dalloc<int32_t>(SL * maxl); d.head_choice = h->dalloc<int32_t>(SL * maxl);
-        d.head_key = h->dalloc<double>(SL * maxl);
+        d.head_rec = h->dalloc<int4>(SL * maxl);
         d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
         d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
         d.Dacc = h->dalloc<double>(SO); d.rel_ptr = h->dalloc<int32_t>(SO); d.dep_ptr = h->dalloc<int32_t>(SO);
-        d.ctr = h->dalloc<int64_t>((size_t)h->S * sim::CTR_N);
+        d.ctr = h->dalloc<int64_t>((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
         d.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
         d.err = h->dalloc<int32_t>(sim::ERR_N);
         h->ttt_dev = h->dalloc<double>(h->S);
@@ -639,6 +713,7 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
             h->gT_dev = h->dalloc<double>(h->S);
             h->grad_tmp = h->dalloc<float>(std::max(SL, (size_t)h->S * h->O * std::max(h->B, 1)));
         }
+        build_classes(h);
         derive(h);
         zero_state(h);
         HIPCHK(hipStreamSynchronize(h->stream));
@@ -744,7 +819,7 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         HIPCHK(hipMemcpyAsync(st.data(), h->d.status, SN, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(relt.data(), h->d.rel_t, SN * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(dept.data(), h->d.dep_t, SN * 4, hipMemcpyDeviceToHost, h->stream));
-        std::vector<int64_t> ctr((size_t)h->S * sim::CTR_N);
+        std::vector<int64_t> ctr((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
         HIPCHK(hipMemcpyAsync(ctr.data(), h->d.ctr, ctr.size() * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         for (int s = 0; s < h->S; ++s) {
@@ -760,8 +835,8 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
                 relt[ga] = 0;
                 dept[ga] = -2;   // placed, not departed: no departure graft
             }
-            ctr[(size_t)s * sim::CTR_N + sim::CTR_RELEASED] += n;
-            ctr[(size_t)s * sim::CTR_N + sim::CTR_DEPARTED] += n;
+            ctr[(size_t)s * sim::kCtrSlots * sim::CTR_N + sim::CTR_RELEASED] += n;
+            ctr[(size_t)s * sim::kCtrSlots * sim::CTR_N + sim::CTR_DEPARTED] += n;
         }
         HIPCHK(hipMemcpyAsync(h->d.rtail, rt.data(), SL * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ring_pos, rp.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
@@ -903,7 +978,7 @@ int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t 
         HIPCHK(hipMemcpyAsync(rh.data(), h->d.rhead, SL * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(rt.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(st.data(), h->d.status, SN, hipMemcpyDeviceToHost, h->stream));
-        std::vector<int64_t> ctr((size_t)h->S * sim::CTR_N);
+        std::vector<int64_t> ctr((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
         HIPCHK(hipMemcpyAsync(ctr.data(), h->d.ctr, ctr.size() * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         if (status) for (size_t i = 0; i < SN; ++i) status[i] = st[i];
@@ -924,7 +999,9 @@ int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t 
         if (counters) {
             for (int s = 0; s < h->S; ++s) {
                 int64_t *c = counters + (size_t)s * SIM_C_COUNT;
-                const int64_t *g = ctr.data() + (size_t)s * sim::CTR_N;
+                int64_t g[sim::CTR_N] = {0};
+                for (int q = 0; q < sim::kCtrSlots; ++q)
+                    for (int k = 0; k < sim::CTR_N; ++k) g[k] += ctr[((size_t)s * sim::kCtrSlots + q) * sim::CTR_N + k];
                 for (int k = 0; k < SIM_C_COUNT; ++k) c[k] = g[k];
                 c[SIM_C_ON_NET] = g[sim::CTR_DEPARTED] - g[sim::CTR_EXITED];
             }
@@ -952,6 +1029,8 @@ int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq)
         if (E) HIPCHK(hipMemcpyAsync(E, h->d.E, SL * 8, hipMemcpyDeviceToHost, h->stream));
         if (next_seq) HIPCHK(hipMemcpyAsync(next_seq, h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
+        // the device keeps the bucket before the end-of-step idle cap min(B, 1)
+        if (B) for (size_t i = 0; i < SL; ++i) B[i] = B[i] > 1.0 ? 1.0 : B[i];
     });
 }
 
@@ -1001,6 +1080,33 @@ int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, con
         HIPCHK(hipStreamSynchronize(h->stream));
         (void)hipFree(scratch);
         if (rc != 0) fail(SIM_EUNSUPPORTED, "a segment exceeds the LDS sort capacity");
+    });
+}
+
+int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev)
+{
+    return guarded(h, [&] {
+        auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
+        if (!ok(g_link) || !ok(g_node) || !ok(g_rev)) fail(SIM_EINVAL, "group sizes must be 16, 32 or 64");
+        int need = 1;
+        for (int v = 0; v < h->Nn; ++v) {
+            need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * h->maxl + (h->org_off[v + 1] - h->org_off[v]));
+            need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
+        }
+        if (g_node < need) fail(SIM_EINVAL, "node group smaller than the largest node's candidates");
+        h->g_link = h->d.g_link = g_link;
+        h->g_node = h->d.g_node = g_node;
+        h->g_rev = h->d.g_rev = g_rev;
+        build_classes(h);
+    });
+}
+
+int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev)
+{
+    return guarded(h, [&] {
+        if (g_link) *g_link = h->g_link;
+        if (g_node) *g_node = h->g_node;
+        if (g_rev) *g_rev = h->g_rev;
     });
 }
 

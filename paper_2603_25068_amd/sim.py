@@ -82,6 +82,8 @@ def lib():
         "sim_time": ([vp, vp], C.c_int),
         "sim_philox": ([vp, i32, vp, vp, vp], C.c_int),
         "sim_segsort": ([vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "sim_set_schedule": ([vp, C.c_int, C.c_int, C.c_int], C.c_int),
+        "sim_get_schedule": ([vp, vp, vp, vp], C.c_int),
         "sim_set_timing": ([vp, C.c_int], C.c_int),
         "sim_get_timing": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
     }
@@ -97,7 +99,7 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_segsort",
-            "sim_set_timing", "sim_get_timing"]
+            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing"]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -322,6 +324,14 @@ class Simulator:
                                       C.c_void_p(seq.data_ptr()), C.c_void_p(perm.data_ptr()),
                                       C.c_void_p(off.data_ptr())))
         return perm, off
+
+    def set_schedule(self, g_link: int, g_node: int, g_rev: int):
+        self._chk(self._L.sim_set_schedule(self._h, g_link, g_node, g_rev))
+
+    def schedule(self):
+        a, b, c = C.c_int(0), C.c_int(0), C.c_int(0)
+        self._chk(self._L.sim_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def set_timing(self, on: bool = True):
         self._chk(self._L.sim_set_timing(self._h, int(on)))

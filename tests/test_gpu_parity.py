@@ -205,3 +205,24 @@ def test_errors_are_reported():
     with pytest.raises(SimError) as e:
         s.place([0], [0], [0.0])
     assert e.value.code == SIM_ESTATE
+
+
+@pytest.mark.parametrize("sched", [(16, 64, 16), (32, 64, 32), (64, 64, 64), (16, 32, 64)])
+def test_schedules_give_identical_results(sched):
+    w = W.random_small(12, nx=5, ny=5, n_agents=800, rates=True, steps=300, lanes_max=3)
+    ref = _sim(w, record=True, ckpt_every=50).rollout()
+    cr, tr = ref.observables()
+    gr = ref.backward(gQ=np.ones((1,) + cr.shape[1:], np.float32), gT=[1.0])
+    s = _sim(w, record=True, ckpt_every=50)
+    need = s.schedule()[1]
+    gl, gn, gv = sched
+    s.set_schedule(gl, max(gn, need), gv)
+    s.rollout()
+    cs, ts = s.observables()
+    assert np.array_equal(cr, cs) and np.array_equal(tr, ts)
+    a, b = ref.state(), s.state()
+    for k in ("status", "link", "pos", "seq"):
+        assert np.array_equal(a[k], b[k]), k
+    gs = s.backward(gQ=np.ones((1,) + cr.shape[1:], np.float32), gT=[1.0])
+    for k in gr:
+        assert np.array_equal(gr[k], gs[k]), k
