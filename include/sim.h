@@ -218,6 +218,47 @@ int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
 int sim_set_timing(sim_t *h, int enable);
 int sim_get_timing(sim_t *h, double *ms, int64_t *launches, int n_kinds, int reset);
 
+/* Device bytes sim_create would allocate for these inputs (host-only work:
+ * validation, numbering, shortest times).  SIM_EINVAL for invalid inputs. */
+int sim_footprint(const sim_network *net, const sim_demand *dem, const sim_config *cfg, size_t *bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of forward rollout requests.
+ *
+ * A server owns a loop thread and host preparation workers.  srv_submit
+ * copies the request (network, demand, config, T steps) and returns at once.
+ * Requests are admitted in arrival order (a later one may pass one that does
+ * not fit) when a slot is free and the request's device footprint
+ * (sim_footprint) fits the remaining budget; each admitted request gets its
+ * own device state and stream, and all running requests advance chunk by
+ * chunk so their kernels overlap.  Results do not depend on the mix.  A
+ * request that fails validation or exceeds the budget on its own ends
+ * SRV_FAILED without disturbing the others.  hip_device = -1 runs a
+ * host-only executor (admission logic only, zero observables) for tests.
+ * ------------------------------------------------------------------------ */
+typedef struct srv_t srv_t;
+enum { SRV_QUEUED = 0, SRV_RUNNING = 1, SRV_DONE = 2, SRV_FAILED = 3, SRV_CANCELLED = 4 };
+
+int srv_create(int hip_device, size_t mem_budget_bytes, int32_t max_slots, int32_t chunk_steps, srv_t **out);
+int srv_submit(srv_t *s, const sim_network *net, const sim_demand *dem, const sim_config *cfg, int32_t T,
+               int64_t *ticket);
+int srv_poll(srv_t *s, int64_t ticket, int *state);
+/* Block until the request is done, failed or cancelled, or timeout_s passes. */
+int srv_wait(srv_t *s, int64_t ticket, double timeout_s, int *state);
+/* Results of a SRV_DONE request into host buffers (each may be NULL): counts
+ * [S x det x bins], total travel time [S], vehicle-steps [S] (S = the
+ * request's n_scenarios), latency from submission to completion in seconds.
+ * SIM_ESTATE before completion; the request's failure code after failure. */
+int srv_result(srv_t *s, int64_t ticket, float *counts, double *ttt, int64_t *vehicle_steps, double *latency_s);
+const char *srv_error(srv_t *s, int64_t ticket);
+int srv_cancel(srv_t *s, int64_t ticket);
+/* Latency percentiles of completed requests, vehicle-steps per second from
+ * the first arrival to the last completion, completions, and the largest
+ * number of requests that ran at once. */
+int srv_stats(srv_t *s, double *p50_s, double *p99_s, double *vehicle_steps_per_s, int64_t *completed,
+              int64_t *max_running);
+int srv_destroy(srv_t *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,7 +82,8 @@ struct Dev {
     float *tape_pos;                 // [(W+1) * S * ring_total]
     int32_t *tape_agent;             // same
     int32_t *tape_head, *tape_tail;  // [(W+1) * S * L]
-    float *adj;                      // [S*N] adjoint of the agent's current position
+    int32_t *tape_dst;               // [(W+1) * S * L * maxl] entry slot of each leaving head (-1: exit)
+    float *adj_ring;                 // [S * ring_total] adjoint of the position of each ring slot's agent
     float *depg;                     // [S*N] adjoint reaching a departure graft, times u of the first link
     double *gu, *gk;                 // [S*L] accumulated parameter gradients
     const float *gQ;                 // [S*D*nb] dL/dcounts (device copy)
@@ -90,9 +91,29 @@ struct Dev {
     const float *gx;                 // [S*N]
 };
 
+}  // namespace sim
+
+
+#include "sim.h"
+#include <string>
+
+namespace sim {
+
+// serving hooks (sim_runtime.cpp)
+sim_t *host_prepare(const sim_network *net, const sim_demand *dem, const sim_config *cfg, int device, int *code,
+                    std::string *err);
+size_t footprint_of(const sim_t *h);
+int device_attach(sim_t *h, hipStream_t stream, std::string *err);
+int rollout_enqueue(sim_t *h, int T, std::string *err);
+int results_enqueue(sim_t *h, float *counts, double *ttt, int64_t *vsteps, std::string *err);
+int device_errors(sim_t *h, std::string *err);
+int counts_size(const sim_t *h);
+int scenarios_of(const sim_t *h);
+void destroy_handle(sim_t *h);
+
 // kernel launchers (sim_kernels.hip)
 void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st);
-void launch_node(const Dev &d, int t, hipStream_t st);
+void launch_node(const Dev &d, int t, int tape_k, hipStream_t st);
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st);
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st);
 void launch_rate_grad(const Dev &d, float *g_rates, hipStream_t st);
@@ -105,5 +126,6 @@ void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capaci
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, hipStream_t st);
 void launch_counts(const Dev &d, float *out, hipStream_t st);
 void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st);
+void launch_gather_links(const double *src, const int32_t *linv, float *dst, int S, int L, hipStream_t st);
 
 }  // namespace sim

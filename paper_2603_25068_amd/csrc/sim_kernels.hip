@@ -29,6 +29,14 @@ __device__ __forceinline__ int xcd_tile()
     return x * q + (x < r ? x : r) + k;
 }
 
+// Same mapping for block b of a role that owns nb consecutive blocks whose
+// first block id is a multiple of 8 (so b % 8 is still the XCD).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ int readlane_i(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
@@ -237,7 +245,8 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
             d.tape_tail[(int64_t)tape_k * d.S * d.L + seg] = h0 + n;
         }
     }
-    if (gl == 0 && n_raw > cap) atomicOr(&d.err[ERR_RING_OVERFLOW], 1);
+    // a ring keeps `lanes` slots free, so an entry slot never aliases a slot live one step earlier
+    if (gl == 0 && n_raw > cap - ln) atomicOr(&d.err[ERR_RING_OVERFLOW], 1);
     float dpos[kMaxDetPerLink];
     int dcnt[kMaxDetPerLink];
 #pragma unroll
@@ -317,17 +326,17 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
     constexpr int sbuf = 8 * G + kMaxLanes;
     static_assert(per * sbuf <= 4 * kBigLds, "small-segment staging exceeds LDS");
     const int small_items = d.S * d.lk_n_small;
-    const int small_blocks = (small_items + per - 1) / per;
+    const int small_blocks = ((small_items + per - 1) / per + 7) & ~7;   // a multiple of 8: roles keep the XCD pattern
     if ((int)blockIdx.x < small_blocks) {
         const Group<G> g;
-        const int item = blockIdx.x * per + (int)threadIdx.x / G;
+        const int item = xcd_remap(blockIdx.x, small_blocks) * per + (int)threadIdx.x / G;
         if (item >= small_items) return;
         const int s = item / d.lk_n_small;
         const int seg = s * d.L + d.lk_small[item - s * d.lk_n_small];
         link_segment<G>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
     } else {
         const Group<64> g;
-        const int item = ((int)blockIdx.x - small_blocks) * 4 + (int)threadIdx.x / 64;
+        const int item = xcd_remap((int)blockIdx.x - small_blocks, (int)gridDim.x - small_blocks) * 4 + (int)threadIdx.x / 64;
         if (item >= d.S * d.lk_n_big) return;
         const int s = item / d.lk_n_big;
         const int seg = s * d.L + d.lk_big[item - s * d.lk_n_big];
@@ -353,7 +362,7 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 // link in the first load.
 // ---------------------------------------------------------------------------
 template <int G>
-__global__ __launch_bounds__(256) void k_node(Dev d, int t)
+__global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
 {
     const Group<G> g;
     const int item = group_item<G>();
@@ -562,9 +571,11 @@ __global__ __launch_bounds__(256) void k_node(Dev d, int t)
         if (mk == ch) { tbase = tk; rbase = bk; rcap = ck; }
     }
     const int64_t ga = (int64_t)s * d.N + (ag >= 0 ? ag : 0);
+    const int64_t slot = (int64_t)s * d.ring_total + rbase + (tbase + erank) % rcap;
+    if (tape_k >= 0 && passed && from >= 0)   // where each leaving head went (-1: left the network)
+        d.tape_dst[((int64_t)tape_k * d.S * d.L + sL + from) * maxl + (gl - qi * maxl)] = ch >= 0 ? (int32_t)slot : -1;
     if (passed) {
         if (ch >= 0) {
-            const int64_t slot = (int64_t)s * d.ring_total + rbase + (tbase + erank) % rcap;
             d.ring_agent[slot] = ag;
             d.ring_pos[slot] = 0.f;
             if (origin >= 0) {
@@ -607,25 +618,27 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
 
 // ---------------------------------------------------------------------------
 // Reverse of step t (tape entry k holds time t, k+1 time t+1), per segment.
-// Input: adj[a] = dL/dx_a(t+1) for agents on the network at t+1 (sampled
-// counts at t+1 already added).  Output: adj[a] = dL/dx_a(t) for agents on
-// this link at t, plus the counts sampled at t and the departure grafts of
-// agents that entered at t.  Branches are recomputed from the taped time-t
-// positions with the forward's exact float operations.
+// The adjoint lives in a ring-parallel array: an agent keeps its ring slot
+// while it is on a link, so adj_ring[slot] holds dL/dx of that slot's agent.
+// Input: adj_ring = dL/dx(t+1) for slots live at t+1 (counts sampled at t+1
+// included).  Output: adj_ring = dL/dx(t) for this link's slots live at t,
+// plus the counts sampled at t; and the departure grafts of agents that
+// entered this link during step t.  Branches are recomputed from the taped
+// time-t positions with the forward's exact float operations.
 //   cap (SI-A eq. tg): dx_hat/dx' = 1 in both branches;
-//   transfer (SI-B eq. transfer, SI-C): the entry position carries x_hat;
+//   transfer (SI-B eq. transfer, SI-C): the entry position carries x_hat, so
+//     a leaving head reads the adjoint at its entry slot (taped forward);
 //   exit: total travel time falls by (x_hat - sg x_hat)/u of the last link;
 //   free: x' = x + u dt; congested: x' = x_lead - dn/kappa; stopped: x' = x.
 // Each agent has at most one follower (rank + lanes), so the leader term is
 // a gather.  A piece of ranks [lo, hi) is staged in LDS with its leader and
-// follower halos (taped positions, agent ids, then the time-t+1 adjoints of
-// [lo, hi + lanes)); all reads of a piece finish before its writes, and
-// pieces go front to back, so no piece reads an adjoint another one wrote.
-// (Followers never leave in the step: only heads, rank < lanes, do.)
-// init = 1: adj = dL/dx(T) at the final state (no step).
+// follower halos; all reads of a piece finish before its writes, and pieces
+// go front to back.  Entry slots written in step t never alias slots live at
+// t (a ring keeps `lanes` slots free), so concurrent segments do not race.
+// init = 1: adj_ring = dL/dx(T) at the final state (no step).
 // ---------------------------------------------------------------------------
 constexpr int kRevSmall = 8;        // small segments: capacity <= kRevSmall * G
-constexpr int kRevBigLds = 1728;    // LDS words per wavefront for big segments (three arrays)
+constexpr int kRevBigLds = 1152;    // LDS words per wavefront for big segments (two arrays)
 
 template <int G>
 __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
@@ -634,12 +647,13 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     const int gl = g.gl;
     const int s = seg / d.L, j = seg - s * d.L;
     const int64_t SL = (int64_t)d.S * d.L;
-    const int cap = d.cap[j], ln = d.lanes[j], vhead = d.head[j];
+    const int cap = d.cap[j], ln = d.lanes[j];
     const int hk = d.tape_head[tape_k * SL + seg];
     const int n = min(d.tape_tail[tape_k * SL + seg] - hk, cap);
     const int npass = init ? 0 : d.tape_head[(tape_k + 1) * SL + seg] - hk;
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
-    const int64_t tb = (int64_t)tape_k * d.S * d.ring_total + base;
+    const int64_t RTS = (int64_t)d.S * d.ring_total;
+    const int64_t tb = (int64_t)tape_k * RTS + base;
     const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j];
     const float uj = d.u[seg], kap = d.kappa[seg];
     const double dkap = (double)d.platoon / ((double)kap * (double)kap);
@@ -664,43 +678,30 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
             dpos[k] = d.det_pos[det];
         }
     }
-    const int P = bufcap / 3;
-    float *xb = buf;
-    int *ab = reinterpret_cast<int *>(buf + P);
-    float *pb = buf + 2 * P;
+    const int P = bufcap / 2;
+    float *xb = buf, *pb = buf + P;
     const int piece = P - 2 * kMaxLanes;
+    const int64_t dst0 = ((int64_t)tape_k * SL + seg) * d.maxl;
     double gu = 0.0, gk = 0.0;
     for (int lo = 0; lo < n; lo += piece) {
         const int hi = min(n, lo + piece);
         const int slo = max(0, lo - ln), shi = min(n, hi + ln);
-        // taped positions and agents of [slo, shi)
-        for (int r = slo + gl; r < shi; r += 2 * G) {
-            float x2[2];
-            int a2[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int rr = r + q * G;
-                x2[q] = 0.f; a2[q] = 0;
-                if (rr < shi) { const int sl = slot_of(rr); x2[q] = d.tape_pos[tb + sl]; a2[q] = d.tape_agent[tb + sl]; }
+        // taped positions of [slo, shi) and the adjoints of the x_hat of [lo, shi)
+        for (int r = slo + gl; r < shi; r += G) {
+            const int sl = slot_of(r);
+            xb[r - slo] = d.tape_pos[tb + sl];
+            if (r >= lo) {
+                float ap;
+                if (init) ap = d.gx ? d.gx[sN + d.tape_agent[tb + sl]] : 0.f;
+                else if (r < npass) { const int ds = d.tape_dst[dst0 + r]; ap = ds < 0 ? exit_adj : d.adj_ring[ds]; }
+                else ap = d.adj_ring[base + sl];
+                pb[r - slo] = ap;
             }
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-                if (r + q * G < shi) { xb[r + q * G - slo] = x2[q]; ab[r + q * G - slo] = a2[q]; }
-        }
-        wave_lds_sync();
-        // time-t+1 adjoints of the x_hat of [lo, shi)
-        for (int r = lo + gl; r < shi; r += G) {
-            const int a = ab[r - slo];
-            float ap;
-            if (init) ap = d.gx ? d.gx[sN + a] : 0.f;
-            else ap = (r < npass && d.agent_dest[a] == vhead) ? exit_adj : d.adj[sN + a];
-            pb[r - slo] = ap;
         }
         wave_lds_sync();
         for (int r0 = lo; r0 < hi; r0 += G) {
             const int r = r0 + gl;
-            const bool v = r < hi;
-            if (!v) continue;
+            if (r >= hi) continue;
             const float x = xb[r - slo];
             const float ap = pb[r - slo];
             float anew;
@@ -735,11 +736,19 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
                     anew += gC[k] * sc * sg * (1.0f - sg);
                 }
             }
-            const int a = ab[r - slo];
-            d.adj[sN + a] = anew;
-            if (d.dep_t[sN + a] == t - 1) d.depg[sN + a] = anew * uj;
+            d.adj_ring[base + slot_of(r)] = anew;
         }
         wave_lds_sync();
+    }
+    // departure grafts of the agents that entered this link during step t
+    if (!init && d.depg) {
+        const int e0 = d.tape_tail[tape_k * SL + seg], e1 = d.tape_tail[(tape_k + 1) * SL + seg];
+        const int64_t tb1 = (int64_t)(tape_k + 1) * RTS + base;
+        for (int q = e0 + gl; q < e1; q += G) {
+            const int sl = q % cap;
+            const int a = d.tape_agent[tb1 + sl];
+            if (d.dep_t[sN + a] == t) d.depg[sN + a] = d.adj_ring[base + sl] * uj;
+        }
     }
     gu = g.sum(gu);
     gk = g.sum(gk);
@@ -754,20 +763,20 @@ __global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int i
 {
     __shared__ float lds[4 * kRevBigLds];
     constexpr int per = 256 / G;
-    constexpr int sbuf = 3 * (kRevSmall * G + 2 * kMaxLanes);
+    constexpr int sbuf = 2 * (kRevSmall * G + 2 * kMaxLanes);
     static_assert(per * sbuf <= 4 * kRevBigLds, "small-segment staging exceeds LDS");
     const int small_items = d.S * d.rv_n_small;
-    const int small_blocks = (small_items + per - 1) / per;
+    const int small_blocks = ((small_items + per - 1) / per + 7) & ~7;   // a multiple of 8: roles keep the XCD pattern
     if ((int)blockIdx.x < small_blocks) {
         const Group<G> g;
-        const int item = blockIdx.x * per + (int)threadIdx.x / G;
+        const int item = xcd_remap(blockIdx.x, small_blocks) * per + (int)threadIdx.x / G;
         if (item >= small_items) return;
         const int s = item / d.rv_n_small;
         const int seg = s * d.L + d.rv_small[item - s * d.rv_n_small];
         reverse_segment<G>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
     } else {
         const Group<64> g;
-        const int item = ((int)blockIdx.x - small_blocks) * 4 + (int)threadIdx.x / 64;
+        const int item = xcd_remap((int)blockIdx.x - small_blocks, (int)gridDim.x - small_blocks) * 4 + (int)threadIdx.x / 64;
         if (item >= d.S * d.rv_n_big) return;
         const int s = item / d.rv_n_big;
         const int seg = s * d.L + d.rv_big[item - s * d.rv_n_big];
@@ -855,6 +864,15 @@ __global__ void k_counts(Dev d, float *out)
     if (i >= (int64_t)d.S * d.D * d.nb) return;
     const int b = (int)(i % d.nb);
     out[i] = (float)(d.cum[i] - (b > 0 ? d.cum[i - 1] : 0));
+}
+
+// dst[s, caller link] = src[s, internal link], double -> float
+__global__ void k_gather_links(const double *src, const int32_t *linv, float *dst, int S, int L)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)S * L) return;
+    const int64_t s = i / L, jo = i - s * L;
+    dst[i] = (float)src[s * L + linv[jo]];
 }
 
 __global__ void k_d2f(const double *src, float *dst, int64_t n)
@@ -1001,7 +1019,7 @@ static inline int blocks_for(int64_t items, int G) { const int per = 256 / G; re
 static inline int class_blocks(int S, int n_small, int n_big, int G)
 {
     const int per = 256 / G;
-    return (S * n_small + per - 1) / per + (S * n_big + 3) / 4;
+    return ((((S * n_small + per - 1) / per) + 7) & ~7) + (S * n_big + 3) / 4;
 }
 
 void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
@@ -1012,13 +1030,13 @@ void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
     default: hipLaunchKernelGGL(k_link<64>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 64)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
     }
 }
-void launch_node(const Dev &d, int t, hipStream_t st)
+void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
 {
     const int64_t items = (int64_t)d.S * d.Nn;
     switch (d.g_node) {
-    case 16: hipLaunchKernelGGL(k_node<16>, dim3(blocks_for(items, 16)), dim3(256), 0, st, d, t); break;
-    case 32: hipLaunchKernelGGL(k_node<32>, dim3(blocks_for(items, 32)), dim3(256), 0, st, d, t); break;
-    default: hipLaunchKernelGGL(k_node<64>, dim3(blocks_for(items, 64)), dim3(256), 0, st, d, t); break;
+    case 16: hipLaunchKernelGGL(k_node<16>, dim3(blocks_for(items, 16)), dim3(256), 0, st, d, t, tape_k); break;
+    case 32: hipLaunchKernelGGL(k_node<32>, dim3(blocks_for(items, 32)), dim3(256), 0, st, d, t, tape_k); break;
+    default: hipLaunchKernelGGL(k_node<64>, dim3(blocks_for(items, 64)), dim3(256), 0, st, d, t, tape_k); break;
     }
 }
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
@@ -1053,6 +1071,12 @@ void launch_counts(const Dev &d, float *out, hipStream_t st)
     const int64_t n = (int64_t)d.S * d.D * d.nb;
     if (n == 0) return;
     hipLaunchKernelGGL(k_counts, dim3((int)((n + 255) / 256)), dim3(256), 0, st, d, out);
+}
+void launch_gather_links(const double *src, const int32_t *linv, float *dst, int S, int L, hipStream_t st)
+{
+    const int64_t n = (int64_t)S * L;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_links, dim3((int)((n + 255) / 256)), dim3(256), 0, st, src, linv, dst, S, L);
 }
 void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st)
 {

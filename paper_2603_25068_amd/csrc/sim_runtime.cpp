@@ -78,6 +78,8 @@ struct sim_t {
 
     // derived host structures
     std::vector<int32_t> cap, ring_base, out_off, out_lnk, in_off, in_lnk, org_off, org_list, det_off, det_list;
+    std::vector<int32_t> nperm, ninv, lperm, linv;   // internal <-> caller numbering of nodes and links
+    int32_t *linv_dev = nullptr;
     std::vector<int32_t> dest_nodes, agent_didx;
     std::vector<double> dist, tff;
     std::vector<int32_t> q_off, q_list;  // full queues (as built at create)
@@ -109,6 +111,10 @@ struct sim_t {
         return vsteps_dev;
     }
 
+    size_t footprint = 0;     // device bytes this handle allocates
+    double theta_cfg = 0.0;   // config kept for deferred allocation (serving)
+    int32_t uturn_cfg = 1;
+    int n_ck = 0;
     int t = 0;
     std::vector<Ckpt> ckpts;  // [n_ckpt] + final
     int W = 0;                // tape window (= ckpt_every)
@@ -320,6 +326,76 @@ void upload_queues(sim_t *h)
     HIPCHK(hipStreamSynchronize(h->stream));
 }
 
+// Locality-preserving internal numbering: nodes in reverse Cuthill-McKee
+// order of the undirected node graph (neighbours get nearby ids), links by
+// (new tail node, original id), so a node's out-links stay in original-id
+// order.  Callers always see the original numbering; the runtime translates
+// at the boundary.
+void renumber(sim_t *h)
+{
+    const int Nn = h->Nn, L = h->L;
+    std::vector<std::vector<int>> adj(Nn);
+    for (int j = 0; j < L; ++j) {
+        adj[h->tail[j]].push_back(h->head[j]);
+        adj[h->head[j]].push_back(h->tail[j]);
+    }
+    for (auto &a : adj) {
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+    }
+    auto deg_less = [&](int a, int b) { return adj[a].size() != adj[b].size() ? adj[a].size() < adj[b].size() : a < b; };
+    std::vector<int> start(Nn);
+    for (int v = 0; v < Nn; ++v) start[v] = v;
+    std::sort(start.begin(), start.end(), deg_less);
+    std::vector<int> order;
+    order.reserve(Nn);
+    std::vector<char> seen(Nn, 0);
+    for (int st : start) {
+        if (seen[st]) continue;
+        size_t qh = order.size();
+        order.push_back(st);
+        seen[st] = 1;
+        while (qh < order.size()) {
+            const int x = order[qh++];
+            std::vector<int> nb;
+            for (int y : adj[x]) if (!seen[y]) nb.push_back(y);
+            std::sort(nb.begin(), nb.end(), deg_less);
+            for (int y : nb) { seen[y] = 1; order.push_back(y); }
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    h->nperm = order;
+    h->ninv.assign(Nn, 0);
+    for (int k = 0; k < Nn; ++k) h->ninv[order[k]] = k;
+    h->lperm.resize(L);
+    for (int j = 0; j < L; ++j) h->lperm[j] = j;
+    std::sort(h->lperm.begin(), h->lperm.end(), [&](int a, int b) {
+        const int ta = h->ninv[h->tail[a]], tb = h->ninv[h->tail[b]];
+        return ta != tb ? ta < tb : a < b;
+    });
+    h->linv.assign(L, 0);
+    for (int k = 0; k < L; ++k) h->linv[h->lperm[k]] = k;
+    auto perm_f = [&](std::vector<float> &v) { std::vector<float> o(L); for (int k = 0; k < L; ++k) o[k] = v[h->lperm[k]]; v.swap(o); };
+    auto perm_i = [&](std::vector<int32_t> &v) { std::vector<int32_t> o(L); for (int k = 0; k < L; ++k) o[k] = v[h->lperm[k]]; v.swap(o); };
+    perm_i(h->tail); perm_i(h->head); perm_i(h->lanes);
+    for (auto &x : h->tail) x = h->ninv[x];
+    for (auto &x : h->head) x = h->ninv[x];
+    perm_f(h->length); perm_f(h->free_speed); perm_f(h->jam_density); perm_f(h->capacity);
+    perm_f(h->beta); perm_f(h->alpha); perm_f(h->cost);
+    for (auto &x : h->origin_node) x = h->ninv[x];
+    for (auto &x : h->det_link) x = h->linv[x];
+    for (auto &x : h->agent_dest) x = h->ninv[x];
+}
+
+// per-link values [S x L]: caller order -> internal order
+std::vector<float> links_in(const sim_t *h, const float *v)
+{
+    std::vector<float> o((size_t)h->S * h->L);
+    for (int s = 0; s < h->S; ++s)
+        for (int k = 0; k < h->L; ++k) o[(size_t)s * h->L + k] = v[(size_t)s * h->L + h->lperm[k]];
+    return o;
+}
+
 // links split by ring capacity for the link phase and the reverse
 void build_classes(sim_t *h)
 {
@@ -407,7 +483,7 @@ void do_step(sim_t *h, int tape_k)
     sim::launch_link(h->d, t, sb, tape_k, h->stream);
     h->time_end(0, e0);
     h->time_begin(1, &e1);
-    sim::launch_node(h->d, t, h->stream);
+    sim::launch_node(h->d, t, tape_k, h->stream);
     h->time_end(1, e1);
     HIPCHK(hipGetLastError());
     h->t = t + 1;
@@ -445,7 +521,387 @@ void copy_out(sim_t *h, void *dst, const void *src_dev, size_t bytes, int on_dev
     HIPCHK(hipMemcpyAsync(dst, src_dev, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
 }
 
+// Host-side preparation of a handle: validation, renumbering, adjacency,
+// rings, shortest times, queues and the device footprint.  No device calls.
+void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const sim_config *cfg)
+{
+        // ---------------- validate and copy ----------------
+    const int L = net->n_links, Nn = net->n_nodes;
+    if (L <= 0 || Nn <= 0) fail(SIM_EINVAL, "network needs nodes and links");
+    if (!net->tail || !net->head || !net->lanes || !net->length || !net->free_speed || !net->jam_density ||
+        !net->capacity)
+        fail(SIM_EINVAL, "missing link array");
+    h->L = L; h->Nn = Nn;
+    h->tail.assign(net->tail, net->tail + L);
+    h->head.assign(net->head, net->head + L);
+    h->lanes.assign(net->lanes, net->lanes + L);
+    h->length.assign(net->length, net->length + L);
+    h->free_speed.assign(net->free_speed, net->free_speed + L);
+    h->jam_density.assign(net->jam_density, net->jam_density + L);
+    h->capacity.assign(net->capacity, net->capacity + L);
+    h->beta = net->beta ? std::vector<float>(net->beta, net->beta + L) : std::vector<float>(L, 0.f);
+    h->alpha = net->alpha ? std::vector<float>(net->alpha, net->alpha + L) : std::vector<float>(L, 1.f);
+    h->cost = net->cost ? std::vector<float>(net->cost, net->cost + L) : std::vector<float>(L, 1.f);
+    int maxl = 1;
+    for (int j = 0; j < L; ++j) {
+        if (h->tail[j] < 0 || h->tail[j] >= Nn || h->head[j] < 0 || h->head[j] >= Nn)
+            fail(SIM_EINVAL, "link " + std::to_string(j) + ": node index out of range");
+        if (h->lanes[j] < 1 || h->lanes[j] > sim::kMaxLanes) fail(SIM_EINVAL, "lanes must be in [1, 8]");
+        if (!(h->length[j] > 0.02f) || !(h->free_speed[j] > 0.f) || !(h->jam_density[j] > 0.f) ||
+            !(h->capacity[j] >= 0.f) || !(h->cost[j] > 0.f) || !std::isfinite(h->length[j]) ||
+            !std::isfinite(h->free_speed[j]) || !std::isfinite(h->capacity[j]))
+            fail(SIM_EINVAL, "link " + std::to_string(j) + ": non-positive or non-finite length/speed/density/cost");
+        maxl = std::max(maxl, h->lanes[j]);
+    }
+    h->maxl = maxl;
+    h->O = net->n_origins;
+    if (h->O < 0 || (h->O > 0 && !net->origin_node)) fail(SIM_EINVAL, "bad origins");
+    h->origin_node.assign(net->origin_node, net->origin_node + h->O);
+    for (int k = 0; k < h->O; ++k)
+        if (h->origin_node[k] < 0 || h->origin_node[k] >= Nn) fail(SIM_EINVAL, "origin node out of range");
+    h->D = net->n_detectors;
+    if (h->D < 0 || (h->D > 0 && (!net->detector_link || !net->detector_pos))) fail(SIM_EINVAL, "bad detectors");
+    h->det_link.assign(net->detector_link, net->detector_link + h->D);
+    h->det_pos.assign(net->detector_pos, net->detector_pos + h->D);
+    for (int k = 0; k < h->D; ++k) {
+        const int j = h->det_link[k];
+        if (j < 0 || j >= L) fail(SIM_EINVAL, "detector link out of range");
+        if (!(h->det_pos[k] > 0.f) || !(h->det_pos[k] <= h->length[j] - 0.01f))
+            fail(SIM_EINVAL, "detector position must lie in (0, length - 0.01]");
+    }
+    h->N = dem->n_agents;
+    if (h->N < 0 || (h->N > 0 && (!dem->agent_origin || !dem->agent_dest))) fail(SIM_EINVAL, "bad agents");
+    h->agent_origin.assign(dem->agent_origin, dem->agent_origin + h->N);
+    h->agent_dest.assign(dem->agent_dest, dem->agent_dest + h->N);
+    h->fixed_mode = dem->ready_time != nullptr;
+    if (h->fixed_mode) h->ready.assign(dem->ready_time, dem->ready_time + h->N);
+    else {
+        h->B = dem->n_rate_bins;
+        h->rate_bin_s = dem->rate_bin_s;
+        if (h->B <= 0 || !dem->rates || !(dem->rate_bin_s > 0)) fail(SIM_EINVAL, "rate mode needs rates and bins");
+        h->rates.assign(dem->rates, dem->rates + (size_t)h->O * h->B);
+        for (float r : h->rates)
+            if (!(r >= 0.f) || !std::isfinite(r)) fail(SIM_EINVAL, "rates must be finite and >= 0");
+    }
+    for (int i = 0; i < h->N; ++i) {
+        if (h->agent_origin[i] < 0 || h->agent_origin[i] >= h->O) fail(SIM_EINVAL, "agent origin out of range");
+        if (h->agent_dest[i] < 0 || h->agent_dest[i] >= Nn) fail(SIM_EINVAL, "agent destination out of range");
+        if (h->agent_dest[i] == h->origin_node[h->agent_origin[i]])
+            fail(SIM_EINVAL, "agent destination equals its origin node");
+    }
+    h->dt = cfg->dt;
+    h->platoon = cfg->platoon;
+    if (!(cfg->dt > 0) || cfg->platoon < 1) fail(SIM_EINVAL, "dt > 0 and platoon >= 1 required");
+    if (!h->fixed_mode) {
+        const double k = h->rate_bin_s / h->dt;
+        if (std::fabs(k - std::round(k)) > 1e-9) fail(SIM_EINVAL, "rate bins must be a whole number of steps");
+    }
+    h->S = cfg->n_scenarios;
+    if (h->S < 1) fail(SIM_EINVAL, "n_scenarios >= 1");
+    h->cbs = cfg->count_bin_steps;
+    h->nb = cfg->n_count_bins;
+    if (h->nb < 0 || (h->nb > 0 && h->cbs < 1)) fail(SIM_EINVAL, "count bins need count_bin_steps >= 1");
+    h->ckpt_every = cfg->ckpt_every > 0 ? cfg->ckpt_every : 60;
+    h->max_steps = cfg->max_steps;
+    h->record = cfg->record_for_backward;
+    if (h->record && h->max_steps <= 0) fail(SIM_EINVAL, "record_for_backward needs max_steps > 0");
+    h->seeds.resize(h->S);
+    for (int s = 0; s < h->S; ++s) h->seeds[s] = cfg->scenario_seed ? cfg->scenario_seed[s] : cfg->seed + (uint64_t)s;
+
+    // ---------------- graph ----------------
+    renumber(h);
+    build_csr(Nn, h->tail, h->out_off, h->out_lnk);
+    build_csr(Nn, h->head, h->in_off, h->in_lnk);
+    build_csr(Nn, h->origin_node, h->org_off, h->org_list);
+    build_csr(L, h->det_link, h->det_off, h->det_list);
+    for (int v = 0; v < Nn; ++v) {
+        const int nc = (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]);
+        if (nc > sim::kWave) fail(SIM_EUNSUPPORTED, "node " + std::to_string(v) + ": more than 64 merge candidates");
+        if (h->out_off[v + 1] - h->out_off[v] > sim::kWave) fail(SIM_EUNSUPPORTED, "node out-degree above 64");
+    }
+    for (int j = 0; j < L; ++j)
+        if (h->det_off[j + 1] - h->det_off[j] > sim::kMaxDetPerLink) fail(SIM_EUNSUPPORTED, "more than 4 detectors on a link");
+    // lanes per node: the smallest group that holds every node's candidates and out-links
+    int need = 1;
+    for (int v = 0; v < Nn; ++v) {
+        need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]));
+        need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
+    }
+    h->g_node = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
+    for (int v = 0; v < Nn; ++v) {
+        h->max_in = std::max(h->max_in, h->in_off[v + 1] - h->in_off[v]);
+        h->max_out = std::max(h->max_out, h->out_off[v + 1] - h->out_off[v]);
+        h->max_org = std::max(h->max_org, h->org_off[v + 1] - h->org_off[v]);
+    }
+    if (h->max_in > 255 || h->max_out > 255 || h->max_org > 255) fail(SIM_EUNSUPPORTED, "node degree above 255");
+    h->node_cnt.resize(Nn);
+    h->in_pad.assign((size_t)Nn * h->max_in, -1);
+    h->out_pad.assign((size_t)Nn * h->max_out, -1);
+    for (int v = 0; v < Nn; ++v) {
+        const int di = h->in_off[v + 1] - h->in_off[v], dout = h->out_off[v + 1] - h->out_off[v];
+        const int no = h->org_off[v + 1] - h->org_off[v];
+        h->node_cnt[v] = di | (dout << 8) | (no << 16);
+        for (int k = 0; k < di; ++k) h->in_pad[(size_t)v * h->max_in + k] = h->in_lnk[h->in_off[v] + k];
+        for (int k = 0; k < dout; ++k) h->out_pad[(size_t)v * h->max_out + k] = h->out_lnk[h->out_off[v] + k];
+    }
+    // rings: a link holds at most lanes * (floor(L / spacing) + 1) agents; two extra rows of slack
+    h->cap.resize(L);
+    h->ring_base.resize(L);
+    h->min_spacing.resize(L);
+    int64_t tot = 0;
+    for (int j = 0; j < L; ++j) {
+        const float sp = (float)h->platoon / h->jam_density[j];
+        h->min_spacing[j] = sp;
+        // a lane chain holds at most floor(L / spacing) + 2 agents under float rounding; one
+        // more row per lane keeps `lanes` slots free for the step's leavers
+        const double rows = std::floor((double)h->length[j] / (double)sp) + 4.0;
+        const double c = rows * h->lanes[j];
+        if (c > 1e8) fail(SIM_EUNSUPPORTED, "link too long for its jam spacing");
+        h->cap[j] = (int32_t)c;
+        h->ring_base[j] = (int32_t)tot;
+        tot += h->cap[j];
+        if (tot > (int64_t)1 << 30) fail(SIM_EUNSUPPORTED, "ring storage above 2^30 slots");
+    }
+    h->ring_total = tot;
+    if ((int64_t)h->S * tot >= ((int64_t)1 << 31)) fail(SIM_EUNSUPPORTED, "scenarios x ring slots above 2^31");
+    // destinations, numbered in node order
+    std::vector<int32_t> didx(Nn, -1);
+    for (int i = 0; i < h->N; ++i) didx[h->agent_dest[i]] = 0;
+    for (int v = 0; v < Nn; ++v)
+        if (didx[v] == 0) { didx[v] = (int32_t)h->dest_nodes.size(); h->dest_nodes.push_back(v); }
+    h->agent_didx.resize(h->N);
+    for (int i = 0; i < h->N; ++i) h->agent_didx[i] = didx[h->agent_dest[i]];
+    shortest_times(h);
+    for (int i = 0; i < h->N; ++i) {
+        const double dd = h->dist[(size_t)h->agent_didx[i] * Nn + h->origin_node[h->agent_origin[i]]];
+        if (!(dd < std::numeric_limits<double>::infinity()))
+            fail(SIM_EINVAL, "agent " + std::to_string(i) + ": destination unreachable from its origin");
+    }
+    h->tff.resize(L);
+    for (int m = 0; m < L; ++m) h->tff[m] = (double)h->length[m] / (double)h->free_speed[m];
+    build_queues(h, nullptr);
+
+    // ---------------- memory budget ----------------
+    const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
+    const size_t SR = (size_t)h->S * h->ring_total;
+    size_t bytes = SR * 8 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
+                   h->dist.size() * 8 + (size_t)h->S * h->D * h->nb * 8;
+    int n_ck = 0;
+    if (h->record) {
+        n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
+        h->W = h->ckpt_every;
+        bytes += (size_t)n_ck * (SR * 8 + SL * 24 + SO * 16 + SN);
+        bytes += (size_t)(h->W + 1) * (SR * 8 + SL * 8 + SL * maxl * 4) + SR * 4 + SN * 4 + SL * 16;
+    }
+    h->footprint = bytes;
+    h->n_ck = n_ck;
+    if (cfg->mem_budget_bytes && bytes > cfg->mem_budget_bytes)
+        fail(SIM_ENOMEM, "footprint " + std::to_string(bytes) + " B exceeds the memory budget");
+
+}
+
+// Device allocation and upload of a prepared handle.
+void allocate_device(sim_t *h, const sim_config *cfg)
+{
+    const int L = h->L, Nn = h->Nn, maxl = h->maxl, n_ck = h->n_ck;
+    const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
+    const size_t SR = (size_t)h->S * h->ring_total;
+        Dev &d = h->d;
+    d.S = h->S; d.L = L; d.Nn = Nn; d.O = h->O; d.N = h->N; d.D = h->D; d.nb = h->nb; d.cbs = h->cbs;
+    d.n_dest = (int)h->dest_nodes.size(); d.maxl = maxl; d.n_rate_bins = h->B;
+    d.fixed_mode = h->fixed_mode; d.allow_uturn = cfg->allow_uturn; d.platoon = h->platoon;
+    d.g_link = h->g_link; d.g_node = h->g_node; d.g_rev = h->g_rev;
+    d.ring_total = h->ring_total; d.dt = h->dt; d.theta = cfg->dest_logit_coef; d.rate_bin_s = h->rate_bin_s;
+    d.tail = h->upload(h->tail); d.head = h->upload(h->head); d.lanes = h->upload(h->lanes);
+    h->linv_dev = h->upload(h->linv);
+    d.cap = h->upload(h->cap); d.ring_base = h->upload(h->ring_base);
+    d.length = h->upload(h->length);
+    std::vector<float> thr(L);
+    for (int j = 0; j < L; ++j) thr[j] = h->length[j] - 0.01f;
+    d.thr = h->upload(thr);
+    d.out_off = h->upload(h->out_off); d.out_lnk = h->upload(h->out_lnk);
+    d.in_off = h->upload(h->in_off); d.in_lnk = h->upload(h->in_lnk);
+    d.org_off = h->upload(h->org_off); d.org_list = h->upload(h->org_list);
+    d.det_off = h->upload(h->det_off); d.det_list = h->upload(h->det_list);
+    d.det_pos = h->upload(h->det_pos);
+    d.tff = h->upload(h->tff); d.dist = h->upload(h->dist);
+    d.agent_didx = h->upload(h->agent_didx); d.agent_dest = h->upload(h->agent_dest);
+    d.agent_origin = h->upload(h->agent_origin);
+    h->q_off_dev = h->upload(h->q_off);
+    h->q_list_dev = h->dalloc<int32_t>(h->q_list.size());
+    h->q_dest_dev = h->dalloc<int32_t>(h->q_list.size());
+    h->q_didx_dev = h->dalloc<int32_t>(h->q_list.size());
+    h->q_rstep_dev = h->dalloc<int64_t>(h->q_rstep.size());
+    h->org_pad_dev = h->dalloc<int2>((size_t)Nn * h->max_org);
+    upload_queues(h);
+    d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
+    d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev; d.org_pad = h->org_pad_dev;
+    d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
+    d.max_in = h->max_in; d.max_out = h->max_out; d.max_org = h->max_org;
+    d.seed = h->upload(h->seeds);
+    // parameters, scenario-major
+    auto rep = [&](const std::vector<float> &v) {
+        std::vector<float> r((size_t)h->S * v.size());
+        for (int s = 0; s < h->S; ++s) std::copy(v.begin(), v.end(), r.begin() + (size_t)s * v.size());
+        return r;
+    };
+    h->p_u = h->upload(rep(h->free_speed)); h->p_kappa = h->upload(rep(h->jam_density));
+    h->p_beta = h->upload(rep(h->beta)); h->p_alpha = h->upload(rep(h->alpha)); h->p_cost = h->upload(rep(h->cost));
+    h->p_capm = h->upload(rep(std::vector<float>(L, 1.f)));
+    h->p_rates = h->fixed_mode ? h->dalloc<float>(1) : h->upload(rep(h->rates));
+    h->capacity_dev = h->upload(h->capacity);
+    d.u = h->p_u; d.kappa = h->p_kappa; d.alpha = h->p_alpha; d.rates = h->p_rates;
+    h->vfree = h->dalloc<float>(SL); h->spacing = h->dalloc<float>(SL);
+    h->util = h->dalloc<double>(SL); h->acc = h->dalloc<double>(SL);
+    d.vfree = h->vfree; d.spacing = h->spacing; d.util = h->util; d.acc = h->acc;
+    // state
+    d.ring_pos = h->dalloc<float>(SR); d.ring_agent = h->dalloc<int32_t>(SR);
+    d.rhead = h->dalloc<int32_t>(SL); d.rtail = h->dalloc<int32_t>(SL);
+    d.B = h->dalloc<double>(SL); d.E = h->dalloc<int64_t>(SL);
+    d.slots = h->dalloc<int32_t>(SL); d.nheads = h->dalloc<int32_t>(SL);
+    d.head_rec = h->dalloc<int4>(SL * maxl);
+    d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
+    d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
+    d.Dacc = h->dalloc<double>(SO); d.rel_ptr = h->dalloc<int32_t>(SO); d.dep_ptr = h->dalloc<int32_t>(SO);
+    d.ctr = h->dalloc<int64_t>((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
+    d.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
+    d.err = h->dalloc<int32_t>(sim::ERR_N);
+    h->ttt_dev = h->dalloc<double>(h->S);
+    h->counts_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
+    if (h->record) {
+        h->ckpts.resize(n_ck + 1);
+        for (auto &c : h->ckpts) ckpt_alloc(h, c);
+        d.tape_pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
+        d.tape_agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
+        d.tape_head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+        d.tape_tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+        d.adj_ring = h->dalloc<float>(SR); d.depg = h->dalloc<float>(SN);
+        d.tape_dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
+        d.gu = h->dalloc<double>(SL); d.gk = h->dalloc<double>(SL);
+        h->gQ_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
+        h->gx_dev = h->dalloc<float>(SN);
+        h->gT_dev = h->dalloc<double>(h->S);
+        h->grad_tmp = h->dalloc<float>(std::max(SL, (size_t)h->S * h->O * std::max(h->B, 1)));
+    }
+    build_classes(h);
+    derive(h);
+    zero_state(h);
+    HIPCHK(hipStreamSynchronize(h->stream));
+}
+
 }  // namespace
+
+// ===========================================================================
+// internal hooks for the serving loop (sim_serve.cpp)
+// ===========================================================================
+namespace sim {
+
+sim_t *host_prepare(const sim_network *net, const sim_demand *dem, const sim_config *cfg, int device,
+                    int *code, std::string *err)
+{
+    sim_t *h = nullptr;
+    try {
+        h = new sim_t();
+        h->device = device;
+        sim_config c = *cfg;
+        c.mem_budget_bytes = 0;
+        prepare_host(h, net, dem, &c);
+        h->theta_cfg = cfg->dest_logit_coef;
+        h->uturn_cfg = cfg->allow_uturn;
+        *code = SIM_OK;
+        return h;
+    } catch (const InvalidArg &e) {
+        delete h;
+        *code = e.code;
+        *err = e.msg;
+    } catch (const std::bad_alloc &) {
+        delete h;
+        *code = SIM_ENOMEM;
+        *err = "host allocation failed";
+    }
+    return nullptr;
+}
+
+size_t footprint_of(const sim_t *h) { return h->footprint; }
+
+int device_attach(sim_t *h, hipStream_t stream, std::string *err)
+{
+    try {
+        h->stream = stream;
+        HIPCHK(hipSetDevice(h->device));
+        sim_config c{};
+        c.dest_logit_coef = h->theta_cfg;
+        c.allow_uturn = h->uturn_cfg;
+        allocate_device(h, &c);
+        return SIM_OK;
+    } catch (const InvalidArg &e) {
+        *err = e.msg;
+        return e.code;
+    } catch (const HipError &e) {
+        *err = e.msg;
+        return SIM_EDEVICE;
+    } catch (const std::bad_alloc &) {
+        *err = "host allocation failed";
+        return SIM_ENOMEM;
+    }
+}
+
+// enqueue T steps on the handle's stream without waiting
+int rollout_enqueue(sim_t *h, int T, std::string *err)
+{
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        for (int k = 0; k < T; ++k) do_step(h, -1);
+        return SIM_OK;
+    } catch (const HipError &e) {
+        *err = e.msg;
+        return SIM_EDEVICE;
+    }
+}
+
+// enqueue the observables into caller buffers (host memory, pinned for asynchrony)
+int results_enqueue(sim_t *h, float *counts, double *ttt, int64_t *vsteps, std::string *err)
+{
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        if (counts && h->D * h->nb > 0) {
+            sim::launch_counts(h->d, h->counts_dev, h->stream);
+            HIPCHK(hipMemcpyAsync(counts, h->counts_dev, (size_t)h->S * h->D * h->nb * 4, hipMemcpyDeviceToHost, h->stream));
+        }
+        int64_t *dv = h->dalloc_scratch_i64(h->S);
+        sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->stream);
+        if (ttt) HIPCHK(hipMemcpyAsync(ttt, h->ttt_dev, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
+        if (vsteps) HIPCHK(hipMemcpyAsync(vsteps, dv, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipGetLastError());
+        return SIM_OK;
+    } catch (const HipError &e) {
+        *err = e.msg;
+        return SIM_EDEVICE;
+    } catch (const InvalidArg &e) {
+        *err = e.msg;
+        return e.code;
+    }
+}
+
+int device_errors(sim_t *h, std::string *err)
+{
+    try {
+        check_device_errors(h);
+        return SIM_OK;
+    } catch (const InvalidArg &e) {
+        *err = e.msg;
+        return e.code;
+    } catch (const HipError &e) {
+        *err = e.msg;
+        return SIM_EDEVICE;
+    }
+}
+
+int counts_size(const sim_t *h) { return h->S * h->D * h->nb; }
+int scenarios_of(const sim_t *h) { return h->S; }
+void destroy_handle(sim_t *h) { delete h; }
+
+}  // namespace sim
 
 // ===========================================================================
 // C-ABI
@@ -469,254 +925,8 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
         HIPCHK(hipGetDeviceCount(&ndev));
         if (hip_device < 0 || hip_device >= ndev) fail(SIM_EINVAL, "bad device index");
         HIPCHK(hipSetDevice(hip_device));
-
-        // ---------------- validate and copy ----------------
-        const int L = net->n_links, Nn = net->n_nodes;
-        if (L <= 0 || Nn <= 0) fail(SIM_EINVAL, "network needs nodes and links");
-        if (!net->tail || !net->head || !net->lanes || !net->length || !net->free_speed || !net->jam_density ||
-            !net->capacity)
-            fail(SIM_EINVAL, "missing link array");
-        h->L = L; h->Nn = Nn;
-        h->tail.assign(net->tail, net->tail + L);
-        h->head.assign(net->head, net->head + L);
-        h->lanes.assign(net->lanes, net->lanes + L);
-        h->length.assign(net->length, net->length + L);
-        h->free_speed.assign(net->free_speed, net->free_speed + L);
-        h->jam_density.assign(net->jam_density, net->jam_density + L);
-        h->capacity.assign(net->capacity, net->capacity + L);
-        h->beta = net->beta ? std::vector<float>(net->beta, net->beta + L) : std::vector<float>(L, 0.f);
-        h->alpha = net->alpha ? std::vector<float>(net->alpha, net->alpha + L) : std::vector<float>(L, 1.f);
-        h->cost = net->cost ? std::vector<float>(net->cost, net->cost + L) : std::vector<float>(L, 1.f);
-        int maxl = 1;
-        for (int j = 0; j < L; ++j) {
-            if (h->tail[j] < 0 || h->tail[j] >= Nn || h->head[j] < 0 || h->head[j] >= Nn)
-                fail(SIM_EINVAL, "link " + std::to_string(j) + ": node index out of range");
-            if (h->lanes[j] < 1 || h->lanes[j] > sim::kMaxLanes) fail(SIM_EINVAL, "lanes must be in [1, 8]");
-            if (!(h->length[j] > 0.02f) || !(h->free_speed[j] > 0.f) || !(h->jam_density[j] > 0.f) ||
-                !(h->capacity[j] >= 0.f) || !(h->cost[j] > 0.f) || !std::isfinite(h->length[j]) ||
-                !std::isfinite(h->free_speed[j]) || !std::isfinite(h->capacity[j]))
-                fail(SIM_EINVAL, "link " + std::to_string(j) + ": non-positive or non-finite length/speed/density/cost");
-            maxl = std::max(maxl, h->lanes[j]);
-        }
-        h->maxl = maxl;
-        h->O = net->n_origins;
-        if (h->O < 0 || (h->O > 0 && !net->origin_node)) fail(SIM_EINVAL, "bad origins");
-        h->origin_node.assign(net->origin_node, net->origin_node + h->O);
-        for (int k = 0; k < h->O; ++k)
-            if (h->origin_node[k] < 0 || h->origin_node[k] >= Nn) fail(SIM_EINVAL, "origin node out of range");
-        h->D = net->n_detectors;
-        if (h->D < 0 || (h->D > 0 && (!net->detector_link || !net->detector_pos))) fail(SIM_EINVAL, "bad detectors");
-        h->det_link.assign(net->detector_link, net->detector_link + h->D);
-        h->det_pos.assign(net->detector_pos, net->detector_pos + h->D);
-        for (int k = 0; k < h->D; ++k) {
-            const int j = h->det_link[k];
-            if (j < 0 || j >= L) fail(SIM_EINVAL, "detector link out of range");
-            if (!(h->det_pos[k] > 0.f) || !(h->det_pos[k] <= h->length[j] - 0.01f))
-                fail(SIM_EINVAL, "detector position must lie in (0, length - 0.01]");
-        }
-        h->N = dem->n_agents;
-        if (h->N < 0 || (h->N > 0 && (!dem->agent_origin || !dem->agent_dest))) fail(SIM_EINVAL, "bad agents");
-        h->agent_origin.assign(dem->agent_origin, dem->agent_origin + h->N);
-        h->agent_dest.assign(dem->agent_dest, dem->agent_dest + h->N);
-        h->fixed_mode = dem->ready_time != nullptr;
-        if (h->fixed_mode) h->ready.assign(dem->ready_time, dem->ready_time + h->N);
-        else {
-            h->B = dem->n_rate_bins;
-            h->rate_bin_s = dem->rate_bin_s;
-            if (h->B <= 0 || !dem->rates || !(dem->rate_bin_s > 0)) fail(SIM_EINVAL, "rate mode needs rates and bins");
-            h->rates.assign(dem->rates, dem->rates + (size_t)h->O * h->B);
-            for (float r : h->rates)
-                if (!(r >= 0.f) || !std::isfinite(r)) fail(SIM_EINVAL, "rates must be finite and >= 0");
-        }
-        for (int i = 0; i < h->N; ++i) {
-            if (h->agent_origin[i] < 0 || h->agent_origin[i] >= h->O) fail(SIM_EINVAL, "agent origin out of range");
-            if (h->agent_dest[i] < 0 || h->agent_dest[i] >= Nn) fail(SIM_EINVAL, "agent destination out of range");
-            if (h->agent_dest[i] == h->origin_node[h->agent_origin[i]])
-                fail(SIM_EINVAL, "agent destination equals its origin node");
-        }
-        h->dt = cfg->dt;
-        h->platoon = cfg->platoon;
-        if (!(cfg->dt > 0) || cfg->platoon < 1) fail(SIM_EINVAL, "dt > 0 and platoon >= 1 required");
-        if (!h->fixed_mode) {
-            const double k = h->rate_bin_s / h->dt;
-            if (std::fabs(k - std::round(k)) > 1e-9) fail(SIM_EINVAL, "rate bins must be a whole number of steps");
-        }
-        h->S = cfg->n_scenarios;
-        if (h->S < 1) fail(SIM_EINVAL, "n_scenarios >= 1");
-        h->cbs = cfg->count_bin_steps;
-        h->nb = cfg->n_count_bins;
-        if (h->nb < 0 || (h->nb > 0 && h->cbs < 1)) fail(SIM_EINVAL, "count bins need count_bin_steps >= 1");
-        h->ckpt_every = cfg->ckpt_every > 0 ? cfg->ckpt_every : 60;
-        h->max_steps = cfg->max_steps;
-        h->record = cfg->record_for_backward;
-        if (h->record && h->max_steps <= 0) fail(SIM_EINVAL, "record_for_backward needs max_steps > 0");
-        h->seeds.resize(h->S);
-        for (int s = 0; s < h->S; ++s) h->seeds[s] = cfg->scenario_seed ? cfg->scenario_seed[s] : cfg->seed + (uint64_t)s;
-
-        // ---------------- graph ----------------
-        build_csr(Nn, h->tail, h->out_off, h->out_lnk);
-        build_csr(Nn, h->head, h->in_off, h->in_lnk);
-        build_csr(Nn, h->origin_node, h->org_off, h->org_list);
-        build_csr(L, h->det_link, h->det_off, h->det_list);
-        for (int v = 0; v < Nn; ++v) {
-            const int nc = (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]);
-            if (nc > sim::kWave) fail(SIM_EUNSUPPORTED, "node " + std::to_string(v) + ": more than 64 merge candidates");
-            if (h->out_off[v + 1] - h->out_off[v] > sim::kWave) fail(SIM_EUNSUPPORTED, "node out-degree above 64");
-        }
-        for (int j = 0; j < L; ++j)
-            if (h->det_off[j + 1] - h->det_off[j] > sim::kMaxDetPerLink) fail(SIM_EUNSUPPORTED, "more than 4 detectors on a link");
-        // lanes per node: the smallest group that holds every node's candidates and out-links
-        int need = 1;
-        for (int v = 0; v < Nn; ++v) {
-            need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]));
-            need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
-        }
-        h->g_node = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
-        for (int v = 0; v < Nn; ++v) {
-            h->max_in = std::max(h->max_in, h->in_off[v + 1] - h->in_off[v]);
-            h->max_out = std::max(h->max_out, h->out_off[v + 1] - h->out_off[v]);
-            h->max_org = std::max(h->max_org, h->org_off[v + 1] - h->org_off[v]);
-        }
-        if (h->max_in > 255 || h->max_out > 255 || h->max_org > 255) fail(SIM_EUNSUPPORTED, "node degree above 255");
-        h->node_cnt.resize(Nn);
-        h->in_pad.assign((size_t)Nn * h->max_in, -1);
-        h->out_pad.assign((size_t)Nn * h->max_out, -1);
-        for (int v = 0; v < Nn; ++v) {
-            const int di = h->in_off[v + 1] - h->in_off[v], dout = h->out_off[v + 1] - h->out_off[v];
-            const int no = h->org_off[v + 1] - h->org_off[v];
-            h->node_cnt[v] = di | (dout << 8) | (no << 16);
-            for (int k = 0; k < di; ++k) h->in_pad[(size_t)v * h->max_in + k] = h->in_lnk[h->in_off[v] + k];
-            for (int k = 0; k < dout; ++k) h->out_pad[(size_t)v * h->max_out + k] = h->out_lnk[h->out_off[v] + k];
-        }
-        // rings: a link holds at most lanes * (floor(L / spacing) + 1) agents; two extra rows of slack
-        h->cap.resize(L);
-        h->ring_base.resize(L);
-        h->min_spacing.resize(L);
-        int64_t tot = 0;
-        for (int j = 0; j < L; ++j) {
-            const float sp = (float)h->platoon / h->jam_density[j];
-            h->min_spacing[j] = sp;
-            const double rows = std::floor((double)h->length[j] / (double)sp) + 3.0;
-            const double c = rows * h->lanes[j];
-            if (c > 1e8) fail(SIM_EUNSUPPORTED, "link too long for its jam spacing");
-            h->cap[j] = (int32_t)c;
-            h->ring_base[j] = (int32_t)tot;
-            tot += h->cap[j];
-            if (tot > (int64_t)1 << 30) fail(SIM_EUNSUPPORTED, "ring storage above 2^30 slots");
-        }
-        h->ring_total = tot;
-        // destinations, numbered in node order
-        std::vector<int32_t> didx(Nn, -1);
-        for (int i = 0; i < h->N; ++i) didx[h->agent_dest[i]] = 0;
-        for (int v = 0; v < Nn; ++v)
-            if (didx[v] == 0) { didx[v] = (int32_t)h->dest_nodes.size(); h->dest_nodes.push_back(v); }
-        h->agent_didx.resize(h->N);
-        for (int i = 0; i < h->N; ++i) h->agent_didx[i] = didx[h->agent_dest[i]];
-        shortest_times(h);
-        for (int i = 0; i < h->N; ++i) {
-            const double dd = h->dist[(size_t)h->agent_didx[i] * Nn + h->origin_node[h->agent_origin[i]]];
-            if (!(dd < std::numeric_limits<double>::infinity()))
-                fail(SIM_EINVAL, "agent " + std::to_string(i) + ": destination unreachable from its origin");
-        }
-        h->tff.resize(L);
-        for (int m = 0; m < L; ++m) h->tff[m] = (double)h->length[m] / (double)h->free_speed[m];
-        build_queues(h, nullptr);
-
-        // ---------------- memory budget ----------------
-        const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
-        const size_t SR = (size_t)h->S * h->ring_total;
-        size_t bytes = SR * 8 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
-                       h->dist.size() * 8 + (size_t)h->S * h->D * h->nb * 8;
-        int n_ck = 0;
-        if (h->record) {
-            n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
-            h->W = h->ckpt_every;
-            bytes += (size_t)n_ck * (SR * 8 + SL * 24 + SO * 16 + SN);
-            bytes += (size_t)(h->W + 1) * (SR * 8 + SL * 8) + SN * 8 + SL * 16;
-        }
-        if (cfg->mem_budget_bytes && bytes > cfg->mem_budget_bytes)
-            fail(SIM_ENOMEM, "footprint " + std::to_string(bytes) + " B exceeds the memory budget");
-
-        // ---------------- device ----------------
-        Dev &d = h->d;
-        d.S = h->S; d.L = L; d.Nn = Nn; d.O = h->O; d.N = h->N; d.D = h->D; d.nb = h->nb; d.cbs = h->cbs;
-        d.n_dest = (int)h->dest_nodes.size(); d.maxl = maxl; d.n_rate_bins = h->B;
-        d.fixed_mode = h->fixed_mode; d.allow_uturn = cfg->allow_uturn; d.platoon = h->platoon;
-        d.g_link = h->g_link; d.g_node = h->g_node; d.g_rev = h->g_rev;
-        d.ring_total = h->ring_total; d.dt = h->dt; d.theta = cfg->dest_logit_coef; d.rate_bin_s = h->rate_bin_s;
-        d.tail = h->upload(h->tail); d.head = h->upload(h->head); d.lanes = h->upload(h->lanes);
-        d.cap = h->upload(h->cap); d.ring_base = h->upload(h->ring_base);
-        d.length = h->upload(h->length);
-        std::vector<float> thr(L);
-        for (int j = 0; j < L; ++j) thr[j] = h->length[j] - 0.01f;
-        d.thr = h->upload(thr);
-        d.out_off = h->upload(h->out_off); d.out_lnk = h->upload(h->out_lnk);
-        d.in_off = h->upload(h->in_off); d.in_lnk = h->upload(h->in_lnk);
-        d.org_off = h->upload(h->org_off); d.org_list = h->upload(h->org_list);
-        d.det_off = h->upload(h->det_off); d.det_list = h->upload(h->det_list);
-        d.det_pos = h->upload(h->det_pos);
-        d.tff = h->upload(h->tff); d.dist = h->upload(h->dist);
-        d.agent_didx = h->upload(h->agent_didx); d.agent_dest = h->upload(h->agent_dest);
-        d.agent_origin = h->upload(h->agent_origin);
-        h->q_off_dev = h->upload(h->q_off);
-        h->q_list_dev = h->dalloc<int32_t>(h->q_list.size());
-        h->q_dest_dev = h->dalloc<int32_t>(h->q_list.size());
-        h->q_didx_dev = h->dalloc<int32_t>(h->q_list.size());
-        h->q_rstep_dev = h->dalloc<int64_t>(h->q_rstep.size());
-        h->org_pad_dev = h->dalloc<int2>((size_t)Nn * h->max_org);
-        upload_queues(h);
-        d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
-        d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev; d.org_pad = h->org_pad_dev;
-        d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
-        d.max_in = h->max_in; d.max_out = h->max_out; d.max_org = h->max_org;
-        d.seed = h->upload(h->seeds);
-        // parameters, scenario-major
-        auto rep = [&](const std::vector<float> &v) {
-            std::vector<float> r((size_t)h->S * v.size());
-            for (int s = 0; s < h->S; ++s) std::copy(v.begin(), v.end(), r.begin() + (size_t)s * v.size());
-            return r;
-        };
-        h->p_u = h->upload(rep(h->free_speed)); h->p_kappa = h->upload(rep(h->jam_density));
-        h->p_beta = h->upload(rep(h->beta)); h->p_alpha = h->upload(rep(h->alpha)); h->p_cost = h->upload(rep(h->cost));
-        h->p_capm = h->upload(rep(std::vector<float>(L, 1.f)));
-        h->p_rates = h->fixed_mode ? h->dalloc<float>(1) : h->upload(rep(h->rates));
-        h->capacity_dev = h->upload(h->capacity);
-        d.u = h->p_u; d.kappa = h->p_kappa; d.alpha = h->p_alpha; d.rates = h->p_rates;
-        h->vfree = h->dalloc<float>(SL); h->spacing = h->dalloc<float>(SL);
-        h->util = h->dalloc<double>(SL); h->acc = h->dalloc<double>(SL);
-        d.vfree = h->vfree; d.spacing = h->spacing; d.util = h->util; d.acc = h->acc;
-        // state
-        d.ring_pos = h->dalloc<float>(SR); d.ring_agent = h->dalloc<int32_t>(SR);
-        d.rhead = h->dalloc<int32_t>(SL); d.rtail = h->dalloc<int32_t>(SL);
-        d.B = h->dalloc<double>(SL); d.E = h->dalloc<int64_t>(SL);
-        d.slots = h->dalloc<int32_t>(SL); d.nheads = h->dalloc<int32_t>(SL);
-        d.head_rec = h->dalloc<int4>(SL * maxl);
-        d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
-        d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
-        d.Dacc = h->dalloc<double>(SO); d.rel_ptr = h->dalloc<int32_t>(SO); d.dep_ptr = h->dalloc<int32_t>(SO);
-        d.ctr = h->dalloc<int64_t>((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
-        d.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
-        d.err = h->dalloc<int32_t>(sim::ERR_N);
-        h->ttt_dev = h->dalloc<double>(h->S);
-        h->counts_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
-        if (h->record) {
-            h->ckpts.resize(n_ck + 1);
-            for (auto &c : h->ckpts) ckpt_alloc(h, c);
-            d.tape_pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
-            d.tape_agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
-            d.tape_head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
-            d.tape_tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
-            d.adj = h->dalloc<float>(SN); d.depg = h->dalloc<float>(SN);
-            d.gu = h->dalloc<double>(SL); d.gk = h->dalloc<double>(SL);
-            h->gQ_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
-            h->gx_dev = h->dalloc<float>(SN);
-            h->gT_dev = h->dalloc<double>(h->S);
-            h->grad_tmp = h->dalloc<float>(std::max(SL, (size_t)h->S * h->O * std::max(h->B, 1)));
-        }
-        build_classes(h);
-        derive(h);
-        zero_state(h);
-        HIPCHK(hipStreamSynchronize(h->stream));
+        prepare_host(h, net, dem, cfg);
+        allocate_device(h, cfg);
         *out = h;
         return SIM_OK;
     } catch (const InvalidArg &e) {
@@ -725,6 +935,28 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
     } catch (const HipError &e) {
         delete h;
         return record_error(nullptr, SIM_EDEVICE, e.msg);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return record_error(nullptr, SIM_ENOMEM, "host allocation failed");
+    }
+}
+
+int sim_footprint(const sim_network *net, const sim_demand *dem, const sim_config *cfg, size_t *bytes)
+{
+    if (!net || !dem || !cfg || !bytes) return record_error(nullptr, SIM_EINVAL, "null argument");
+    sim_t *h = nullptr;
+    try {
+        h = new sim_t();
+        h->device = -1;
+        sim_config c = *cfg;
+        c.mem_budget_bytes = 0;
+        prepare_host(h, net, dem, &c);
+        *bytes = h->footprint;
+        delete h;
+        return SIM_OK;
+    } catch (const InvalidArg &e) {
+        delete h;
+        return record_error(nullptr, e.code, e.msg);
     } catch (const std::bad_alloc &) {
         delete h;
         return record_error(nullptr, SIM_ENOMEM, "host allocation failed");
@@ -756,27 +988,24 @@ int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_d
         default: fail(SIM_EINVAL, "unknown parameter group");
         }
         if (n != per * h->S) fail(SIM_EINVAL, "expected " + std::to_string(per * h->S) + " values");
-        std::vector<float> host;
-        if (!on_device || which == SIM_P_KAPPA || which == SIM_P_U || which == SIM_P_COST || which == SIM_P_RATES) {
-            host.resize(n);
-            HIPCHK(hipMemcpyAsync(host.data(), values, n * 4, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
-            for (int64_t i = 0; i < n; ++i) {
-                const float v = host[i];
-                if (!std::isfinite(v)) fail(SIM_EINVAL, "non-finite parameter");
-                if ((which == SIM_P_U || which == SIM_P_KAPPA || which == SIM_P_COST) && !(v > 0.f))
-                    fail(SIM_EINVAL, "u, kappa and cost must be > 0");
-                if (which == SIM_P_RATES && !(v >= 0.f)) fail(SIM_EINVAL, "rates must be >= 0");
-                if (which == SIM_P_KAPPA) {
-                    const int j = (int)(i % h->L);
-                    if ((float)h->platoon / v < h->min_spacing[j])
-                        fail(SIM_EINVAL, "kappa above the value the link rings were sized for");
-                }
+        std::vector<float> host(n);
+        HIPCHK(hipMemcpyAsync(host.data(), values, n * 4, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (which != SIM_P_RATES) host = links_in(h, host.data());   // to the internal link order
+        for (int64_t i = 0; i < n; ++i) {
+            const float v = host[i];
+            if (!std::isfinite(v)) fail(SIM_EINVAL, "non-finite parameter");
+            if ((which == SIM_P_U || which == SIM_P_KAPPA || which == SIM_P_COST) && !(v > 0.f))
+                fail(SIM_EINVAL, "u, kappa and cost must be > 0");
+            if (which == SIM_P_RATES && !(v >= 0.f)) fail(SIM_EINVAL, "rates must be >= 0");
+            if (which == SIM_P_CAP_MULT && !(v >= 0.f)) fail(SIM_EINVAL, "capacity multipliers must be >= 0");
+            if (which == SIM_P_KAPPA) {
+                const int j = (int)(i % h->L);
+                if ((float)h->platoon / v < h->min_spacing[j])
+                    fail(SIM_EINVAL, "kappa above the value the link rings were sized for");
             }
-            HIPCHK(hipMemcpyAsync(dst, host.data(), n * 4, hipMemcpyHostToDevice, h->stream));
-        } else {
-            HIPCHK(hipMemcpyAsync(dst, values, n * 4, hipMemcpyDeviceToDevice, h->stream));
         }
+        HIPCHK(hipMemcpyAsync(dst, host.data(), n * 4, hipMemcpyHostToDevice, h->stream));
         derive(h);
         HIPCHK(hipStreamSynchronize(h->stream));
     });
@@ -798,13 +1027,14 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         if (h->t != 0) fail(SIM_ESTATE, "sim_place is only allowed at t = 0");
         if (n < 0 || (n > 0 && (!agent || !link || !pos))) fail(SIM_EINVAL, "bad placement arrays");
         std::vector<uint8_t> placed(h->N, 0);
-        std::vector<int32_t> cnt(h->L, 0);
+        std::vector<int32_t> cnt(h->L, 0), lk(n > 0 ? n : 1);
         for (int k = 0; k < n; ++k) {
             if (agent[k] < 0 || agent[k] >= h->N || placed[agent[k]]) fail(SIM_EINVAL, "bad or repeated agent");
             if (link[k] < 0 || link[k] >= h->L) fail(SIM_EINVAL, "bad link");
-            if (!(pos[k] >= 0.f) || !(pos[k] <= h->length[link[k]])) fail(SIM_EINVAL, "position outside the link");
+            lk[k] = h->linv[link[k]];
+            if (!(pos[k] >= 0.f) || !(pos[k] <= h->length[lk[k]])) fail(SIM_EINVAL, "position outside the link");
             placed[agent[k]] = 1;
-            if (++cnt[link[k]] > h->cap[link[k]]) fail(SIM_EINVAL, "too many agents placed on a link");
+            if (++cnt[lk[k]] > h->cap[lk[k]]) fail(SIM_EINVAL, "too many agents placed on a link");
         }
         // current (empty, t = 0) rings and per-agent arrays
         const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
@@ -824,7 +1054,7 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         HIPCHK(hipStreamSynchronize(h->stream));
         for (int s = 0; s < h->S; ++s) {
             for (int k = 0; k < n; ++k) {
-                const int j = link[k];
+                const int j = lk[k];
                 const size_t seg = (size_t)s * h->L + j;
                 const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (rt[seg] % h->cap[j]);
                 ra[slot] = agent[k];
@@ -915,7 +1145,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         if (dL_dcounts && nQ) { HIPCHK(hipMemcpyAsync(h->gQ_dev, dL_dcounts, nQ * 4, kin, st)); d.gQ = h->gQ_dev; }
         if (dL_dttt) { HIPCHK(hipMemcpyAsync(h->gT_dev, dL_dttt, h->S * 8, kin, st)); d.gT = h->gT_dev; }
         if (dL_dpos) { HIPCHK(hipMemcpyAsync(h->gx_dev, dL_dpos, SN * 4, kin, st)); d.gx = h->gx_dev; }
-        HIPCHK(hipMemsetAsync(d.adj, 0, SN * 4, st));
+        HIPCHK(hipMemsetAsync(d.adj_ring, 0, (size_t)h->S * h->ring_total * 4, st));
         HIPCHK(hipMemsetAsync(d.depg, 0, SN * 4, st));
         HIPCHK(hipMemsetAsync(d.gu, 0, SL * 8, st));
         HIPCHK(hipMemsetAsync(d.gk, 0, SL * 8, st));
@@ -948,11 +1178,11 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
         const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         if (param_mask & (1u << SIM_P_U)) {
-            sim::launch_d2f(d.gu, h->grad_tmp, SL, st);
+            sim::launch_gather_links(d.gu, h->linv_dev, h->grad_tmp, h->S, h->L, st);
             HIPCHK(hipMemcpyAsync(grads[SIM_P_U], h->grad_tmp, SL * 4, kout, st));
         }
         if (param_mask & (1u << SIM_P_KAPPA)) {
-            sim::launch_d2f(d.gk, h->grad_tmp, SL, st);
+            sim::launch_gather_links(d.gk, h->linv_dev, h->grad_tmp, h->S, h->L, st);
             HIPCHK(hipMemcpyAsync(grads[SIM_P_KAPPA], h->grad_tmp, SL * 4, kout, st));
         }
         if (param_mask & (1u << SIM_P_RATES)) {
@@ -991,7 +1221,7 @@ int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t 
                 for (int q = rh[seg]; q < rt[seg]; ++q) {
                     const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (q % h->cap[j]);
                     const size_t ga = (size_t)s * h->N + ra[slot];
-                    if (link) link[ga] = j;
+                    if (link) link[ga] = h->lperm[j];
                     if (pos) pos[ga] = rp[slot];
                     if (seq) seq[ga] = q;
                 }
@@ -1025,20 +1255,38 @@ int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq)
 {
     return guarded(h, [&] {
         const size_t SL = (size_t)h->S * h->L;
-        if (B) HIPCHK(hipMemcpyAsync(B, h->d.B, SL * 8, hipMemcpyDeviceToHost, h->stream));
-        if (E) HIPCHK(hipMemcpyAsync(E, h->d.E, SL * 8, hipMemcpyDeviceToHost, h->stream));
-        if (next_seq) HIPCHK(hipMemcpyAsync(next_seq, h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        std::vector<double> b(SL);
+        std::vector<int64_t> e(SL);
+        std::vector<int32_t> ns(SL);
+        HIPCHK(hipMemcpyAsync(b.data(), h->d.B, SL * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(e.data(), h->d.E, SL * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ns.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        // the device keeps the bucket before the end-of-step idle cap min(B, 1)
-        if (B) for (size_t i = 0; i < SL; ++i) B[i] = B[i] > 1.0 ? 1.0 : B[i];
+        for (int s = 0; s < h->S; ++s)
+            for (int jo = 0; jo < h->L; ++jo) {
+                const size_t o = (size_t)s * h->L + jo, i = (size_t)s * h->L + h->linv[jo];
+                // the device keeps the bucket before the end-of-step idle cap min(B, 1)
+                if (B) B[o] = b[i] > 1.0 ? 1.0 : b[i];
+                if (E) E[o] = e[i];
+                if (next_seq) next_seq[o] = ns[i];
+            }
     });
 }
 
 int sim_get_dist(sim_t *h, double *out, int32_t *n_dest)
 {
     return guarded(h, [&] {
-        if (n_dest) *n_dest = (int32_t)h->dest_nodes.size();
-        if (out) std::memcpy(out, h->dist.data(), h->dist.size() * 8);
+        const int nd = (int)h->dest_nodes.size();
+        if (n_dest) *n_dest = nd;
+        if (out) {
+            // rows in increasing caller node id of the destination, columns caller node ids
+            std::vector<std::pair<int, int>> rows(nd);
+            for (int k = 0; k < nd; ++k) rows[k] = {h->nperm[h->dest_nodes[k]], k};
+            std::sort(rows.begin(), rows.end());
+            for (int r = 0; r < nd; ++r)
+                for (int vo = 0; vo < h->Nn; ++vo)
+                    out[(size_t)r * h->Nn + vo] = h->dist[(size_t)rows[r].second * h->Nn + h->ninv[vo]];
+        }
     });
 }
 

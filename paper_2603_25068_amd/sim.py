@@ -86,6 +86,16 @@ def lib():
         "sim_get_schedule": ([vp, vp, vp, vp], C.c_int),
         "sim_set_timing": ([vp, C.c_int], C.c_int),
         "sim_get_timing": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
+        "sim_footprint": ([vp, vp, vp, vp], C.c_int),
+        "srv_create": ([C.c_int, C.c_size_t, i32, i32, vp], C.c_int),
+        "srv_submit": ([vp, vp, vp, vp, i32, vp], C.c_int),
+        "srv_poll": ([vp, i64, vp], C.c_int),
+        "srv_wait": ([vp, i64, C.c_double, vp], C.c_int),
+        "srv_result": ([vp, i64, vp, vp, vp, vp], C.c_int),
+        "srv_error": ([vp, i64], C.c_char_p),
+        "srv_cancel": ([vp, i64], C.c_int),
+        "srv_stats": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "srv_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -99,7 +109,9 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_segsort",
-            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing"]
+            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint",
+            "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
+            "srv_stats", "srv_destroy"]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -112,6 +124,40 @@ def _f32(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, np.int32)
+
+
+def _marshal(w, S: int, seeds, steps: int, ckpt_every, max_steps, record: bool, mem_budget_bytes: int):
+    """The C structures of a workload (and the arrays they point into, which
+    the caller keeps alive while the structures are in use)."""
+    net, dem, cfg = w.net, w.dem, w.cfg
+    cbs = int(cfg.count_bin_steps)
+    n_count_bins = steps // cbs if cbs > 0 else 0
+    K = {
+        "tail": _i32(net.tail), "head": _i32(net.head), "lanes": _i32(net.lanes),
+        "length": _f32(net.length), "free_speed": _f32(net.free_speed), "jam_density": _f32(net.jam_density),
+        "capacity": _f32(net.capacity), "beta": _f32(net.beta), "alpha": _f32(net.alpha), "cost": _f32(net.cost),
+        "origin_node": _i32(net.origin_node), "detector_link": _i32(net.detector_link),
+        "detector_pos": _f32(net.detector_pos), "agent_origin": _i32(dem.agent_origin),
+        "agent_dest": _i32(dem.agent_dest),
+    }
+    if dem.ready_time is not None:
+        K["ready_time"] = _f32(dem.ready_time)
+    else:
+        K["rates"] = _f32(dem.rates)
+    if seeds is not None:
+        K["seeds"] = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    n = _Network(net.n_nodes, net.n_links, _p(K["tail"]), _p(K["head"]), _p(K["lanes"]), _p(K["length"]),
+                 _p(K["free_speed"]), _p(K["jam_density"]), _p(K["capacity"]), _p(K["beta"]), _p(K["alpha"]),
+                 _p(K["cost"]), net.n_origins, _p(K["origin_node"]), net.n_detectors, _p(K["detector_link"]),
+                 _p(K["detector_pos"]))
+    d = _Demand(dem.n_agents, _p(K["agent_origin"]), _p(K["agent_dest"]), _p(K.get("ready_time")),
+                dem.n_rate_bins, float(dem.rate_bin_s), _p(K.get("rates")))
+    c = _Config(float(cfg.dt), int(cfg.platoon), float(cfg.gumbel_tau), float(cfg.dest_logit_coef),
+                float(cfg.big_m), int(cfg.seed) & (2 ** 64 - 1), _p(K.get("seeds")), int(S),
+                int(ckpt_every or cfg.ckpt_every), cbs, n_count_bins,
+                int(max_steps if max_steps is not None else steps), int(cfg.allow_uturn), int(record),
+                int(mem_budget_bytes))
+    return n, d, c, K
 
 
 class Simulator:
@@ -136,32 +182,8 @@ class Simulator:
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
-        K = {
-            "tail": _i32(net.tail), "head": _i32(net.head), "lanes": _i32(net.lanes),
-            "length": _f32(net.length), "free_speed": _f32(net.free_speed), "jam_density": _f32(net.jam_density),
-            "capacity": _f32(net.capacity), "beta": _f32(net.beta), "alpha": _f32(net.alpha), "cost": _f32(net.cost),
-            "origin_node": _i32(net.origin_node), "detector_link": _i32(net.detector_link),
-            "detector_pos": _f32(net.detector_pos), "agent_origin": _i32(dem.agent_origin),
-            "agent_dest": _i32(dem.agent_dest),
-        }
-        if dem.ready_time is not None:
-            K["ready_time"] = _f32(dem.ready_time)
-        else:
-            K["rates"] = _f32(dem.rates)
-        if seeds is not None:
-            K["seeds"] = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
-        self._keep = K
-        n = _Network(net.n_nodes, net.n_links, _p(K["tail"]), _p(K["head"]), _p(K["lanes"]), _p(K["length"]),
-                     _p(K["free_speed"]), _p(K["jam_density"]), _p(K["capacity"]), _p(K["beta"]), _p(K["alpha"]),
-                     _p(K["cost"]), net.n_origins, _p(K["origin_node"]), net.n_detectors, _p(K["detector_link"]),
-                     _p(K["detector_pos"]))
-        d = _Demand(dem.n_agents, _p(K["agent_origin"]), _p(K["agent_dest"]), _p(K.get("ready_time")),
-                    dem.n_rate_bins, float(dem.rate_bin_s), _p(K.get("rates")))
-        c = _Config(float(cfg.dt), int(cfg.platoon), float(cfg.gumbel_tau), float(cfg.dest_logit_coef),
-                    float(cfg.big_m), int(cfg.seed) & (2 ** 64 - 1), _p(K.get("seeds")), self.S,
-                    int(ckpt_every or cfg.ckpt_every), cbs, self.n_count_bins,
-                    int(max_steps if max_steps is not None else self.steps), int(cfg.allow_uturn), int(record),
-                    int(mem_budget_bytes))
+        n, d, c, self._keep = _marshal(w, self.S, seeds, self.steps, ckpt_every, max_steps, record,
+                                       mem_budget_bytes)
         h = C.c_void_p()
         rc = self._L.sim_create(C.byref(n), C.byref(d), C.byref(c), device, C.c_void_p(stream.cuda_stream),
                                 C.byref(h))
@@ -342,6 +364,105 @@ class Simulator:
         self._chk(self._L.sim_get_timing(self._h, _p(ms), _p(n), 4, int(reset)))
         names = ("link", "node", "reverse", "copy")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+
+
+SRV_QUEUED, SRV_RUNNING, SRV_DONE, SRV_FAILED, SRV_CANCELLED = 0, 1, 2, 3, 4
+
+
+def footprint(w, n_scenarios: int = 1, steps: Optional[int] = None, record: bool = False) -> int:
+    """Device bytes sim_create would allocate for this workload (host-only)."""
+    L = lib()
+    T = int(steps if steps is not None else w.cfg.steps)
+    n, d, c, keep = _marshal(w, n_scenarios, None, T, None, None, record, 0)
+    out = C.c_size_t()
+    rc = L.sim_footprint(C.byref(n), C.byref(d), C.byref(c), C.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, "sim_footprint rejected the workload")
+    return int(out.value)
+
+
+class Server:
+    """Continuous-batching server of forward rollouts (srv_* in sim.h).
+
+    device = -1 selects the host-only executor (admission and failure logic
+    without a GPU; observables are zero)."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 8 << 30, max_slots: int = 8, chunk_steps: int = 60):
+        self._L = lib()
+        h = C.c_void_p()
+        rc = self._L.srv_create(int(device), int(mem_budget_bytes), int(max_slots), int(chunk_steps), C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, "srv_create failed")
+        self._h = h
+        self._meta = {}
+
+    def submit(self, w, steps: Optional[int] = None, n_scenarios: int = 1, seeds: Optional[Sequence[int]] = None) -> int:
+        T = int(steps if steps is not None else w.cfg.steps)
+        n, d, c, keep = _marshal(w, n_scenarios, seeds, T, None, T, False, 0)
+        t = C.c_int64()
+        rc = self._L.srv_submit(self._h, C.byref(n), C.byref(d), C.byref(c), T, C.byref(t))
+        if rc != SIM_OK:
+            raise SimError(rc, "srv_submit failed")
+        nb = T // int(w.cfg.count_bin_steps) if int(w.cfg.count_bin_steps) > 0 else 0
+        self._meta[t.value] = (int(n_scenarios), int(w.net.n_detectors), nb)
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int()
+        rc = self._L.srv_poll(self._h, ticket, C.byref(st))
+        if rc != SIM_OK:
+            raise SimError(rc, "unknown ticket")
+        return st.value
+
+    def wait(self, ticket: int, timeout_s: float = 600.0) -> int:
+        st = C.c_int()
+        rc = self._L.srv_wait(self._h, ticket, float(timeout_s), C.byref(st))
+        if rc != SIM_OK:
+            raise SimError(rc, "unknown ticket")
+        return st.value
+
+    def result(self, ticket: int):
+        """(counts [S x det x bins], total travel time [S], vehicle-steps [S], latency s)."""
+        S, D, nb = self._meta[ticket]
+        counts = np.zeros((S, D, nb), np.float32)
+        ttt = np.zeros(S, np.float64)
+        vs = np.zeros(S, np.int64)
+        lat = C.c_double()
+        rc = self._L.srv_result(self._h, ticket, _p(counts), _p(ttt), _p(vs), C.byref(lat))
+        if rc != SIM_OK:
+            raise SimError(rc, self.error(ticket))
+        return counts, ttt, vs, lat.value
+
+    def error(self, ticket: int) -> str:
+        return self._L.srv_error(self._h, ticket).decode()
+
+    def cancel(self, ticket: int):
+        self._L.srv_cancel(self._h, ticket)
+
+    def stats(self) -> dict:
+        p50, p99, vps = C.c_double(), C.c_double(), C.c_double()
+        done, mr = C.c_int64(), C.c_int64()
+        self._L.srv_stats(self._h, C.byref(p50), C.byref(p99), C.byref(vps), C.byref(done), C.byref(mr))
+        return {"p50_s": p50.value, "p99_s": p99.value, "vehicle_steps_per_s": vps.value,
+                "completed": done.value, "max_running": mr.value}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.srv_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def make_rollout_function():

@@ -10,12 +10,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "sim.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:int|const char \*)\s*(sim_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(?:int|const char \*)\s*((?:sim|srv)_[a-z_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for n in ("sim_create", "sim_destroy", "sim_step", "sim_rollout", "sim_backward", "sim_set_params"):
+    for n in ("sim_create", "sim_destroy", "sim_step", "sim_rollout", "sim_backward", "sim_set_params",
+              "srv_create", "srv_submit", "srv_result", "srv_destroy"):
         assert n in names
 
 
