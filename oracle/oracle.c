@@ -140,7 +140,7 @@ typedef struct {
 
 /* growable arrays for the decision log */
 typedef struct { int32_t agent, link, leader, branch, capped; double x0, x1; } cf_rec;
-typedef struct { int32_t agent, kind, from, to, tok_k; double tstar, bacc; int32_t rate_bin, qidx; int64_t cfi; int32_t rel_t; } mv_rec;
+typedef struct { int32_t agent, kind, from, to, tok_k; double tstar, bacc; int32_t rate_bin, qidx; int64_t cfi; int32_t rel_t; double dbacc; } mv_rec;
 typedef struct { int32_t det, agent; double x; } smp_rec;
 typedef struct { int32_t t, n_cf, n_mv, n_smp; int64_t cf0, mv0, smp0; int32_t sample_k; } step_rec;
 
@@ -172,6 +172,7 @@ typedef struct orc {
     double *tstar; int32_t *tstar_bin, *qidx, *rel_t;
     /* link state */
     double *B;
+    double *dB;     /* d B / d cap_mult of the same link (frozen decisions: B is affine in it) */
     int64_t *E;
     int32_t *next_seq;
     /* observation */
@@ -185,6 +186,7 @@ typedef struct orc {
     VEC(mv_rec) mv;
     VEC(smp_rec) smp;
     VEC(step_rec) steps;
+    VEC(uint8_t) capf;  /* per logged step and link: 1 if the idle cap clipped the bucket */
     /* scratch */
     int32_t *bucket_off, *bucket, *rank, *leader_of, *branch, *capped, *choice, *won, *head_cnt, *slots, *cfidx;
     pos_t *xhat;
@@ -399,7 +401,7 @@ orc_t *orc_create(const orc_inputs *in)
     o->D = calloc((size_t)O, 8);
     build_queues(o);
 
-    o->B = calloc((size_t)L, 8); o->E = calloc((size_t)L, 8); o->next_seq = calloc((size_t)L, 4);
+    o->B = calloc((size_t)L, 8); o->dB = calloc((size_t)L, 8); o->E = calloc((size_t)L, 8); o->next_seq = calloc((size_t)L, 4);
     o->cprev = calloc((size_t)Dd + 1, 8);
     o->counts = calloc((size_t)Dd * (size_t)(in->n_count_bins > 0 ? in->n_count_bins : 1) + 1, 8);
 
@@ -422,9 +424,9 @@ void orc_destroy(orc_t *o)
         o->det_pos, o->ready, o->rates, o->vfree, o->spacing, o->thr, o->out_off, o->out_lnk,
         o->in_off, o->in_lnk, o->org_off, o->org_list, o->dest_index, o->agent_didx, o->dist,
         o->q_off, o->q_list, o->rel_ptr, o->dep_ptr, o->rstep, o->D, o->status, o->link, o->seq,
-        o->pos, o->tstar, o->tstar_bin, o->qidx, o->rel_t, o->B, o->E, o->next_seq, o->cprev, o->counts,
+        o->pos, o->tstar, o->tstar_bin, o->qidx, o->rel_t, o->B, o->dB, o->E, o->next_seq, o->cprev, o->counts,
         o->bucket_off, o->bucket, o->rank, o->leader_of, o->branch, o->capped, o->choice, o->won,
-        o->head_cnt, o->slots, o->cfidx, o->xhat, o->mkey, o->bacc, o->cf.p, o->mv.p, o->smp.p, o->steps.p,
+        o->head_cnt, o->slots, o->cfidx, o->xhat, o->mkey, o->bacc, o->cf.p, o->mv.p, o->smp.p, o->steps.p, o->capf.p,
         o->base_x1, o->base_xhat, o->base_psi, o->base_sig };
     for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
     free(o);
@@ -602,6 +604,7 @@ int orc_step(orc_t *o)
         o->head_cnt[j] = h;
         o->slots[j] = o->lanes[j] - occ > 0 ? o->lanes[j] - occ : 0;   /* free entry slots */
         o->B[j] += (double)o->cap_mult[j] * (double)o->cap[j] * (double)o->lanes[j] * dt;
+        o->dB[j] += (double)o->cap[j] * (double)o->lanes[j] * dt;
         o->bacc[j] = o->B[j];
     }
 
@@ -702,7 +705,7 @@ int orc_step(orc_t *o)
                 o->status[a] = ST_EXITED;
                 o->link[a] = -1;
                 o->ctr[3]++;
-                if (o->log_on) { mv_rec m = { a, MV_EXIT, j, -1, 0, 0.0, 0.0, -1, 0, sr.cf0 + o->cfidx[a], 0 }; VPUSH(o->mv, m); }
+                if (o->log_on) { mv_rec m = { a, MV_EXIT, j, -1, 0, 0.0, 0.0, -1, 0, sr.cf0 + o->cfidx[a], 0, 0.0 }; VPUSH(o->mv, m); }
             }
         }
     }
@@ -714,8 +717,8 @@ int orc_step(orc_t *o)
             int32_t from = (o->status[a] == ST_ON) ? o->link[a] : -1;
             if (o->log_on) {
                 mv_rec mr;
-                if (from >= 0) mr = (mv_rec){ a, MV_TRANSFER, from, m, tokk[a], 0.0, o->bacc[from], -1, 0, sr.cf0 + o->cfidx[a], 0 };
-                else mr = (mv_rec){ a, MV_DEPART, o->agent_origin[a], m, 0, o->tstar[a], 0.0, o->tstar_bin[a], o->qidx[a], -1, o->rel_t[a] };
+                if (from >= 0) mr = (mv_rec){ a, MV_TRANSFER, from, m, tokk[a], 0.0, o->bacc[from], -1, 0, sr.cf0 + o->cfidx[a], t, o->dB[from] };
+                else mr = (mv_rec){ a, MV_DEPART, o->agent_origin[a], m, 0, o->tstar[a], 0.0, o->tstar_bin[a], o->qidx[a], -1, o->rel_t[a], 0.0 };
                 VPUSH(o->mv, mr);
             }
             if (from >= 0) o->ctr[4]++;
@@ -726,7 +729,12 @@ int orc_step(orc_t *o)
             o->seq[a] = o->next_seq[m]++;
         }
     }
-    for (int32_t j = 0; j < L; ++j) if (o->B[j] > 1.0) o->B[j] = 1.0;
+    /* idle cap; the clipped level no longer depends on the multiplier */
+    for (int32_t j = 0; j < L; ++j) {
+        int clip = o->B[j] > 1.0;
+        if (clip) { o->B[j] = 1.0; o->dB[j] = 0.0; }
+        if (o->log_on) VPUSH(o->capf, (uint8_t)clip);
+    }
 
     /* ---- observe ---- */
     int64_t active = 0, onnet = 0;
@@ -832,14 +840,15 @@ int64_t orc_log_sizes(const orc_t *o, int64_t *out)
 /* gradient the adjoint computes; central differences of it pin the adjoint.*/
 /*                                                                          */
 /* Parameters (NULL -> the values given at create): u[L], kappa[L],        */
-/* rates[O x B].  Outputs: soft counts [det x bins], surrogate total travel */
+/* rates[O x B], cap_mult[L].                                               */
+/* Outputs: soft counts [det x bins], surrogate total travel                */
 /* time, positions of agents on the network at the end (0 elsewhere).       */
 /* First call with record_base = 1 at the base parameters.                  */
 /* ------------------------------------------------------------------------ */
 static double sigm(double z) { return 1.0 / (1.0 + exp(-z)); }
 
 int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const double *rates_in,
-                    int record_base, double *out_counts, double *out_ttt, double *out_pos)
+                    const double *capm_in, int record_base, double *out_counts, double *out_ttt, double *out_pos)
 {
     const orc_inputs *in = &o->in;
     int32_t L = in->n_links, N = in->n_agents, O = in->n_origins, Bn = in->n_rate_bins;
@@ -853,11 +862,14 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
         o->base_psi = malloc(8 * (size_t)(o->mv.n + 1));
         o->base_sig = malloc(8 * (size_t)(o->smp.n + 1));
     }
-    double *u = malloc(8 * (size_t)L), *kap = malloc(8 * (size_t)L);
+    double *u = malloc(8 * (size_t)L), *kap = malloc(8 * (size_t)L), *capm = malloc(8 * (size_t)L);
     for (int32_t j = 0; j < L; ++j) {
         u[j] = u_in ? u_in[j] : (double)o->u[j];
         kap[j] = kappa_in ? kappa_in[j] : (double)o->kappa[j];
+        capm[j] = capm_in ? capm_in[j] : (double)o->cap_mult[j];
     }
+    /* token buckets replayed with the logged consumption and idle-cap clips */
+    double *Bf = calloc((size_t)L + 1, 8), *Bacc = calloc((size_t)L + 1, 8);
     double *x = calloc((size_t)N, 8), *xn = calloc((size_t)N, 8);
     int32_t *on = calloc((size_t)N, 4);
     /* agents placed at t = 0 */
@@ -876,6 +888,10 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
     }
     for (int64_t si = 0; si < o->steps.n; ++si) {
         const step_rec *s = &o->steps.p[si];
+        for (int32_t j = 0; j < L; ++j) {
+            Bf[j] += capm[j] * (double)o->cap[j] * (double)o->lanes[j] * in->dt;
+            Bacc[j] = Bf[j];
+        }
         for (int64_t c = s->cf0; c < s->cf0 + s->n_cf; ++c) {
             const cf_rec *r = &o->cf.p[c];
             int32_t j = r->link;
@@ -892,8 +908,18 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
         for (int64_t c = s->mv0; c < s->mv0 + s->n_mv; ++c) {
             const mv_rec *m = &o->mv.p[c];
             if (m->kind == MV_TRANSFER) {
-                /* grafted entry: value 0, history of the capped position */
-                x[m->agent] = 0.0 + (x[m->agent] - o->base_xhat[m->cfi]);
+                /* admission-time graft: the head's token became available at
+                 * t_tok = (t+1)dt - (B_pre - 1)/(m q n), B_pre the level before its
+                 * token; psi = -u_to * t_tok with u_to frozen */
+                int32_t j = m->from;
+                double mqn = capm[j] * (double)o->cap[j] * (double)o->lanes[j];
+                double bpre = Bacc[j] - (double)m->tok_k;
+                double ttok = (double)(s->t + 1) * in->dt - (bpre - 1.0) / mqn;
+                double psi = -(double)o->u[m->to] * ttok;
+                if (record_base) o->base_psi[c] = psi;
+                Bf[j] -= 1.0;
+                /* grafted entry: value 0, history of the capped position and of the token time */
+                x[m->agent] = 0.0 + (x[m->agent] - o->base_xhat[m->cfi]) + (psi - o->base_psi[c]);
             } else if (m->kind == MV_EXIT) {
                 /* exit earlier by (xhat - sg xhat)/u of the last link */
                 ttt_soft -= (x[m->agent] - o->base_xhat[m->cfi]) / (double)o->u[m->from];
@@ -923,6 +949,7 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
                 on[m->agent] = 1;
             }
         }
+        for (int32_t j = 0; j < L; ++j) if (o->capf.p[si * L + j]) Bf[j] = 1.0;
         if (s->sample_k > 0) {
             int32_t kb = s->sample_k - 1;
             for (int64_t c = s->smp0; c < s->smp0 + s->n_smp; ++c) {
@@ -946,7 +973,7 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
     if (out_ttt) *out_ttt = o->ttt + ttt_soft;
     if (out_pos) for (int32_t i = 0; i < N; ++i) out_pos[i] = (o->status[i] == ST_ON) ? x[i] : 0.0;
     if (record_base) o->have_base = 1;
-    free(u); free(kap); free(x); free(xn); free(on); free(cint); free(csoft);
+    free(u); free(kap); free(capm); free(Bf); free(Bacc); free(x); free(xn); free(on); free(cint); free(csoft);
     (void)O;
     return 0;
 }
@@ -956,10 +983,11 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
 /* at the base parameters (the straight-through and grafting conventions    */
 /* of SI-A/SI-B/SI-C/SI-D).  Cotangents: dL/dcounts [det x bins], dL/dTTT,  */
 /* dL/d(final positions) [N].  Gradients (accumulated, caller zeroes):      */
-/* g_u[L], g_kappa[L], g_rates[O x B].  flags bit 0: no transfer graft.   */
+/* g_u[L], g_kappa[L], g_rates[O x B], g_capm[L].                          */
+/* flags bit 0: no transfer graft.                                          */
 /* ------------------------------------------------------------------------ */
 int orc_backward(orc_t *o, const double *gQ, double gT, const double *gx,
-                 double *g_u, double *g_kappa, double *g_rates, int flags)
+                 double *g_u, double *g_kappa, double *g_rates, double *g_capm, int flags)
 {
     const orc_inputs *in = &o->in;
     int32_t N = in->n_agents, Bn = in->n_rate_bins, nb = in->n_count_bins;
@@ -996,9 +1024,20 @@ int orc_backward(orc_t *o, const double *gQ, double gT, const double *gx,
                 }
                 adj[m->agent] = 0.0;
             }
-            /* MV_TRANSFER: the entry position carries the capped position's history;
-             * flags bit 0 drops that graft (the paper's "without TG" comparison, SI-C) */
-            else if (flags & 1) adj[m->agent] = 0.0;
+            else {
+                /* MV_TRANSFER.  Admission graft: d psi / d m = -u_to d t_tok / d m with
+                 * d t_tok / d m = -(dB_pre/dm)/(m q n) + (B_pre - 1)/(m^2 q n). */
+                if (g_capm) {
+                    int32_t j = m->from;
+                    double mm = (double)o->cap_mult[j], qn = (double)o->cap[j] * (double)o->lanes[j];
+                    double bpre = m->bacc - (double)m->tok_k;
+                    double dtdm = -m->dbacc / (mm * qn) + (bpre - 1.0) / (mm * mm * qn);
+                    g_capm[j] += adj[m->agent] * (-(double)o->u[m->to]) * dtdm;
+                }
+                /* the entry position carries the capped position's history;
+                 * flags bit 0 drops that graft (the paper's "without TG" comparison, SI-C) */
+                if (flags & 1) adj[m->agent] = 0.0;
+            }
         }
         /* car-following, branches frozen; the cap passes the adjoint unchanged */
         for (int64_t c = s->cf0; c < s->cf0 + s->n_cf; ++c) nadj[o->cf.p[c].agent] = 0.0;

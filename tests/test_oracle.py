@@ -497,6 +497,59 @@ def test_adjoint_matches_frozen_surrogate_fd(seed):
         assert ad == pytest.approx(fd, rel=1e-6, abs=1e-8), which
 
 
+@pytest.mark.parametrize("seed", [3, 9])
+def test_capacity_multiplier_adjoint_matches_frozen_surrogate_fd(seed):
+    """Admission-time graft: the derivative of total travel time and of the
+    counts in the capacity multipliers equals central differences of the
+    frozen surrogate (bucket levels replayed with the logged consumption and
+    idle-cap clips)."""
+    w = W.random_small(seed, nx=3, ny=3, n_agents=300, rates=True, steps=240)
+    w.net.capacity = np.full(w.net.n_links, 0.12, np.float32)   # make the buckets bind
+    rng = np.random.default_rng(seed)
+    m = rng.uniform(0.5, 1.0, w.net.n_links).astype(np.float32)
+    o = Oracle(w, variant="f64", log=True, params={"cap_mult": m})
+    o.run()
+    base = {"cap_mult": m.astype(np.float64)}
+    c0, t0, x0 = o.frozen(**base, record_base=True)
+    cnt, ttt = o.counts()
+    np.testing.assert_allclose(c0, cnt, atol=1e-9)
+    assert t0 == pytest.approx(ttt, abs=1e-9)
+    gQ = rng.normal(size=c0.shape)
+    gT = 0.61
+    st = o.state()
+    gx = rng.normal(size=x0.shape) * (st["status"] == ST_ON)
+    g = o.backward(gQ=gQ, gT=gT, gx=gx)["cap_mult"]
+    assert np.count_nonzero(g) > 3
+    d = rng.normal(size=m.shape)
+    h = 1e-6
+    dc, dt_, dx = _fd_directional(o, base, d, "cap_mult", h)
+    fd = (gQ * dc).sum() + gT * dt_ + (gx * dx).sum()
+    assert (g * d).sum() == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+@pytest.mark.parametrize("mult", [1.0, 0.8])
+def test_bottleneck_capacity_gradient_closed_form(mult):
+    """N vehicles jammed at the head of a link with outflow capacity m q n
+    below the car-following limit, free downstream at equal speeds: the k-th
+    token becomes available at k/(m q n), so under admission-time grafting
+    dTTT/dm = -sum_k k / (m^2 q n) exactly; the downstream link's multiplier
+    has no effect (exits take no tokens)."""
+    N, q = 10, 0.5
+    w = W.line(n_links=2, length=200.0, speed=13.9, lanes=1, capacity=q, n_agents=N, steps=60)
+    m = np.float32([mult, 1.0])
+    o = Oracle(w, variant="f64", log=True, params={"cap_mult": m})
+    s = 1.0 / float(np.float32(w.net.jam_density[0]))
+    o.place(list(range(N)), [0] * N, [200.0 - k * s for k in range(N)])
+    o.run(60)
+    st = o.state()
+    assert np.all(st["status"] == ST_EXITED)
+    g = o.backward(gT=1.0)["cap_mult"]
+    mm = float(m[0])
+    expect = -sum(k / (mm * mm * q) for k in range(1, N + 1))
+    assert g[0] == pytest.approx(expect, rel=1e-12)
+    assert g[1] == 0.0
+
+
 def test_free_flow_gradient_closed_form():
     """Lone vehicle: dx(T)/du_j = dt x (steps spent on link j), carried across
     the transfer by the graft."""
