@@ -54,6 +54,37 @@ def byte_model(kind: str, S: int, L: int, Nn: int, O: int, T: int, vs: int, move
     return total / max(launches, 1)
 
 
+def kernel_source_digest() -> str:
+    """Digest of the kernel sources; a counter summary names the digest it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sim_kernels.hip", "sim_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_25068_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain copy of known
+    size gives), or None when there is none for this workload or the kernels
+    have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    try:
+        return int(float(vals["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def make_workload(name: str, sim_steps=None):
     from paper_2603_25068_amd import workloads as W
     if name == "metro":
@@ -92,6 +123,106 @@ def cpu_baseline(w, n_steps: int, budget_s: float):
                       f"reverse sweep, single thread, {vs} vehicle-steps in {el:.1f} s"}
 
 
+def serving_leg(n_requests: int, rate: float, steps: int, max_slots: int, budget: int, seed: int = 41):
+    """Poisson stream of nowcast rollouts on seeded metro networks of log-uniform
+    size: the continuous-batching server against the plain path (one request
+    at a time, in arrival order, each through its own simulator handle).
+    Requests are generated before the clock starts (client side); latency is
+    arrival to result on the host, including host preparation."""
+    import numpy as np
+    import torch
+    from paper_2603_25068_amd import workloads as W
+    from paper_2603_25068_amd.sim import Server, Simulator, SRV_DONE
+
+    reqs = W.serving_requests(n_requests, rate_per_s=rate, steps=steps, seed=seed)
+    arrivals = [a for a, _ in reqs]
+    ws = [W.metro(**spec) for _, spec in reqs]
+
+    # continuous batching
+    srv = Server(device=0, mem_budget_bytes=budget, max_slots=max_slots, chunk_steps=60)
+    t0 = time.perf_counter()
+    tickets = []
+    for a, w in zip(arrivals, ws):
+        d = t0 + a - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tickets.append(srv.submit(w, steps=steps))
+    batched = []
+    for t in tickets:
+        st = srv.wait(t, 1200.0)
+        if st != SRV_DONE:
+            raise RuntimeError(f"request {t} ended in state {st}: {srv.error(t)}")
+        batched.append(srv.result(t))
+    sb = srv.stats()
+    srv.close()
+
+    # plain path: one request at a time, FIFO
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, vs_total, plain_same = [], 0, True
+    for i, (a, w) in enumerate(zip(arrivals, ws)):
+        d = t0 + a - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        sim = Simulator(w, steps=steps, max_steps=steps)
+        sim.rollout(steps)
+        c, T = sim.observables()
+        v = sim.vehicle_steps()
+        done = time.perf_counter()
+        lat.append(done - (t0 + a))
+        vs_total += int(v.sum())
+        plain_same &= bool(np.array_equal(c, batched[i][0]) and np.array_equal(T, batched[i][1])
+                           and np.array_equal(v, batched[i][2]))
+        sim.close()
+    wall = time.perf_counter() - (t0 + arrivals[0])
+    lat = np.sort(np.asarray(lat))
+
+    def pct(x, p):
+        return float(x[min(len(x) - 1, int(np.ceil(p * len(x))) - 1)])
+
+    agents = [int(w.dem.n_agents) for w in ws]
+    links = [int(w.net.n_links) for w in ws]
+    return {
+        "workload": f"Poisson {rate:g} req/s, {n_requests} requests of {steps} steps on seeded metro networks, "
+                    f"links {min(links)}-{max(links)}, agents {min(agents)}-{max(agents)} (log-uniform)",
+        "batched": {"p50_s": round(sb["p50_s"], 4), "p99_s": round(sb["p99_s"], 4),
+                    "vehicle_steps_per_s": round(sb["vehicle_steps_per_s"], 1),
+                    "max_running": sb["max_running"], "max_slots": max_slots, "mem_budget_bytes": budget},
+        "plain_fifo": {"p50_s": round(pct(lat, 0.5), 4), "p99_s": round(pct(lat, 0.99), 4),
+                       "vehicle_steps_per_s": round(vs_total / wall, 1)},
+        "results_identical": plain_same,
+    }
+
+
+def profile_pass(args):
+    """One forward+adjoint pass of the workload and nothing else (for counter
+    runs), or a plain device copy of known size (the counters' calibration)."""
+    import torch
+    from paper_2603_25068_amd.sim import Simulator
+    dev = torch.device("cuda", 0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
+    w = make_workload(args.workload, args.sim_steps)
+    T = w.cfg.steps
+    sim = Simulator(w, record=True, max_steps=T)
+    gQ = torch.ones((1, w.net.n_detectors, sim.n_count_bins), dtype=torch.float32, device=dev)
+    gT = torch.ones(1, dtype=torch.float64, device=dev)
+    if args.schedule:
+        sim.set_schedule(*[int(x) for x in args.schedule.split(",")])
+    sim.reset()
+    sim.step(T)
+    sim.backward_device(gQ=gQ, gT=gT)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_pass": w.name, "sim_steps": T, "vehicle_steps": int(sim.vehicle_steps()[0])}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,11 +233,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-steps", type=int, default=3600)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--profile-pass", action="store_true", help="one forward+adjoint pass only")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--schedule", default="", help="with --profile-pass: g_link,g_node,g_rev")
+    ap.add_argument("--copy-probe-mib", type=int, default=0, help="with --profile-pass: time a plain copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the simulator runs every scenario on a single device; "
               "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_pass:
+        profile_pass(args)
+        return
 
     import numpy as np
     import torch
@@ -137,6 +281,10 @@ def main():
     for _ in range(args.warmup):
         fwd_adj(sim)
         fwd_only(fwd)
+    schedule = None
+    if not args.no_autotune:
+        # tune on the loaded end-of-rollout state (restored afterwards; results do not change)
+        schedule = {"fwd+adj": sim.autotune(probe_steps=30), "fwd": fwd.autotune(probe_steps=30)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -176,6 +324,13 @@ def main():
                 "avg_launch_us": round(1000.0 * avg_ms, 3), "alg_bytes_per_launch": int(bytes_launch),
                 "kernel_ms": {k: [round(v[0], 3), v[1]] for k, v in tm.items()}}
 
+    roofline["traffic"] = measured_traffic(f"k_{dom}", w.name)
+
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(args.serve_requests, args.serve_rate, args.serve_steps, args.serve_slots,
+                              int(args.serve_budget_gib * (1 << 30)))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(make_workload(args.workload, args.sim_steps), args.cpu_steps, args.cpu_budget_s)
@@ -189,9 +344,11 @@ def main():
                    "sim_steps": T, "ckpt_every": w.cfg.ckpt_every, "pass": "forward+adjoint",
                    "vehicle_steps_per_pass": vs, "forward_only_vehicle_steps_per_s": round(fwd_value, 1),
                    "forward_only_ms": round(1000.0 * el_f / args.steps, 3),
-                   "counters": st, "generate_s": round(gen_s, 2)},
+                   "counters": st, "generate_s": round(gen_s, 2),
+                   "schedule_g_link_g_node_g_rev": schedule},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -165,9 +165,13 @@ int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device);
  * Cotangents (each may be NULL): dL_dcounts [S x det x bins] float,
  * dL_dttt [S] double, dL_dpos [S x n_agents] float (final positions of
  * agents on the network).  grads[k] (for each bit k set in param_mask,
- * SIM_P_U, SIM_P_KAPPA, SIM_P_RATES supported) receives dL/d(group k),
- * overwritten, float, same layout as sim_set_params.  Other groups:
- * SIM_EUNSUPPORTED. */
+ * SIM_P_U, SIM_P_KAPPA, SIM_P_RATES, SIM_P_CAP_MULT supported) receives
+ * dL/d(group k), overwritten, float, same layout as sim_set_params.  Rates
+ * reach the loss through departure-time grafting and capacity multipliers
+ * through admission-time grafting: a vehicle released, or let through a
+ * link's outflow token bucket, carries the time at which its release count
+ * or token was reached into its entry position, in the manner of the
+ * trajectory grafting of SI-C.  Other groups: SIM_EUNSUPPORTED. */
 int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const float *dL_dpos,
                  uint32_t param_mask, float *const *grads, int on_device);
 
@@ -205,9 +209,11 @@ int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, ui
 int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
                 const int32_t *seq, int32_t *perm, int32_t *seg_off);
 
-/* Launch schedule: lanes per work item of the link-phase, node-phase and
- * reverse kernels (16, 32 or 64; the node group must hold the largest
- * node's merge candidates and out-links).  Results do not depend on it. */
+/* Launch schedule: lanes per work item of the link-phase and reverse
+ * kernels for small rings, and the floor of the node-phase lane group
+ * (each node runs on the smallest group of 16, 32 or 64 lanes, not below
+ * the floor, that holds its merge candidates and out-links); 16, 32 or 64
+ * each.  Results do not depend on it. */
 int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev);
 int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
 
@@ -217,6 +223,23 @@ int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
  * 1 node phase, 2 reverse, 3 tape/checkpoint copies. */
 int sim_set_timing(sim_t *h, int enable);
 int sim_get_timing(sim_t *h, double *ms, int64_t *launches, int n_kinds, int reset);
+
+/* Autotuner.  Picks the schedule of sim_set_schedule (lanes per work item of
+ * the link and reverse kernels, lane-group floor of the node kernel) for
+ * this handle's shape: each candidate runs
+ * probe_steps steps from the current state (and, for a recording handle,
+ * the reverse sweep over a window recorded from it), timed with HIP events
+ * on the handle's stream, one dimension at a time.  The state is restored
+ * afterwards, so call it on a representative state (e.g. mid-rollout);
+ * results never depend on the schedule, only speed does.  The choice is
+ * cached in the process and, if cache_path is not NULL, appended to that
+ * text file ("key g_link g_node g_rev ms" per line) under a key of the
+ * device architecture and log2-bucketed shape (scenarios, links, agents,
+ * ring slots per link, node candidates, recording); a cached entry is used
+ * without probing unless flags bit 0 is set.  Writes the chosen sizes to
+ * g_link, g_node, g_rev (each may be NULL) and applies them. */
+int sim_autotune(sim_t *h, int32_t probe_steps, const char *cache_path, int32_t flags, int32_t *g_link,
+                 int32_t *g_node, int32_t *g_rev);
 
 /* Device bytes sim_create would allocate for these inputs (host-only work:
  * validation, numbering, shortest times).  SIM_EINVAL for invalid inputs. */

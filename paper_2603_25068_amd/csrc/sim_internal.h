@@ -29,11 +29,13 @@ enum { ERR_RING_OVERFLOW = 0, ERR_CAND_OVERFLOW = 1, ERR_N = 4 };
 struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
-    int32_t g_link, g_node, g_rev;   // lanes per small segment / node / small reverse segment (16, 32 or 64)
+    int32_t g_link, g_node, g_rev;   // lanes per small segment / node floor / small reverse segment (16, 32, 64)
     const int32_t *lk_small, *lk_big;  // links by ring capacity for the link phase (small: cap <= 8 g_link)
     int32_t lk_n_small, lk_n_big;
     const int32_t *rv_small, *rv_big;  // same split for the reverse (small: cap <= 8 g_rev)
     int32_t rv_n_small, rv_n_big;
+    const int32_t *nd_list[3];         // nodes by lane group (16, 32, 64 lanes) for the node phase
+    int32_t nd_n[3];
     int64_t ring_total;
     double dt, theta, rate_bin_s;
 
@@ -60,12 +62,15 @@ struct Dev {
     const float *vfree, *spacing;    // derived: u*dt, platoon/kappa
     const double *util;              // beta / cost
     const double *acc;               // cap_mult * capacity * lanes * dt
+    const float *capm;               // [S*L] capacity multipliers
+    const float *capacity;           // [L] outflow capacity per lane
 
     // state
     float *ring_pos;
     int32_t *ring_agent;
     int32_t *rhead, *rtail;          // [S*L]
     double *B;                       // token bucket [S*L]
+    double *dB;                      // [S*L] dB/d cap_mult (recording handles only, else null)
     int64_t *E;                      // cumulative outflow [S*L]
     int32_t *slots, *nheads;         // [S*L]
     int4 *head_rec;                  // [S*L*maxl] (agent, destination, table row, -) of each head
@@ -83,9 +88,10 @@ struct Dev {
     int32_t *tape_agent;             // same
     int32_t *tape_head, *tape_tail;  // [(W+1) * S * L]
     int32_t *tape_dst;               // [(W+1) * S * L * maxl] entry slot of each leaving head (-1: exit)
+    float *tape_dstg;                // same shape as tape_dst: admission-graft factor -u_to dt_tok/dm
     float *adj_ring;                 // [S * ring_total] adjoint of the position of each ring slot's agent
     float *depg;                     // [S*N] adjoint reaching a departure graft, times u of the first link
-    double *gu, *gk;                 // [S*L] accumulated parameter gradients
+    double *gu, *gk, *gm;            // [S*L] accumulated parameter gradients (u, kappa, cap_mult)
     const float *gQ;                 // [S*D*nb] dL/dcounts (device copy)
     const double *gT;                // [S]
     const float *gx;                 // [S*N]

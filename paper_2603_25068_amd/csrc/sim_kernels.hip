@@ -230,11 +230,12 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
         hdst = d.agent_dest[hag];
         hdidx = d.agent_didx[hag];
     }
-    double Bv = 0.0, accv = 0.0;
+    double Bv = 0.0, accv = 0.0, dBv = 0.0;
     int64_t Ev = 0;
     if (gl == 0) {
         Bv = d.B[seg];
         accv = d.acc[seg];
+        if (d.dB) dBv = d.dB[seg];
         if (sample_b >= 0) Ev = d.E[seg];
     }
     int64_t tb = -1;
@@ -305,6 +306,8 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     const int h = min(nh, min(ln, d.maxl));
     if (gl == 0) {
         d.B[seg] = (Bv > 1.0 ? 1.0 : Bv) + accv;
+        // tangent of the level in the multiplier; the idle cap clears it
+        if (d.dB) d.dB[seg] = (Bv > 1.0 ? 0.0 : dBv) + (double)d.capacity[j] * (double)ln * d.dt;
         d.slots[seg] = max(0, ln - nocc);
         d.nheads[seg] = h;
         if (viol)
@@ -359,16 +362,12 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 // Out-link lanes k < out-degree hold the out-link's data, broadcast to the
 // candidates by shuffles; four shortest-time lookups are in flight at once.
 // Per-node link lists are padded node-major tables, so every lane finds its
-// link in the first load.
+// link in the first load.  `item` only spreads the counter atomics.
 // ---------------------------------------------------------------------------
 template <int G>
-__global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
+__device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k)
 {
-    const Group<G> g;
-    const int item = group_item<G>();
-    if (item >= d.S * d.Nn) return;
     const int gl = g.gl;
-    const int s = item / d.Nn, v = item - s * d.Nn;
     const int maxl = d.maxl;
     const int cnt = d.node_cnt[v];
     const int deg = cnt & 0xff, dego = (cnt >> 8) & 0xff, norg = (cnt >> 16) & 0xff;
@@ -398,13 +397,16 @@ __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
     }
     // ---- in-link lanes (resolve) ----
     int64_t sjq = -1;
-    double Bj = 0.0;
+    double Bj = 0.0, dBj = 0.0;
     int nhq = 0;
+    const bool graft = tape_k >= 0 && d.tape_dstg != nullptr;   // admission-graft tape (recording replay)
     if (gl < deg) {
         sjq = sL + jin_res;
         Bj = d.B[sjq];
         nhq = d.nheads[sjq];
+        if (graft) dBj = d.dB[sjq];
     }
+    const double Bacc = Bj;   // accrued level before this step's tokens
     // ---- candidate of this lane ----
     int ag = -1, dst = -1, didx = 0, origin = -1, from = -1, ftail = -1;
     double alpha = 1.0;
@@ -572,8 +574,32 @@ __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
     }
     const int64_t ga = (int64_t)s * d.N + (ag >= 0 ? ag : 0);
     const int64_t slot = (int64_t)s * d.ring_total + rbase + (tbase + erank) % rcap;
-    if (tape_k >= 0 && passed && from >= 0)   // where each leaving head went (-1: left the network)
-        d.tape_dst[((int64_t)tape_k * d.S * d.L + sL + from) * maxl + (gl - qi * maxl)] = ch >= 0 ? (int32_t)slot : -1;
+    // admission graft: a head leaving on a token carries the token's availability
+    // time t_tok = (t+1)dt - (B_pre - 1)/(m q n) into its entry position
+    // (psi = -u_to t_tok); B_pre = accrued level minus the tokens taken ahead of it
+    float gfac = 0.f;
+    if (graft) {
+        const double Bq = __shfl(Bacc, q_of_lane, G), dBq = __shfl(dBj, q_of_lane, G);
+        const int myr = gl - q_of_lane * maxl;
+        int tok = 0;
+        for (int r = 0; r < maxl; ++r) {
+            const int c2 = __shfl(ch, min(q_of_lane * maxl + r, G - 1), G);
+            tok += (r < myr && c2 >= 0);
+        }
+        if (passed && from >= 0 && ch >= 0) {
+            const double mm = (double)d.capm[sL + from];
+            const double mqn = mm * (double)d.capacity[from] * (double)d.lanes[from];
+            if (mqn > 0.0) {
+                const double dtdm = -dBq / mqn + (Bq - (double)tok - 1.0) / (mm * mqn);
+                gfac = (float)(-(double)d.u[sL + ch] * dtdm);
+            }
+        }
+    }
+    if (tape_k >= 0 && passed && from >= 0) {   // where each leaving head went (-1: left the network)
+        const int64_t ti = ((int64_t)tape_k * d.S * d.L + sL + from) * maxl + (gl - qi * maxl);
+        d.tape_dst[ti] = ch >= 0 ? (int32_t)slot : -1;
+        if (graft) d.tape_dstg[ti] = gfac;
+    }
     if (passed) {
         if (ch >= 0) {
             d.ring_agent[slot] = ag;
@@ -593,6 +619,36 @@ __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
         }
     }
     add_counters<G>(d, g, s, item, inc);
+}
+
+// Node phase launch: nodes are split on the host into classes by the lane
+// group that holds their candidates (16, 32 or 64 lanes, never below the
+// schedule's floor); one launch runs the three classes as block roles, each
+// role's block range remapped so that neighbouring nodes share an XCD.
+__global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
+{
+    const int b = (int)blockIdx.x;
+    const int n16 = d.S * d.nd_n[0], n32 = d.S * d.nd_n[1], n64 = d.S * d.nd_n[2];
+    const int b16 = ((n16 + 15) / 16 + 7) & ~7, b32 = ((n32 + 7) / 8 + 7) & ~7;
+    if (b < b16) {
+        const Group<16> g;
+        const int item = xcd_remap(b, b16) * 16 + (int)threadIdx.x / 16;
+        if (item >= n16) return;
+        const int s = item / d.nd_n[0];
+        node_work<16>(d, g, s, d.nd_list[0][item - s * d.nd_n[0]], item, t, tape_k);
+    } else if (b < b16 + b32) {
+        const Group<32> g;
+        const int item = xcd_remap(b - b16, b32) * 8 + (int)threadIdx.x / 32;
+        if (item >= n32) return;
+        const int s = item / d.nd_n[1];
+        node_work<32>(d, g, s, d.nd_list[1][item - s * d.nd_n[1]], item, t, tape_k);
+    } else {
+        const Group<64> g;
+        const int item = xcd_remap(b - b16 - b32, (int)gridDim.x - b16 - b32) * 4 + (int)threadIdx.x / 64;
+        if (item >= n64) return;
+        const int s = item / d.nd_n[2];
+        node_work<64>(d, g, s, d.nd_list[2][item - s * d.nd_n[2]], item, t, tape_k);
+    }
 }
 
 // Tape entry without an update (the state at the end of a replay window).
@@ -682,7 +738,7 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     float *xb = buf, *pb = buf + P;
     const int piece = P - 2 * kMaxLanes;
     const int64_t dst0 = ((int64_t)tape_k * SL + seg) * d.maxl;
-    double gu = 0.0, gk = 0.0;
+    double gu = 0.0, gk = 0.0, gm = 0.0;
     for (int lo = 0; lo < n; lo += piece) {
         const int hi = min(n, lo + piece);
         const int slo = max(0, lo - ln), shi = min(n, hi + ln);
@@ -693,7 +749,12 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
             if (r >= lo) {
                 float ap;
                 if (init) ap = d.gx ? d.gx[sN + d.tape_agent[tb + sl]] : 0.f;
-                else if (r < npass) { const int ds = d.tape_dst[dst0 + r]; ap = ds < 0 ? exit_adj : d.adj_ring[ds]; }
+                else if (r < npass) {
+                    const int ds = d.tape_dst[dst0 + r];
+                    ap = ds < 0 ? exit_adj : d.adj_ring[ds];
+                    // admission graft of a head that left on a token (once per rank: r < hi)
+                    if (d.gm && ds >= 0 && r < hi) gm += (double)ap * (double)d.tape_dstg[dst0 + r];
+                }
                 else ap = d.adj_ring[base + sl];
                 pb[r - slo] = ap;
             }
@@ -752,9 +813,11 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     }
     gu = g.sum(gu);
     gk = g.sum(gk);
+    if (d.gm) gm = g.sum(gm);
     if (gl == 0 && !init) {
         d.gu[seg] += gu;
         d.gk[seg] += gk;
+        if (d.gm) d.gm[seg] += gm;
     }
 }
 
@@ -1014,7 +1077,6 @@ int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const
 // launchers
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int64_t waves) { return (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock); }
-static inline int blocks_for(int64_t items, int G) { const int per = 256 / G; return (int)((items + per - 1) / per); }
 
 static inline int class_blocks(int S, int n_small, int n_big, int G)
 {
@@ -1032,12 +1094,9 @@ void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 }
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
 {
-    const int64_t items = (int64_t)d.S * d.Nn;
-    switch (d.g_node) {
-    case 16: hipLaunchKernelGGL(k_node<16>, dim3(blocks_for(items, 16)), dim3(256), 0, st, d, t, tape_k); break;
-    case 32: hipLaunchKernelGGL(k_node<32>, dim3(blocks_for(items, 32)), dim3(256), 0, st, d, t, tape_k); break;
-    default: hipLaunchKernelGGL(k_node<64>, dim3(blocks_for(items, 64)), dim3(256), 0, st, d, t, tape_k); break;
-    }
+    const int n16 = d.S * d.nd_n[0], n32 = d.S * d.nd_n[1], n64 = d.S * d.nd_n[2];
+    const int blocks = (((n16 + 15) / 16 + 7) & ~7) + (((n32 + 7) / 8 + 7) & ~7) + (n64 + 3) / 4;
+    hipLaunchKernelGGL(k_node, dim3(std::max(blocks, 1)), dim3(256), 0, st, d, t, tape_k);
 }
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 {

@@ -8,10 +8,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <limits>
 #include <new>
 #include <queue>
@@ -48,7 +52,7 @@ struct Ckpt {
     float *ring_pos = nullptr;
     int32_t *ring_agent = nullptr;
     int32_t *rhead = nullptr, *rtail = nullptr;
-    double *B = nullptr;
+    double *B = nullptr, *dB = nullptr;
     int64_t *E = nullptr;
     double *Dacc = nullptr;
     int32_t *rel_ptr = nullptr, *dep_ptr = nullptr;
@@ -72,6 +76,8 @@ struct sim_t {
     int32_t g_link = 16, g_node = 64, g_rev = 16;   // lanes per work item
     int32_t *lk_small_dev = nullptr, *lk_big_dev = nullptr, *rv_small_dev = nullptr, *rv_big_dev = nullptr;
     size_t lk_small_cap = 0, lk_big_cap = 0, rv_small_cap = 0, rv_big_cap = 0;
+    int32_t *nd_dev[3] = {nullptr, nullptr, nullptr};
+    size_t nd_cap[3] = {0, 0, 0};
     std::vector<int32_t> tail, head, lanes, origin_node, det_link, agent_origin, agent_dest;
     std::vector<float> length, free_speed, jam_density, capacity, beta, alpha, cost, det_pos, ready, rates;
     std::vector<uint64_t> seeds;
@@ -93,6 +99,13 @@ struct sim_t {
     // mutable parameter buffers
     float *p_u = nullptr, *p_kappa = nullptr, *p_beta = nullptr, *p_alpha = nullptr, *p_cost = nullptr,
           *p_rates = nullptr, *p_capm = nullptr, *capacity_dev = nullptr;
+    float *tape_dstg_buf = nullptr;   // admission-graft tape, attached only for cap_mult gradients
+    double *gm_buf = nullptr;
+    // autotuner snapshot of the live state (allocated on first use)
+    bool tune_alloc = false;
+    Ckpt tune_ck;
+    double *tune_tstar = nullptr;
+    int32_t *tune_rel = nullptr, *tune_dep = nullptr, *tune_exit = nullptr, *tune_cum = nullptr;
     float *vfree = nullptr, *spacing = nullptr;
     double *util = nullptr, *acc = nullptr;
     // mutable queue buffers
@@ -287,6 +300,7 @@ void zero_state(sim_t *h)
     HIPCHK(hipMemsetAsync(d.rhead, 0, SL * 4, st));
     HIPCHK(hipMemsetAsync(d.rtail, 0, SL * 4, st));
     HIPCHK(hipMemsetAsync(d.B, 0, SL * 8, st));
+    if (d.dB) HIPCHK(hipMemsetAsync(d.dB, 0, SL * 8, st));
     HIPCHK(hipMemsetAsync(d.E, 0, SL * 8, st));
     HIPCHK(hipMemsetAsync(d.slots, 0, SL * 4, st));
     HIPCHK(hipMemsetAsync(d.nheads, 0, SL * 4, st));
@@ -412,7 +426,17 @@ void build_classes(sim_t *h)
     put(h->lk_big_dev, h->lk_big_cap, lb);
     put(h->rv_small_dev, h->rv_small_cap, rs);
     put(h->rv_big_dev, h->rv_big_cap, rb);
+    // nodes by the lane group that holds their merge candidates and out-links
+    std::vector<int32_t> nd[3];
+    for (int v = 0; v < h->Nn; ++v) {
+        const int need = std::max((h->in_off[v + 1] - h->in_off[v]) * h->maxl + (h->org_off[v + 1] - h->org_off[v]),
+                                  h->out_off[v + 1] - h->out_off[v]);
+        const int gv = std::max(h->g_node, need <= 16 ? 16 : (need <= 32 ? 32 : 64));
+        nd[gv == 16 ? 0 : (gv == 32 ? 1 : 2)].push_back(v);
+    }
+    for (int c = 0; c < 3; ++c) put(h->nd_dev[c], h->nd_cap[c], nd[c]);
     Dev &d = h->d;
+    for (int c = 0; c < 3; ++c) { d.nd_list[c] = h->nd_dev[c]; d.nd_n[c] = (int)nd[c].size(); }
     d.lk_small = h->lk_small_dev; d.lk_big = h->lk_big_dev; d.lk_n_small = (int)ls.size(); d.lk_n_big = (int)lb.size();
     d.rv_small = h->rv_small_dev; d.rv_big = h->rv_big_dev; d.rv_n_small = (int)rs.size(); d.rv_n_big = (int)rb.size();
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -443,6 +467,7 @@ void ckpt_alloc(sim_t *h, Ckpt &c)
     c.rhead = h->dalloc<int32_t>(SL);
     c.rtail = h->dalloc<int32_t>(SL);
     c.B = h->dalloc<double>(SL);
+    c.dB = h->dalloc<double>(SL);
     c.E = h->dalloc<int64_t>(SL);
     c.Dacc = h->dalloc<double>(SO);
     c.rel_ptr = h->dalloc<int32_t>(SO);
@@ -465,6 +490,7 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save)
     cp(c.rhead, d.rhead, SL * 4);
     cp(c.rtail, d.rtail, SL * 4);
     cp(c.B, d.B, SL * 8);
+    if (d.dB) cp(c.dB, d.dB, SL * 8);
     cp(c.E, d.E, SL * 8);
     cp(c.Dacc, d.Dacc, SO * 8);
     cp(c.rel_ptr, d.rel_ptr, SO * 4);
@@ -621,13 +647,9 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     }
     for (int j = 0; j < L; ++j)
         if (h->det_off[j + 1] - h->det_off[j] > sim::kMaxDetPerLink) fail(SIM_EUNSUPPORTED, "more than 4 detectors on a link");
-    // lanes per node: the smallest group that holds every node's candidates and out-links
-    int need = 1;
-    for (int v = 0; v < Nn; ++v) {
-        need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]));
-        need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
-    }
-    h->g_node = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
+    // lanes per node: a floor; each node gets the smallest group (16, 32, 64) above it that holds
+    // its candidates and out-links
+    h->g_node = 16;
     for (int v = 0; v < Nn; ++v) {
         h->max_in = std::max(h->max_in, h->in_off[v + 1] - h->in_off[v]);
         h->max_out = std::max(h->max_out, h->out_off[v + 1] - h->out_off[v]);
@@ -750,6 +772,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     h->p_capm = h->upload(rep(std::vector<float>(L, 1.f)));
     h->p_rates = h->fixed_mode ? h->dalloc<float>(1) : h->upload(rep(h->rates));
     h->capacity_dev = h->upload(h->capacity);
+    d.capm = h->p_capm; d.capacity = h->capacity_dev;
     d.u = h->p_u; d.kappa = h->p_kappa; d.alpha = h->p_alpha; d.rates = h->p_rates;
     h->vfree = h->dalloc<float>(SL); h->spacing = h->dalloc<float>(SL);
     h->util = h->dalloc<double>(SL); h->acc = h->dalloc<double>(SL);
@@ -778,6 +801,10 @@ void allocate_device(sim_t *h, const sim_config *cfg)
         d.adj_ring = h->dalloc<float>(SR); d.depg = h->dalloc<float>(SN);
         d.tape_dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
         d.gu = h->dalloc<double>(SL); d.gk = h->dalloc<double>(SL);
+        d.dB = h->dalloc<double>(SL);
+        h->tape_dstg_buf = h->dalloc<float>((size_t)(h->W + 1) * SL * maxl);
+        h->gm_buf = h->dalloc<double>(SL);
+        d.tape_dstg = nullptr; d.gm = nullptr;
         h->gQ_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
         h->gx_dev = h->dalloc<float>(SN);
         h->gT_dev = h->dalloc<double>(h->S);
@@ -1132,8 +1159,11 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         if (!h->record) fail(SIM_ESTATE, "handle was created without record_for_backward");
         if (!h->rec_valid || h->t == 0 || h->ckpts[0].t != 0)
             fail(SIM_ESTATE, "sim_backward needs a recorded rollout from t = 0 (at most max_steps)");
-        const uint32_t ok = (1u << SIM_P_U) | (1u << SIM_P_KAPPA) | (1u << SIM_P_RATES);
-        if (param_mask & ~ok) fail(SIM_EUNSUPPORTED, "gradient groups supported: u, kappa, rates");
+        const uint32_t ok = (1u << SIM_P_U) | (1u << SIM_P_KAPPA) | (1u << SIM_P_RATES) | (1u << SIM_P_CAP_MULT);
+        if (param_mask & ~ok) fail(SIM_EUNSUPPORTED, "gradient groups supported: u, kappa, rates, cap_mult");
+        const bool want_m = (param_mask & (1u << SIM_P_CAP_MULT)) != 0;
+        h->d.tape_dstg = want_m ? h->tape_dstg_buf : nullptr;
+        h->d.gm = want_m ? h->gm_buf : nullptr;
         if ((param_mask & (1u << SIM_P_RATES)) && h->fixed_mode) fail(SIM_EINVAL, "rates need departure-rate mode");
         if (param_mask && !grads) fail(SIM_EINVAL, "grads is NULL");
         Dev d = h->d;
@@ -1149,6 +1179,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         HIPCHK(hipMemsetAsync(d.depg, 0, SN * 4, st));
         HIPCHK(hipMemsetAsync(d.gu, 0, SL * 8, st));
         HIPCHK(hipMemsetAsync(d.gk, 0, SL * 8, st));
+        if (want_m) HIPCHK(hipMemsetAsync(d.gm, 0, SL * 8, st));
         const int T = h->t;
         Ckpt &fin = h->ckpts.back();
         ckpt_copy(h, fin, true);
@@ -1176,6 +1207,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         ckpt_copy(h, fin, false);
         h->t = T;
         h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
+        h->d.tape_dstg = nullptr; h->d.gm = nullptr;
         const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         if (param_mask & (1u << SIM_P_U)) {
             sim::launch_gather_links(d.gu, h->linv_dev, h->grad_tmp, h->S, h->L, st);
@@ -1184,6 +1216,10 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         if (param_mask & (1u << SIM_P_KAPPA)) {
             sim::launch_gather_links(d.gk, h->linv_dev, h->grad_tmp, h->S, h->L, st);
             HIPCHK(hipMemcpyAsync(grads[SIM_P_KAPPA], h->grad_tmp, SL * 4, kout, st));
+        }
+        if (want_m) {
+            sim::launch_gather_links(d.gm, h->linv_dev, h->grad_tmp, h->S, h->L, st);
+            HIPCHK(hipMemcpyAsync(grads[SIM_P_CAP_MULT], h->grad_tmp, SL * 4, kout, st));
         }
         if (param_mask & (1u << SIM_P_RATES)) {
             const size_t nr = (size_t)h->S * h->O * h->B;
@@ -1331,17 +1367,211 @@ int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, con
     });
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner: lane-group sizes of the link, node and reverse kernels, timed on
+// the live state and cached per shape bucket
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, 3>> g_tune_mem;
+
+int node_group_need(const sim_t *h)
+{
+    int need = 1;
+    for (int v = 0; v < h->Nn; ++v) {
+        need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * h->maxl + (h->org_off[v + 1] - h->org_off[v]));
+        need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
+    }
+    return need;
+}
+
+std::string shape_key(const sim_t *h)
+{
+    hipDeviceProp_t p;
+    HIPCHK(hipGetDeviceProperties(&p, h->device));
+    auto lg = [](double x) { return (int)std::lround(std::log2(std::max(1.0, x))); };
+    std::string arch = p.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    return arch + "/S" + std::to_string(h->S) + "/L" + std::to_string(lg(h->L)) + "/N" + std::to_string(lg(h->N)) +
+           "/R" + std::to_string(lg((double)h->ring_total / std::max(1, h->L))) + "/in" +
+           std::to_string(node_group_need(h)) + "/rec" + std::to_string(h->record ? 1 : 0);
+}
+
+bool cache_lookup(const std::string &path, const std::string &key, std::array<int, 3> &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool hit = false;
+    auto it = g_tune_mem.find(key);
+    if (it != g_tune_mem.end()) { out = it->second; hit = true; }
+    if (!path.empty()) {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {   // "key g_link g_node g_rev"; the last entry of a key wins
+            const size_t sp = line.find(' ');
+            if (sp == std::string::npos || line.compare(0, sp, key) != 0 || sp != key.size()) continue;
+            int a = 0, b = 0, c = 0;
+            if (std::sscanf(line.c_str() + sp, "%d %d %d", &a, &b, &c) == 3) { out = {a, b, c}; hit = true; }
+        }
+    }
+    return hit;
+}
+
+void cache_store(const std::string &path, const std::string &key, const std::array<int, 3> &v, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_mem[key] = v;
+    if (path.empty()) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << ' ' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << ms << '\n';
+}
+
+void tune_snapshot(sim_t *h, bool save)
+{
+    Dev &d = h->d;
+    const size_t SN = (size_t)h->S * h->N, nc = (size_t)h->S * h->D * std::max(h->nb, 1);
+    if (!h->tune_alloc) {
+        ckpt_alloc(h, h->tune_ck);
+        h->tune_tstar = h->dalloc<double>(SN);
+        h->tune_rel = h->dalloc<int32_t>(SN);
+        h->tune_dep = h->dalloc<int32_t>(SN);
+        h->tune_exit = h->dalloc<int32_t>(SN);
+        h->tune_cum = h->dalloc<int32_t>(nc);
+        h->tune_alloc = true;
+    }
+    ckpt_copy(h, h->tune_ck, save);
+    auto cp = [&](void *snap, void *live, size_t bytes) {
+        if (save) HIPCHK(hipMemcpyAsync(snap, live, bytes, hipMemcpyDeviceToDevice, h->stream));
+        else HIPCHK(hipMemcpyAsync(live, snap, bytes, hipMemcpyDeviceToDevice, h->stream));
+    };
+    cp(h->tune_tstar, d.tstar, SN * 8);
+    cp(h->tune_rel, d.rel_t, SN * 4);
+    cp(h->tune_dep, d.dep_t, SN * 4);
+    cp(h->tune_exit, d.exit_t, SN * 4);
+    cp(h->tune_cum, d.cum, nc * 4);
+}
+
+void set_groups(sim_t *h, int gl, int gn, int gr)
+{
+    h->g_link = h->d.g_link = gl;
+    h->g_node = h->d.g_node = gn;
+    h->g_rev = h->d.g_rev = gr;
+    build_classes(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_autotune(sim_t *h, int32_t probe_steps, const char *cache_path, int32_t flags, int32_t *g_link,
+                 int32_t *g_node, int32_t *g_rev)
+{
+    return guarded(h, [&] {
+        if (probe_steps < 1) fail(SIM_EINVAL, "probe_steps must be >= 1");
+        const std::string key = shape_key(h), path = cache_path ? cache_path : "";
+        std::array<int, 3> best = {h->g_link, h->g_node, h->g_rev};
+        auto valid = [&](const std::array<int, 3> &v) {
+            auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
+            return ok(v[0]) && ok(v[1]) && ok(v[2]);
+        };
+        std::array<int, 3> cached;
+        if (!(flags & 1) && cache_lookup(path, key, cached) && valid(cached)) {
+            set_groups(h, cached[0], cached[1], cached[2]);
+            best = cached;
+        } else {
+            const hipStream_t st = h->stream;
+            const int t0 = h->t;
+            hipEvent_t ea, eb;
+            HIPCHK(hipEventCreate(&ea));
+            HIPCHK(hipEventCreate(&eb));
+            const bool timing = h->timing;
+            h->timing = false;
+            tune_snapshot(h, true);
+            auto elapsed = [&]() {
+                HIPCHK(hipEventSynchronize(eb));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ea, eb));
+                return (double)ms;
+            };
+            // forward: steps from the snapshot (one untimed warm-up step per candidate)
+            auto time_forward = [&](const std::array<int, 3> &v) {
+                set_groups(h, v[0], v[1], v[2]);
+                tune_snapshot(h, false);
+                h->t = t0;
+                do_step(h, -1);
+                HIPCHK(hipEventRecord(ea, st));
+                for (int k = 0; k < probe_steps; ++k) do_step(h, -1);
+                HIPCHK(hipEventRecord(eb, st));
+                return elapsed();
+            };
+            double best_ms = 0.0;
+            for (int dim = 0; dim < 2; ++dim) {
+                double bms = 1e300;
+                std::array<int, 3> bv = best;
+                for (int g : {16, 32, 64}) {
+                    std::array<int, 3> v = best;
+                    v[dim] = g;
+                    if (!valid(v)) continue;
+                    const double ms = time_forward(v);
+                    if (ms < bms) { bms = ms; bv = v; }
+                }
+                best = bv;
+                best_ms = bms;
+            }
+            // reverse: record a window from the snapshot, then time the reverse sweep over it
+            if (h->record) {
+                set_groups(h, best[0], best[1], best[2]);
+                tune_snapshot(h, false);
+                h->t = t0;
+                const int Ww = std::min(probe_steps, h->W);
+                Dev d = h->d;
+                d.gQ = nullptr; d.gT = nullptr; d.gx = nullptr; d.gm = nullptr;
+                for (int k = 0; k < Ww; ++k) do_step(h, k);
+                sim::launch_tape_snapshot(d, Ww, st);
+                double bms = 1e300;
+                int bg = best[2];
+                for (int g : {16, 32, 64}) {
+                    h->g_rev = h->d.g_rev = g;
+                    build_classes(h);
+                    d.g_rev = g;
+                    d.rv_small = h->d.rv_small; d.rv_big = h->d.rv_big;
+                    d.rv_n_small = h->d.rv_n_small; d.rv_n_big = h->d.rv_n_big;
+                    for (int rep = 0; rep < 2; ++rep) {   // first sweep warms up
+                        HIPCHK(hipMemsetAsync(d.adj_ring, 0, (size_t)h->S * h->ring_total * 4, st));
+                        HIPCHK(hipEventRecord(ea, st));
+                        for (int k = Ww - 1; k >= 0; --k) sim::launch_reverse(d, t0 + k, k, 0, st);
+                        HIPCHK(hipEventRecord(eb, st));
+                        const double ms = elapsed();
+                        if (rep == 1 && ms < bms) { bms = ms; bg = g; }
+                    }
+                }
+                best[2] = bg;
+                HIPCHK(hipMemsetAsync(d.gu, 0, (size_t)h->S * h->L * 8, st));
+                HIPCHK(hipMemsetAsync(d.gk, 0, (size_t)h->S * h->L * 8, st));
+                HIPCHK(hipMemsetAsync(d.depg, 0, (size_t)h->S * h->N * 4, st));
+            }
+            set_groups(h, best[0], best[1], best[2]);
+            tune_snapshot(h, false);
+            h->t = t0;
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipEventDestroy(ea));
+            HIPCHK(hipEventDestroy(eb));
+            h->timing = timing;
+            cache_store(path, key, best, best_ms);
+        }
+        if (g_link) *g_link = best[0];
+        if (g_node) *g_node = best[1];
+        if (g_rev) *g_rev = best[2];
+    });
+}
+
 int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev)
 {
     return guarded(h, [&] {
         auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
         if (!ok(g_link) || !ok(g_node) || !ok(g_rev)) fail(SIM_EINVAL, "group sizes must be 16, 32 or 64");
-        int need = 1;
-        for (int v = 0; v < h->Nn; ++v) {
-            need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * h->maxl + (h->org_off[v + 1] - h->org_off[v]));
-            need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
-        }
-        if (g_node < need) fail(SIM_EINVAL, "node group smaller than the largest node's candidates");
         h->g_link = h->d.g_link = g_link;
         h->g_node = h->d.g_node = g_node;
         h->g_rev = h->d.g_rev = g_rev;

@@ -87,6 +87,7 @@ def lib():
         "sim_set_timing": ([vp, C.c_int], C.c_int),
         "sim_get_timing": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
         "sim_footprint": ([vp, vp, vp, vp], C.c_int),
+        "sim_autotune": ([vp, i32, C.c_char_p, i32, vp, vp, vp], C.c_int),
         "srv_create": ([C.c_int, C.c_size_t, i32, i32, vp], C.c_int),
         "srv_submit": ([vp, vp, vp, vp, i32, vp], C.c_int),
         "srv_poll": ([vp, i64, vp], C.c_int),
@@ -109,7 +110,7 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_segsort",
-            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint",
+            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
             "srv_stats", "srv_destroy"]
 
@@ -355,6 +356,14 @@ class Simulator:
         self._chk(self._L.sim_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def autotune(self, probe_steps: int = 20, cache_path: Optional[str] = None, force: bool = False):
+        """Pick and apply the fastest lane-group schedule for this shape from the
+        current state (restored afterwards); returns (g_link, g_node, g_rev)."""
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._chk(self._L.sim_autotune(self._h, int(probe_steps), cache_path.encode() if cache_path else None,
+                                       1 if force else 0, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
     def set_timing(self, on: bool = True):
         self._chk(self._L.sim_set_timing(self._h, int(on)))
 
@@ -468,30 +477,34 @@ class Server:
 def make_rollout_function():
     """torch.autograd.Function around one recorded rollout: forward sets the
     parameters and runs T steps, returning detector counts and total travel
-    time; backward runs the checkpointed adjoint."""
+    time; backward runs the checkpointed adjoint.  `rates` and `cap_mult` may
+    be None (left as they are, no gradient)."""
     import torch
 
     class SimRollout(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, sim: Simulator, T: int, free_speed, jam_density, rates):
+        def forward(ctx, sim: Simulator, T: int, free_speed, jam_density, rates=None, cap_mult=None):
             sim.set_params("free_speed", free_speed)
             sim.set_params("jam_density", jam_density)
             if rates is not None and rates.numel() > 0:
                 sim.set_params("rates", rates)
+            if cap_mult is not None:
+                sim.set_params("cap_mult", cap_mult)
             sim.reset()
             sim.step(T)
             counts, ttt = sim.observables_device()
             ctx.sim = sim
             ctx.has_rates = rates is not None and rates.numel() > 0
+            ctx.has_capm = cap_mult is not None
             return counts, ttt
 
         @staticmethod
         def backward(ctx, g_counts, g_ttt):
             sim = ctx.sim
-            groups = ("free_speed", "jam_density") + (("rates",) if ctx.has_rates else ())
+            groups = ("free_speed", "jam_density") + (("rates",) if ctx.has_rates else ()) + \
+                (("cap_mult",) if ctx.has_capm else ())
             g = sim.backward_device(gQ=g_counts.float() if g_counts is not None else None,
                                     gT=g_ttt.double() if g_ttt is not None else None, groups=groups)
-            gr = g.get("rates")
-            return None, None, g["free_speed"], g["jam_density"], gr
+            return None, None, g["free_speed"], g["jam_density"], g.get("rates"), g.get("cap_mult")
 
     return SimRollout

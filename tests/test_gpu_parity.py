@@ -226,3 +226,90 @@ def test_schedules_give_identical_results(sched):
     gs = s.backward(gQ=np.ones((1,) + cr.shape[1:], np.float32), gT=[1.0])
     for k in gr:
         assert np.array_equal(gr[k], gs[k]), k
+
+
+@pytest.mark.parametrize("seed", [3, 9])
+def test_capacity_multiplier_gradient_parity(seed):
+    """Admission-time graft on the GPU against the oracle, with binding
+    buckets and random multipliers; every other group on the same run too."""
+    w = W.random_small(seed, nx=4, ny=4, n_agents=600, rates=True, steps=300)
+    w.net.capacity = np.full(w.net.n_links, 0.12, np.float32)
+    rng = np.random.default_rng(seed)
+    m = rng.uniform(0.5, 1.0, w.net.n_links).astype(np.float32)
+    o = Oracle(w, log=True, params={"cap_mult": m}).run()
+    s = _sim(w, record=True, ckpt_every=45, params={"cap_mult": m}).rollout()
+    _compare_state(o, s, ctx="trajectory")
+    cnt, _ = o.counts()
+    gQ = rng.normal(size=cnt.shape).astype(np.float32)
+    gT = 0.7
+    go = o.backward(gQ=gQ.astype(np.float64), gT=gT)
+    gg = s.backward(gQ=gQ[None], gT=[gT], groups=("free_speed", "jam_density", "rates", "cap_mult"))
+    assert np.count_nonzero(go["cap_mult"]) > 3
+    for k in ("free_speed", "jam_density", "rates", "cap_mult"):
+        _grad_close(go[k], gg[k][0], k)
+
+
+def test_bottleneck_capacity_gradient_closed_form_gpu():
+    N, q = 10, 0.5
+    w = W.line(n_links=2, length=200.0, speed=13.9, lanes=1, capacity=q, n_agents=N, steps=60)
+    m = np.float32([0.8, 1.0])
+    s = _sim(w, record=True, max_steps=60, ckpt_every=7, params={"cap_mult": m})
+    sp = 1.0 / float(np.float32(w.net.jam_density[0]))
+    s.place(list(range(N)), [0] * N, [200.0 - k * sp for k in range(N)])
+    s.step(60)
+    g = s.backward(gT=[1.0], groups=("cap_mult",))["cap_mult"][0]
+    mm = float(m[0])
+    assert g[0] == pytest.approx(-sum(k / (mm * mm * q) for k in range(1, N + 1)), rel=1e-5)
+    assert g[1] == 0.0
+
+
+def test_batched_control_gradients_match_oracle():
+    """Candidate control scenarios in one launch per step: each scenario's
+    total-travel-time gradient in the capacity multipliers of the controlled
+    links equals the oracle's for that scenario."""
+    w = W.random_small(14, nx=4, ny=4, n_agents=700, rates=True, steps=300)
+    w.net.capacity = np.full(w.net.n_links, 0.15, np.float32)
+    S = 4
+    ctrl, m = W.control_multipliers(w.net.n_links, w.net.n_links // 2, S, seed0=500)
+    seeds = [200 + k for k in range(S)]
+    s = _sim(w, n_scenarios=S, record=True, params={"cap_mult": m}, seeds=seeds).rollout()
+    gg = s.backward(gT=np.ones(S), groups=("cap_mult",))["cap_mult"]
+    for k in range(S):
+        o = Oracle(w, log=True, params={"cap_mult": m[k]}, seed=seeds[k]).run()
+        _compare_state(o, s, scen=k, ctx=f"scenario {k}")
+        go = o.backward(gT=1.0)["cap_mult"]
+        _grad_close(go, gg[k], f"cap_mult scenario {k}")
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    """The autotuner probes from the live state and puts it back: a rollout
+    tuned half-way equals an untuned one (values and gradients), and a second
+    handle of the same shape takes the cached choice without probing."""
+    w = W.random_small(12, nx=5, ny=5, n_agents=800, rates=True, steps=300, lanes_max=3)
+    gQ = np.ones((1, w.net.n_detectors, 4), np.float32)
+    ref = _sim(w, record=True, ckpt_every=50).rollout()
+    cr, tr = ref.observables()
+    gr = ref.backward(gQ=gQ, gT=[1.0], groups=("free_speed", "jam_density", "rates", "cap_mult"))
+    s = _sim(w, record=True, ckpt_every=50)
+    s.step(150)
+    before, lb = s.state(), s.link_state()
+    path = tmp_path / "schedules.txt"
+    sched = s.autotune(probe_steps=12, cache_path=str(path))
+    assert s.t == 150 and tuple(s.schedule()) == tuple(sched)
+    after, la = s.state(), s.link_state()
+    for k in ("status", "link", "pos", "seq", "counters"):
+        assert np.array_equal(before[k], after[k]), k
+    for k in lb:
+        assert np.array_equal(lb[k], la[k]), k
+    s.step(150)
+    cs, ts = s.observables()
+    assert np.array_equal(cr, cs) and np.array_equal(tr, ts)
+    gs = s.backward(gQ=gQ, gT=[1.0], groups=("free_speed", "jam_density", "rates", "cap_mult"))
+    for k in gr:
+        assert np.array_equal(gr[k], gs[k]), k
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:4] == [str(x) for x in sched]
+    s2 = _sim(w, record=True, ckpt_every=50)
+    s2.step(20)
+    assert tuple(s2.autotune(probe_steps=12, cache_path=str(path))) == tuple(sched)
+    assert len(path.read_text().splitlines()) == 1
