@@ -185,6 +185,18 @@ int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t 
  * the number of agents on the network after the step. */
 int sim_get_stats(sim_t *h, int64_t *vehicle_steps);
 
+/* Whole simulation state as an opaque host blob (agent rings, per-link and
+ * per-origin state, per-agent times, counters, detector samples, placed
+ * agents, step counter), for resuming a run or restarting it elsewhere.
+ * sim_get_full_state: with blob NULL writes the size to *n; otherwise blob
+ * must hold cap >= that many bytes (SIM_EINVAL if not).  sim_set_full_state
+ * loads a blob taken from a handle created with the same network, agent
+ * pool and configuration (SIM_EINVAL otherwise) and sets the step counter;
+ * a handle restored to t > 0 cannot run sim_backward until sim_reset
+ * (its checkpoints do not cover the restored past). */
+int sim_get_full_state(sim_t *h, void *blob, size_t cap, size_t *n);
+int sim_set_full_state(sim_t *h, const void *blob, size_t n);
+
 /* Per (scenario, link) state, host arrays [S x n_links] (any may be NULL):
  * token bucket B, cumulative outflow E, next entry sequence number. */
 int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq);
@@ -210,10 +222,10 @@ int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, con
                 const int32_t *seq, int32_t *perm, int32_t *seg_off);
 
 /* Launch schedule: lanes per work item of the link-phase and reverse
- * kernels for small rings, and the floor of the node-phase lane group
- * (each node runs on the smallest group of 16, 32 or 64 lanes, not below
- * the floor, that holds its merge candidates and out-links); 16, 32 or 64
- * each.  Results do not depend on it. */
+ * kernels for rings of at most 128 slots (8, 16, 32 or 64; larger rings run
+ * on a whole wavefront), and the floor of the node-phase lane group (16, 32
+ * or 64: each node runs on the smallest group, not below the floor, that
+ * holds its merge candidates and out-links).  Results do not depend on it. */
 int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev);
 int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
 

@@ -18,6 +18,7 @@ namespace sim {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxLanes = 8;     // lanes per link accepted by sim_create
+constexpr int kSmallRing = 128;  // rings of at most this many slots run on a lane group, larger on a wavefront
 constexpr int kMaxDetPerLink = 4;
 constexpr int kCtrSlots = 64;      // counters are spread over this many slots per scenario
 enum : int32_t { CH_STUCK = -1, CH_EXIT = -2, CH_NONE = -3 };
@@ -29,13 +30,11 @@ enum { ERR_RING_OVERFLOW = 0, ERR_CAND_OVERFLOW = 1, ERR_N = 4 };
 struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
+    int32_t rate_bin_steps;          // steps per departure-rate bin (rate bins are whole numbers of steps)
     int32_t g_link, g_node, g_rev;   // lanes per small segment / node floor / small reverse segment (16, 32, 64)
-    const int32_t *lk_small, *lk_big;  // links by ring capacity for the link phase (small: cap <= 8 g_link)
-    int32_t lk_n_small, lk_n_big;
-    const int32_t *rv_small, *rv_big;  // same split for the reverse (small: cap <= 8 g_rev)
-    int32_t rv_n_small, rv_n_big;
-    const int32_t *nd_list[3];         // nodes by lane group (16, 32, 64 lanes) for the node phase
-    int32_t nd_n[3];
+    int32_t lk_n_small, lk_n_big;    // links [0, lk_n_small): rings of <= kSmallRing slots; the rest big
+    int32_t rv_n_small, rv_n_big;    // the same split for the reverse
+    int32_t nd_begin[4], nd_n[4];    // node id ranges of the node kernel's 8-, 16-, 32- and 64-lane roles
     int64_t ring_total;
     double dt, theta, rate_bin_s;
 
@@ -52,6 +51,9 @@ struct Dev {
     const int32_t *q_dest, *q_didx;  // destination node / table row of each queue entry
     const int32_t *node_cnt;         // per node: in-degree | out-degree << 8 | origins << 16
     const int32_t *in_pad, *out_pad; // [Nn x max_in], [Nn x max_out] link ids in CSR order
+    const int32_t *in_loff;          // [Nn x max_in] first head lane of each in-link (prefix sum of lanes)
+    const int2 *cand;                // [Nn x max_cand] head lane -> (in-link, in-link index | rank << 8)
+    int32_t max_cand;
     const int2 *org_pad;             // [Nn x max_org] (origin, first queue entry)
     int32_t max_in, max_out, max_org;
     const int64_t *q_rstep;          // fixed mode: release step of each queue entry
@@ -68,6 +70,7 @@ struct Dev {
     // state
     float *ring_pos;
     int32_t *ring_agent;
+    int2 *ring_aux;                  // [S * ring_total] (destination node, table row) of each slot's agent
     int32_t *rhead, *rtail;          // [S*L]
     double *B;                       // token bucket [S*L]
     double *dB;                      // [S*L] dB/d cap_mult (recording handles only, else null)

@@ -86,40 +86,29 @@ __device__ __forceinline__ double gumbel_of(uint32_t w)
     return -log(-log(U));
 }
 
-// Route choice (SI-B): candidates are the out-links of node v that can still
-// reach the destination (and are not the reverse of `from` unless U-turns
-// are allowed); utility beta/c - theta*(t_ff + shortest time from the link's
-// head), hard choice argmax(V + g) (Gumbel-max; the temperature only shapes
-// the gradient).  Ties go to the lower candidate index.
-__device__ int choose_link(const Dev &d, int s, int a, int v, int from, int t, int *ties)
-{
-    const int beg = d.out_off[v], end = d.out_off[v + 1];
-    const double *dist = d.dist + (int64_t)d.agent_didx[a] * d.Nn;
-    const uint64_t seed = d.seed[s];
-    double best = -INFINITY, second = -INFINITY;
-    int arg = CH_STUCK, blk = -1;
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-    for (int k = beg; k < end; ++k) {
-        const int m = d.out_lnk[k], c = k - beg;
-        if (!d.allow_uturn && from >= 0 && d.head[m] == d.tail[from]) continue;
-        const double dm = dist[d.head[m]];
-        if (!(dm < INFINITY)) continue;
-        if ((c >> 2) != blk) { blk = c >> 2; draw4(seed, a, t, 0, blk, w); }
-        const double V = d.util[(int64_t)s * d.L + m] - d.theta * (d.tff[m] + dm);
-        const double sc = V + gumbel_of(w[c & 3]);
-        if (sc > best) { second = best; best = sc; arg = m; }
-        else if (sc > second) second = sc;
-    }
-    if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) ++*ties;
-    return arg;
-}
 
-__device__ __forceinline__ double merge_noise(uint64_t seed, int a, int t)
+// The same draw in single precision.  With k = w >> 8, U = (k + 1/2) 2^-24.
+// For U < 1/2 the inner value y = -ln U is at least ln 2, so the rounding of
+// U to float (2^-24 relative) and a few-ulp log keep y within ~1e-6 relative.
+// For U >= 1/2, 1 - U = (2^25 - 2k - 1) 2^-25 is an odd integer below 2^24
+// times a power of two, exact in float, and y = -log1p(-(1 - U)) keeps full
+// relative accuracy however close U is to 1.  The outer log then adds a few
+// ulp of |g| <= 18, so |g - g_double| < 1e-5.  A decision is taken on these
+// values only when it wins by kFastMargin (100 times that); otherwise it is
+// recomputed with gumbel_of, so every decision equals the double-precision one.
+__device__ __forceinline__ float gumbel_fast(uint32_t w)
 {
-    uint32_t w[4];
-    draw4(seed, a, t, 1, 0, w);
-    return gumbel_of(w[0]);
+    const uint32_t k = w >> 8;
+    float y;
+    if (k < (1u << 23)) {
+        y = -__logf(((float)k + 0.5f) * (1.0f / 16777216.0f));
+    } else {
+        const float e = (float)((1u << 25) - 2u * k - 1u) * (1.0f / 33554432.0f);
+        y = -log1pf(-e);
+    }
+    return -__logf(y);
 }
+constexpr double kFastMargin = 1e-3;
 
 // ---------------------------------------------------------------------------
 // Lane groups: a work item (segment or node) is served by G consecutive
@@ -153,8 +142,6 @@ struct Group {
     }
 };
 
-template <int G>
-__device__ __forceinline__ int group_item() { return xcd_tile() * (256 / G) + (int)threadIdx.x / G; }
 
 // Counter increments of one work item: summed over its lane group, then one
 // atomic per non-zero counter into one of kCtrSlots slots (spread by item) so
@@ -181,8 +168,9 @@ __device__ __forceinline__ void add_counters(Dev &d, const Group<G> &g, int s, i
 //   step's idle cap min(B, 1) is applied here, before the accrual), detector
 //   crossings, order check; records the heads (agent, destination) for the
 //   node phase.
-// Links are split by ring capacity: small rings (capacity <= 8G) are served
-// by G lanes, the others by a whole wavefront.  A segment is staged into LDS
+// Links are split by ring capacity: small rings (at most kSmallRing slots,
+// internal ids [0, lk_n_small)) are served by G lanes, the others by a whole
+// wavefront.  A segment is staged into LDS
 // (a piece of up to bufcap ranks plus the leader halo) with all loads in
 // flight at once, then updated from that snapshot: every input is a time-t
 // position, so the update is a pure gather.  Pieces of very long segments
@@ -225,10 +213,11 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     // head records (speculatively, lanes below the lane count)
     int hag = -1, hdst = -1, hdidx = 0;
-    if (gl < ln && gl < n) {
+    if (gl < ln && gl < n) {   // the agent's destination travels with it in the ring
         hag = d.ring_agent[base + slot_of(gl)];
-        hdst = d.agent_dest[hag];
-        hdidx = d.agent_didx[hag];
+        const int2 ax = d.ring_aux[base + slot_of(gl)];
+        hdst = ax.x;
+        hdidx = ax.y;
     }
     double Bv = 0.0, accv = 0.0, dBv = 0.0;
     int64_t Ev = 0;
@@ -335,14 +324,14 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
         const int item = xcd_remap(blockIdx.x, small_blocks) * per + (int)threadIdx.x / G;
         if (item >= small_items) return;
         const int s = item / d.lk_n_small;
-        const int seg = s * d.L + d.lk_small[item - s * d.lk_n_small];
+        const int seg = s * d.L + (item - s * d.lk_n_small);
         link_segment<G>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
     } else {
         const Group<64> g;
         const int item = xcd_remap((int)blockIdx.x - small_blocks, (int)gridDim.x - small_blocks) * 4 + (int)threadIdx.x / 64;
         if (item >= d.S * d.lk_n_big) return;
         const int s = item / d.lk_n_big;
-        const int seg = s * d.L + d.lk_big[item - s * d.lk_n_big];
+        const int seg = s * d.L + d.lk_n_small + (item - s * d.lk_n_big);
         link_segment<64>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / 64) * kBigLds, kBigLds);
     }
 }
@@ -358,7 +347,8 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 //   of each in-link's heads against its token bucket; grafted transfer:
 //   leavers pop from the in-link ring, entrants push at position 0 onto the
 //   out-link ring (SI-B eq. transfer; the graft itself lives in the adjoint).
-// Candidate lanes: in-link q, head rank r -> lane q*maxl + r; then origins.
+// Candidate lanes: the heads of in-link q take lanes [off_q, off_q + lanes_q)
+// (a per-node table gives each lane its in-link and head rank); then origins.
 // Out-link lanes k < out-degree hold the out-link's data, broadcast to the
 // candidates by shuffles; four shortest-time lookups are in flight at once.
 // Per-node link lists are padded node-major tables, so every lane finds its
@@ -371,7 +361,8 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const int maxl = d.maxl;
     const int cnt = d.node_cnt[v];
     const int deg = cnt & 0xff, dego = (cnt >> 8) & 0xff, norg = (cnt >> 16) & 0xff;
-    const int nc = deg * maxl + norg;
+    const int ncin = (cnt >> 24) & 0xff;   // head lanes of the in-links (sum of their lane counts)
+    const int nc = ncin + norg;
     const int64_t sL = (int64_t)s * d.L;
     int inc[CTR_N];
 #pragma unroll
@@ -379,9 +370,12 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
 
     // first-level loads issued together (padded tables need no offsets)
     const int om_raw = d.out_pad[(int64_t)v * d.max_out + min(gl, d.max_out - 1)];
-    const int qi = (gl < deg * maxl) ? gl / maxl : 0;
-    const int jin_cand = d.in_pad[(int64_t)v * d.max_in + min(qi, d.max_in - 1)];
+    const int2 cm = d.cand[(int64_t)v * d.max_cand + min(gl, d.max_cand - 1)];   // (in-link, q | rank << 8)
+    const bool head_lane = gl < ncin;
+    const int qi = head_lane ? (cm.y & 0xff) : 0, hr_r = head_lane ? (cm.y >> 8) : 0;
+    const int jin_cand = cm.x;
     const int jin_res = d.in_pad[(int64_t)v * d.max_in + min(gl, d.max_in - 1)];
+    const int off_res = d.in_loff[(int64_t)v * d.max_in + min(gl, d.max_in - 1)];   // first head lane of in-link gl
     // ---- out-link lanes ----
     int om = -1, ohead = -1, oslots = 0, otail = 0, obase = 0, ocap = 1;
     double outil = 0.0, otff = 0.0;
@@ -398,20 +392,23 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     // ---- in-link lanes (resolve) ----
     int64_t sjq = -1;
     double Bj = 0.0, dBj = 0.0;
-    int nhq = 0;
+    int nhq = 0, hq0 = 0;
+    int64_t Eq0 = 0;
     const bool graft = tape_k >= 0 && d.tape_dstg != nullptr;   // admission-graft tape (recording replay)
-    if (gl < deg) {
+    if (gl < deg) {   // everything this lane updates at the end is read here, with the first loads
         sjq = sL + jin_res;
         Bj = d.B[sjq];
         nhq = d.nheads[sjq];
+        hq0 = d.rhead[sjq];
+        Eq0 = d.E[sjq];
         if (graft) dBj = d.dB[sjq];
     }
     const double Bacc = Bj;   // accrued level before this step's tokens
     // ---- candidate of this lane ----
-    int ag = -1, dst = -1, didx = 0, origin = -1, from = -1, ftail = -1;
+    int ag = -1, dst = -1, didx = 0, origin = -1, from = -1, ftail = -1, dp0 = 0;
     double alpha = 1.0;
-    if (gl < deg * maxl) {
-        const int r = gl - qi * maxl;
+    if (head_lane) {
+        const int r = hr_r;
         const int jj = jin_cand;
         const int64_t sj = sL + jj;
         const int nh = d.nheads[sj];
@@ -420,42 +417,54 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         const int tl = d.tail[jj];
         if (r < nh) { ag = hr.x; dst = hr.y; didx = hr.z; from = jj; alpha = (double)al; ftail = tl; }
     } else if (gl < nc) {
-        const int2 oq = d.org_pad[(int64_t)v * d.max_org + (gl - deg * maxl)];
+        const int2 oq = d.org_pad[(int64_t)v * d.max_org + (gl - ncin)];
         origin = oq.x;
         const int qb = oq.y, qn = d.q_off[origin + 1] - qb;
         const int so = s * d.O + origin;
         const int rel = d.rel_ptr[so];
+        dp0 = d.dep_ptr[so];
+        // the queue front is the entry at the departure pointer whether or not this step releases
+        // it: load it before any release is written
+        int fa = -1, fdst = -1, fdidx = 0;
+        if (dp0 < qn) { fa = d.q_list[qb + dp0]; fdst = d.q_dest[qb + dp0]; fdidx = d.q_didx[qb + dp0]; }
         int newrel = rel;
+        double D = 0.0, rr = 1.0;
+        const double t1 = (t + 1) * d.dt;
         if (d.fixed_mode) {
-            while (newrel < qn && d.q_rstep[qb + newrel] <= (int64_t)t) {
-                const int a = d.q_list[qb + newrel];
-                d.status[(int64_t)s * d.N + a] = AG_QUEUED;
-                d.rel_t[(int64_t)s * d.N + a] = t;
-                ++newrel;
-            }
+            while (newrel < qn && d.q_rstep[qb + newrel] <= (int64_t)t) ++newrel;
         } else {
+            // bins are whole numbers of steps: step t lies in bin t / steps_per_bin, and only its
+            // neighbours can touch the step through rounding of the bin edges (bins in increasing
+            // order, as a sum over all bins would add them)
             double incr = 0.0;
-            const double t0 = t * d.dt, t1 = (t + 1) * d.dt;
-            for (int b = 0; b < d.n_rate_bins; ++b) {
+            const double t0 = t * d.dt;
+            const int bc = t / d.rate_bin_steps;
+            for (int b = max(bc - 1, 0); b <= bc + 1 && b < d.n_rate_bins; ++b) {
                 const double lo = fmax(b * d.rate_bin_s, t0), hi = fmin((b + 1) * d.rate_bin_s, t1);
                 if (hi > lo) incr += (double)d.rates[((int64_t)s * d.O + origin) * d.n_rate_bins + b] * (hi - lo);
             }
-            const double D = d.Dacc[so] + incr;
+            D = d.Dacc[so] + incr;
             if (incr != 0.0) d.Dacc[so] = D;
-            const double rr = incr / d.dt;
-            while (newrel < qn && (double)(newrel + 1) <= D) {
-                const int a = d.q_list[qb + newrel];
-                const int64_t ga = (int64_t)s * d.N + a;
+            rr = incr / d.dt;
+            while (newrel < qn && (double)(newrel + 1) <= D) ++newrel;
+        }
+        // mark the released agents, four queue entries loaded per round before their writes
+        for (int k0 = rel; k0 < newrel; k0 += 4) {
+            int a4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a4[q] = (k0 + q < newrel) ? d.q_list[qb + k0 + q] : -1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (a4[q] < 0) continue;
+                const int64_t ga = (int64_t)s * d.N + a4[q];
                 d.status[ga] = AG_QUEUED;
-                d.tstar[ga] = t1 - (D - (double)(newrel + 1)) / rr;
+                if (!d.fixed_mode) d.tstar[ga] = t1 - (D - (double)(k0 + q + 1)) / rr;
                 d.rel_t[ga] = t;
-                ++newrel;
             }
         }
         if (newrel != rel) d.rel_ptr[so] = newrel;
         inc[CTR_RELEASED] += newrel - rel;
-        const int dp = d.dep_ptr[so];
-        if (dp < newrel) { ag = d.q_list[qb + dp]; dst = d.q_dest[qb + dp]; didx = d.q_didx[qb + dp]; }
+        if (dp0 < newrel) { ag = fa; dst = fdst; didx = fdidx; }
     }
     if (g.count(ag >= 0) == 0) {   // nothing to move at this node this step
         add_counters<G>(d, g, s, item, inc);
@@ -467,35 +476,52 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const bool exiting = ag >= 0 && from >= 0 && dst == v;
     const bool chooser = ag >= 0 && !exiting;
     const double *dist = d.dist + (int64_t)didx * d.Nn;
-    double best = -INFINITY, second = -INFINITY;
-    int arg = CH_STUCK;
-    for (int b0 = 0; b0 < dego; b0 += 4) {
-        int hk[4], mk[4];
-        double tk[4], uk[4], dm[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int src = min(b0 + q, G - 1);
-            hk[q] = __shfl(ohead, src, G);
-            mk[q] = __shfl(om, src, G);
-            tk[q] = __shfl(otff, src, G);
-            uk[q] = __shfl(outil, src, G);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dm[q] = (chooser && b0 + q < dego) ? dist[hk[q]] : INFINITY;
-        if (chooser) {
-            uint32_t w[4];
-            draw4(seed, ag, t, 0, b0 >> 2, w);
+    // one pass per out-link block of 4: shortest times, Philox words, scores V + g
+    auto choice_pass = [&](bool on, bool exact, double &best, double &second, int &arg, int &argk) {
+        best = -INFINITY;
+        second = -INFINITY;
+        arg = CH_STUCK;
+        argk = 0;
+        for (int b0 = 0; b0 < dego; b0 += 4) {
+            int hk[4], mk[4];
+            double tk[4], uk[4], dm[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (b0 + q >= dego) continue;
-                if (!d.allow_uturn && from >= 0 && hk[q] == ftail) continue;
-                if (!(dm[q] < INFINITY)) continue;
-                const double V = uk[q] - d.theta * (tk[q] + dm[q]);
-                const double sc = V + gumbel_of(w[q]);
-                if (sc > best) { second = best; best = sc; arg = mk[q]; }
-                else if (sc > second) second = sc;
+                const int src = min(b0 + q, G - 1);
+                hk[q] = __shfl(ohead, src, G);
+                mk[q] = __shfl(om, src, G);
+                tk[q] = __shfl(otff, src, G);
+                uk[q] = __shfl(outil, src, G);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dm[q] = (on && b0 + q < dego) ? dist[hk[q]] : INFINITY;
+            if (on) {
+                uint32_t w[4];
+                draw4(seed, ag, t, 0, b0 >> 2, w);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (b0 + q >= dego) continue;
+                    if (!d.allow_uturn && from >= 0 && hk[q] == ftail) continue;
+                    if (!(dm[q] < INFINITY)) continue;
+                    const double V = uk[q] - d.theta * (tk[q] + dm[q]);
+                    const double gq = exact ? gumbel_of(w[q]) : (double)gumbel_fast(w[q]);
+                    const double sc = V + gq;
+                    if (sc > best) { second = best; best = sc; arg = mk[q]; argk = b0 + q; }
+                    else if (sc > second) second = sc;
+                }
             }
         }
+    };
+    double best, second;
+    int arg, argk;   // chosen link and its index among the node's out-links (the lane holding its data)
+    choice_pass(chooser, false, best, second, arg, argk);
+    // lanes whose winner is not clear on the fast noise redo the choice in double precision
+    const bool redo = chooser && second > -INFINITY && best - second < kFastMargin;
+    if (g.count(redo)) {
+        double b2, s2;
+        int a2, k2;
+        choice_pass(redo, true, b2, s2, a2, k2);
+        if (redo) { best = b2; second = s2; arg = a2; argk = k2; }
     }
     int ch = CH_NONE;
     if (chooser) {
@@ -504,28 +530,45 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     } else if (exiting) {
         ch = CH_EXIT;
     }
+    // merge key alpha_from + g' on the fast noise; exact below where two keys for one link are close
+    uint32_t wm[4] = {0u, 0u, 0u, 0u};
     double key = 0.0;
-    if (ag >= 0) key = alpha + merge_noise(seed, ag, t);
+    if (ag >= 0) {
+        draw4(seed, ag, t, 1, 0, wm);
+        key = alpha + (double)gumbel_fast(wm[0]);
+    }
 
     // ---- merge: rank among candidates wanting the same link ----
     // the loops below visit only lanes that hold a candidate (group-uniform mask)
-    const unsigned long long cmask = g.mask(ag >= 0);
+    // rank among the choosers of the same out-link: one ballot per out-link, pairwise key
+    // comparisons only where at least two candidates want it
     int rank = 0, close = 0;
-    for (unsigned long long mm = cmask; mm; mm &= mm - 1) {
-        const int src = __ffsll((long long)mm) - 1;
-        const int c2 = __shfl(ch, src, G);
-        const double k2 = __shfl(key, src, G);
-        const int a2 = __shfl(ag, src, G);
-        if (ch >= 0 && c2 == ch && src != gl) {
-            if (k2 > key || (k2 == key && a2 < ag)) ++rank;
-            else if (key - k2 < 1e-12 * (1.0 + fabs(key))) close = 1;
+    bool knear = false;
+    auto rank_pass = [&]() {
+        rank = 0;
+        close = 0;
+        for (int k = 0; k < dego; ++k) {
+            const int omk = __shfl(om, k, G);
+            const unsigned long long mk = g.mask(ag >= 0 && ch == omk);
+            if (__popcll(mk) < 2) continue;
+            for (unsigned long long mm = mk; mm; mm &= mm - 1) {
+                const int src = __ffsll((long long)mm) - 1;
+                const double k2 = __shfl(key, src, G);
+                const int a2 = __shfl(ag, src, G);
+                if (ag >= 0 && ch == omk && src != gl) {
+                    if (k2 > key || (k2 == key && a2 < ag)) ++rank;
+                    else if (key - k2 < 1e-12 * (1.0 + fabs(key))) close = 1;
+                    knear |= fabs(k2 - key) < kFastMargin;
+                }
+            }
         }
+    };
+    rank_pass();
+    if (g.count(knear)) {   // keys of competing candidates too close for the fast noise: all exact
+        if (ag >= 0) key = alpha + gumbel_of(wm[0]);
+        rank_pass();
     }
-    int sl = 0;
-    for (int k = 0; k < dego; ++k) {
-        const int mk = __shfl(om, k, G), sk = __shfl(oslots, k, G);
-        if (mk == ch) sl = sk;
-    }
+    const int sl = __shfl(oslots, min(argk, G - 1), G);
     const int won = (ch >= 0) && rank < sl;
     if (ch >= 0) inc[CTR_TIES] += close;
 
@@ -533,7 +576,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     int np = 0;
     bool stop = false, consumed = false;
     for (int r = 0; r < maxl; ++r) {
-        const int src = min(gl * maxl + r, G - 1);
+        const int src = min(off_res + r, G - 1);
         const int c2 = __shfl(ch, src, G);
         const int w2 = __shfl(won, src, G);
         if (gl < deg && !stop && r < nhq) {
@@ -545,33 +588,33 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     if (gl < deg) {
         if (consumed) d.B[sjq] = Bj;   // the idle cap min(B, 1) is applied at the next accrual
         if (np) {
-            d.E[sjq] += np;
-            d.rhead[sjq] += np;
+            d.E[sjq] = Eq0 + np;
+            d.rhead[sjq] = hq0 + np;
         }
     }
-    const int q_of_lane = (gl < deg * maxl) ? gl / maxl : 0;
+    const int q_of_lane = qi;
     const int np_q = __shfl(np, q_of_lane, G);
     int passed = 0;
-    if (gl < deg * maxl) passed = (ag >= 0) && (gl - q_of_lane * maxl) < np_q;
+    if (head_lane) passed = (ag >= 0) && hr_r < np_q;
     else passed = (origin >= 0 && ag >= 0 && won);
 
-    // ---- entrants per out-link (lanes < dego) and each entrant's place in key order ----
+    // ---- entrants per out-link (lane k < dego counts link k's) and each entrant's place in key order ----
     int nent = 0, erank = 0;
-    for (unsigned long long mm = g.mask(passed != 0); mm; mm &= mm - 1) {
-        const int src = __ffsll((long long)mm) - 1;
-        const int c2 = __shfl(ch, src, G);
-        const int p2 = 1;
-        const double k2 = __shfl(key, src, G);
-        const int a2 = __shfl(ag, src, G);
-        nent += (p2 && c2 == om && om >= 0);
-        if (passed && ch >= 0 && p2 && c2 == ch && src != gl && (k2 > key || (k2 == key && a2 < ag))) ++erank;
+    for (int k = 0; k < dego; ++k) {
+        const int omk = __shfl(om, k, G);
+        const unsigned long long pm = g.mask(passed && ch == omk);
+        if (gl == k) nent = __popcll(pm);
+        if (__popcll(pm) < 2) continue;
+        for (unsigned long long mm = pm; mm; mm &= mm - 1) {
+            const int src = __ffsll((long long)mm) - 1;
+            const double k2 = __shfl(key, src, G);
+            const int a2 = __shfl(ag, src, G);
+            if (passed && ch == omk && src != gl && (k2 > key || (k2 == key && a2 < ag))) ++erank;
+        }
     }
     if (gl < dego && nent) d.rtail[sL + om] = otail + nent;
-    int tbase = 0, rbase = 0, rcap = 1;
-    for (int k = 0; k < dego; ++k) {
-        const int mk = __shfl(om, k, G), tk = __shfl(otail, k, G), bk = __shfl(obase, k, G), ck = __shfl(ocap, k, G);
-        if (mk == ch) { tbase = tk; rbase = bk; rcap = ck; }
-    }
+    const int ksrc = min(argk, G - 1);
+    const int tbase = __shfl(otail, ksrc, G), rbase = __shfl(obase, ksrc, G), rcap = __shfl(ocap, ksrc, G);
     const int64_t ga = (int64_t)s * d.N + (ag >= 0 ? ag : 0);
     const int64_t slot = (int64_t)s * d.ring_total + rbase + (tbase + erank) % rcap;
     // admission graft: a head leaving on a token carries the token's availability
@@ -580,10 +623,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     float gfac = 0.f;
     if (graft) {
         const double Bq = __shfl(Bacc, q_of_lane, G), dBq = __shfl(dBj, q_of_lane, G);
-        const int myr = gl - q_of_lane * maxl;
+        const int myr = hr_r, myoff = __shfl(off_res, q_of_lane, G);
         int tok = 0;
         for (int r = 0; r < maxl; ++r) {
-            const int c2 = __shfl(ch, min(q_of_lane * maxl + r, G - 1), G);
+            const int c2 = __shfl(ch, min(myoff + r, G - 1), G);
             tok += (r < myr && c2 >= 0);
         }
         if (passed && from >= 0 && ch >= 0) {
@@ -596,18 +639,19 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         }
     }
     if (tape_k >= 0 && passed && from >= 0) {   // where each leaving head went (-1: left the network)
-        const int64_t ti = ((int64_t)tape_k * d.S * d.L + sL + from) * maxl + (gl - qi * maxl);
+        const int64_t ti = ((int64_t)tape_k * d.S * d.L + sL + from) * maxl + hr_r;
         d.tape_dst[ti] = ch >= 0 ? (int32_t)slot : -1;
         if (graft) d.tape_dstg[ti] = gfac;
     }
     if (passed) {
         if (ch >= 0) {
             d.ring_agent[slot] = ag;
+            d.ring_aux[slot] = make_int2(dst, didx);
             d.ring_pos[slot] = 0.f;
             if (origin >= 0) {
                 d.status[ga] = AG_ON;
                 d.dep_t[ga] = t;
-                d.dep_ptr[s * d.O + origin] += 1;
+                d.dep_ptr[s * d.O + origin] = dp0 + 1;
                 inc[CTR_DEPARTED] += 1;
             } else {
                 inc[CTR_TRANSFERS] += 1;
@@ -622,33 +666,43 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
 }
 
 // Node phase launch: nodes are split on the host into classes by the lane
-// group that holds their candidates (16, 32 or 64 lanes, never below the
-// schedule's floor); one launch runs the three classes as block roles, each
-// role's block range remapped so that neighbouring nodes share an XCD.
+// group that holds their candidates (8, 16, 32 or 64 lanes, never below the
+// schedule's floor; each class a contiguous id range); one launch runs the
+// four classes as block roles, each role's block range remapped so that
+// neighbouring nodes share an XCD.
+template <int G>
+__device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t, int tape_k)
+{
+    const Group<G> g;
+    const int per = 256 / G;
+    const int n = d.S * d.nd_n[c];
+    const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / G;
+    if (item >= n) return true;
+    const int s = item / d.nd_n[c];
+    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k);
+    return true;
+}
+
+__host__ __device__ __forceinline__ int node_role_blocks(int n, int G, bool last)
+{
+    const int per = 256 / G;
+    const int b = (n + per - 1) / per;
+    return last ? b : ((b + 7) & ~7);   // inner roles in multiples of 8 keep the XCD pattern
+}
+
 __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
 {
-    const int b = (int)blockIdx.x;
-    const int n16 = d.S * d.nd_n[0], n32 = d.S * d.nd_n[1], n64 = d.S * d.nd_n[2];
-    const int b16 = ((n16 + 15) / 16 + 7) & ~7, b32 = ((n32 + 7) / 8 + 7) & ~7;
-    if (b < b16) {
-        const Group<16> g;
-        const int item = xcd_remap(b, b16) * 16 + (int)threadIdx.x / 16;
-        if (item >= n16) return;
-        const int s = item / d.nd_n[0];
-        node_work<16>(d, g, s, d.nd_list[0][item - s * d.nd_n[0]], item, t, tape_k);
-    } else if (b < b16 + b32) {
-        const Group<32> g;
-        const int item = xcd_remap(b - b16, b32) * 8 + (int)threadIdx.x / 32;
-        if (item >= n32) return;
-        const int s = item / d.nd_n[1];
-        node_work<32>(d, g, s, d.nd_list[1][item - s * d.nd_n[1]], item, t, tape_k);
-    } else {
-        const Group<64> g;
-        const int item = xcd_remap(b - b16 - b32, (int)gridDim.x - b16 - b32) * 4 + (int)threadIdx.x / 64;
-        if (item >= n64) return;
-        const int s = item / d.nd_n[2];
-        node_work<64>(d, g, s, d.nd_list[2][item - s * d.nd_n[2]], item, t, tape_k);
-    }
+    int b = (int)blockIdx.x;
+    const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
+    if (b < b8) { node_role<8>(d, 0, b, b8, t, tape_k); return; }
+    b -= b8;
+    const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
+    if (b < b16) { node_role<16>(d, 1, b, b16, t, tape_k); return; }
+    b -= b16;
+    const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
+    if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k); return; }
+    b -= b32;
+    node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k);
 }
 
 // Tape entry without an update (the state at the end of a replay window).
@@ -693,8 +747,8 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
 // t (a ring keeps `lanes` slots free), so concurrent segments do not race.
 // init = 1: adj_ring = dL/dx(T) at the final state (no step).
 // ---------------------------------------------------------------------------
-constexpr int kRevSmall = 8;        // small segments: capacity <= kRevSmall * G
-constexpr int kRevBigLds = 1152;    // LDS words per wavefront for big segments (two arrays)
+constexpr int kRevSmall = 8;        // staging of a small segment: kRevSmall * G >= kSmallRing slots
+constexpr int kRevBigLds = 1280;    // LDS words per wavefront for big segments (two arrays)
 
 template <int G>
 __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
@@ -739,6 +793,12 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     const int piece = P - 2 * kMaxLanes;
     const int64_t dst0 = ((int64_t)tape_k * SL + seg) * d.maxl;
     double gu = 0.0, gk = 0.0, gm = 0.0;
+    double gu0 = 0.0, gk0 = 0.0, gm0 = 0.0;   // accumulators of this segment, read with the first loads
+    if (gl == 0 && !init) {
+        gu0 = d.gu[seg];
+        gk0 = d.gk[seg];
+        if (d.gm) gm0 = d.gm[seg];
+    }
     for (int lo = 0; lo < n; lo += piece) {
         const int hi = min(n, lo + piece);
         const int slo = max(0, lo - ln), shi = min(n, hi + ln);
@@ -815,9 +875,9 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     gk = g.sum(gk);
     if (d.gm) gm = g.sum(gm);
     if (gl == 0 && !init) {
-        d.gu[seg] += gu;
-        d.gk[seg] += gk;
-        if (d.gm) d.gm[seg] += gm;
+        d.gu[seg] = gu0 + gu;
+        d.gk[seg] = gk0 + gk;
+        if (d.gm) d.gm[seg] = gm0 + gm;
     }
 }
 
@@ -835,14 +895,14 @@ __global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int i
         const int item = xcd_remap(blockIdx.x, small_blocks) * per + (int)threadIdx.x / G;
         if (item >= small_items) return;
         const int s = item / d.rv_n_small;
-        const int seg = s * d.L + d.rv_small[item - s * d.rv_n_small];
+        const int seg = s * d.L + (item - s * d.rv_n_small);
         reverse_segment<G>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
     } else {
         const Group<64> g;
         const int item = xcd_remap((int)blockIdx.x - small_blocks, (int)gridDim.x - small_blocks) * 4 + (int)threadIdx.x / 64;
         if (item >= d.S * d.rv_n_big) return;
         const int s = item / d.rv_n_big;
-        const int seg = s * d.L + d.rv_big[item - s * d.rv_n_big];
+        const int seg = s * d.L + d.rv_n_small + (item - s * d.rv_n_big);
         reverse_segment<64>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / 64) * kRevBigLds, kRevBigLds);
     }
 }
@@ -1087,6 +1147,7 @@ static inline int class_blocks(int S, int n_small, int n_big, int G)
 void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 {
     switch (d.g_link) {
+    case 8: hipLaunchKernelGGL(k_link<8>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 8)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
     case 16: hipLaunchKernelGGL(k_link<16>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 16)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
     case 32: hipLaunchKernelGGL(k_link<32>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 32)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
     default: hipLaunchKernelGGL(k_link<64>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 64)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
@@ -1094,8 +1155,8 @@ void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 }
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
 {
-    const int n16 = d.S * d.nd_n[0], n32 = d.S * d.nd_n[1], n64 = d.S * d.nd_n[2];
-    const int blocks = (((n16 + 15) / 16 + 7) & ~7) + (((n32 + 7) / 8 + 7) & ~7) + (n64 + 3) / 4;
+    const int blocks = node_role_blocks(d.S * d.nd_n[0], 8, false) + node_role_blocks(d.S * d.nd_n[1], 16, false) +
+                       node_role_blocks(d.S * d.nd_n[2], 32, false) + node_role_blocks(d.S * d.nd_n[3], 64, true);
     hipLaunchKernelGGL(k_node, dim3(std::max(blocks, 1)), dim3(256), 0, st, d, t, tape_k);
 }
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
@@ -1105,6 +1166,7 @@ void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st)
 {
     switch (d.g_rev) {
+    case 8: hipLaunchKernelGGL(k_reverse<8>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 8)), dim3(256), 0, st, d, t, tape_k, init); break;
     case 16: hipLaunchKernelGGL(k_reverse<16>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 16)), dim3(256), 0, st, d, t, tape_k, init); break;
     case 32: hipLaunchKernelGGL(k_reverse<32>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 32)), dim3(256), 0, st, d, t, tape_k, init); break;
     default: hipLaunchKernelGGL(k_reverse<64>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 64)), dim3(256), 0, st, d, t, tape_k, init); break;

@@ -51,6 +51,7 @@ struct InvalidArg {
 struct Ckpt {
     float *ring_pos = nullptr;
     int32_t *ring_agent = nullptr;
+    int2 *ring_aux = nullptr;
     int32_t *rhead = nullptr, *rtail = nullptr;
     double *B = nullptr, *dB = nullptr;
     int64_t *E = nullptr;
@@ -74,10 +75,8 @@ struct sim_t {
     double dt = 1.0, rate_bin_s = 0.0;
     int32_t platoon = 1, ckpt_every = 60, max_steps = 0, record = 0;
     int32_t g_link = 16, g_node = 64, g_rev = 16;   // lanes per work item
-    int32_t *lk_small_dev = nullptr, *lk_big_dev = nullptr, *rv_small_dev = nullptr, *rv_big_dev = nullptr;
-    size_t lk_small_cap = 0, lk_big_cap = 0, rv_small_cap = 0, rv_big_cap = 0;
-    int32_t *nd_dev[3] = {nullptr, nullptr, nullptr};
-    size_t nd_cap[3] = {0, 0, 0};
+    int32_t n_small_links = 0;         // internal links [0, n_small_links) have rings of <= kSmallRing slots
+    int32_t nd_off[5] = {0, 0, 0, 0, 0};  // internal nodes by lane-group class (8, 16, 32, 64 lanes), contiguous
     std::vector<int32_t> tail, head, lanes, origin_node, det_link, agent_origin, agent_dest;
     std::vector<float> length, free_speed, jam_density, capacity, beta, alpha, cost, det_pos, ready, rates;
     std::vector<uint64_t> seeds;
@@ -99,6 +98,15 @@ struct sim_t {
     // mutable parameter buffers
     float *p_u = nullptr, *p_kappa = nullptr, *p_beta = nullptr, *p_alpha = nullptr, *p_cost = nullptr,
           *p_rates = nullptr, *p_capm = nullptr, *capacity_dev = nullptr;
+    // two tape sets: the reverse sweep of one window reads one while the replay of the window
+    // before it writes the other, on a second stream
+    struct TapeSet {
+        float *pos = nullptr, *dstg = nullptr;
+        int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *dst = nullptr;
+    };
+    TapeSet tapes[2];
+    hipStream_t aux = nullptr;               // replay stream of the backward pass
+    std::vector<hipEvent_t> bw_events;       // replay-done and reverse-done events per window
     float *tape_dstg_buf = nullptr;   // admission-graft tape, attached only for cap_mult gradients
     double *gm_buf = nullptr;
     // autotuner snapshot of the live state (allocated on first use)
@@ -113,7 +121,9 @@ struct sim_t {
     int64_t *q_rstep_dev = nullptr;
     int2 *org_pad_dev = nullptr;
     std::vector<int32_t> node_cnt, in_pad, out_pad;
-    int32_t max_in = 1, max_out = 1, max_org = 1;
+    int32_t max_in = 1, max_out = 1, max_org = 1, max_cand = 1;
+    std::vector<int32_t> in_loff;
+    std::vector<int2> cand;
     // adjoint buffers
     float *gQ_dev = nullptr, *gx_dev = nullptr;
     double *gT_dev = nullptr, *ttt_dev = nullptr;
@@ -132,6 +142,7 @@ struct sim_t {
     std::vector<Ckpt> ckpts;  // [n_ckpt] + final
     int W = 0;                // tape window (= ckpt_every)
     bool rec_valid = false;
+    std::vector<uint8_t> placed;  // agents put on links by sim_place (not in the origin queues)
 
     // timing
     bool timing = false;
@@ -163,6 +174,8 @@ struct sim_t {
         if (stream) (void)hipStreamSynchronize(stream);
         for (auto &e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (auto e : ev_pool) (void)hipEventDestroy(e);
+        if (aux) { (void)hipStreamSynchronize(aux); (void)hipStreamDestroy(aux); }
+        for (auto e : bw_events) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
 
@@ -345,6 +358,21 @@ void upload_queues(sim_t *h)
 // (new tail node, original id), so a node's out-links stay in original-id
 // order.  Callers always see the original numbering; the runtime translates
 // at the boundary.
+// ring slots of a link: a lane chain holds at most floor(L / spacing) + 2 agents under float
+// rounding; one more row per lane keeps `lanes` slots free for the step's leavers
+double ring_slots(float length, int lanes, float jam_density, int platoon)
+{
+    const float sp = (float)platoon / jam_density;
+    return (std::floor((double)length / (double)sp) + 4.0) * lanes;
+}
+
+// lane-group class of a node from its merge candidates and out-links: 0 (16), 1 (32), 2 (64 lanes)
+int node_class(int need) { return need <= 8 ? 0 : (need <= 16 ? 1 : (need <= 32 ? 2 : 3)); }
+
+// Internal numbering.  Nodes: reverse Cuthill-McKee for locality, then grouped by lane-group class
+// (stable), so each class of the node kernel is a contiguous id range.  Links: small rings first,
+// then by new tail node and original id, so each class of the link and reverse kernels is a
+// contiguous id range and a node's out-links lie together.
 void renumber(sim_t *h)
 {
     const int Nn = h->Nn, L = h->L;
@@ -378,12 +406,33 @@ void renumber(sim_t *h)
         }
     }
     std::reverse(order.begin(), order.end());
+    {
+        std::vector<int> din(Nn, 0), dout(Nn, 0), norg(Nn, 0), cls(Nn, 0);
+        // candidates of a node: a head lane per lane of each in-link, plus its origin queues
+        for (int j = 0; j < L; ++j) { din[h->head[j]] += h->lanes[j]; dout[h->tail[j]]++; }
+        for (int o = 0; o < h->O; ++o) norg[h->origin_node[o]]++;
+        for (int v = 0; v < Nn; ++v) cls[v] = node_class(std::max(din[v] + norg[v], dout[v]));
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls[a] < cls[b]; });
+        h->nd_off[0] = 0;
+        for (int c = 0; c < 4; ++c) {
+            int n = 0;
+            for (int v = 0; v < Nn; ++v) n += cls[v] == c;
+            h->nd_off[c + 1] = h->nd_off[c] + n;
+        }
+    }
     h->nperm = order;
     h->ninv.assign(Nn, 0);
     for (int k = 0; k < Nn; ++k) h->ninv[order[k]] = k;
+    std::vector<char> big(L);
+    h->n_small_links = 0;
+    for (int j = 0; j < L; ++j) {
+        big[j] = ring_slots(h->length[j], h->lanes[j], h->jam_density[j], h->platoon) > sim::kSmallRing;
+        h->n_small_links += !big[j];
+    }
     h->lperm.resize(L);
     for (int j = 0; j < L; ++j) h->lperm[j] = j;
     std::sort(h->lperm.begin(), h->lperm.end(), [&](int a, int b) {
+        if (big[a] != big[b]) return big[a] < big[b];
         const int ta = h->ninv[h->tail[a]], tb = h->ninv[h->tail[b]];
         return ta != tb ? ta < tb : a < b;
     });
@@ -410,36 +459,20 @@ std::vector<float> links_in(const sim_t *h, const float *v)
     return o;
 }
 
-// links split by ring capacity for the link phase and the reverse
+// work-item ranges of the link, node and reverse kernels (contiguous id ranges, see renumber)
 void build_classes(sim_t *h)
 {
-    std::vector<int32_t> ls, lb, rs, rb;
-    for (int j = 0; j < h->L; ++j) {
-        (h->cap[j] <= 8 * h->g_link ? ls : lb).push_back(j);
-        (h->cap[j] <= 8 * h->g_rev ? rs : rb).push_back(j);
-    }
-    auto put = [&](int32_t *&dev, size_t &capn, const std::vector<int32_t> &v) {
-        if (!dev || capn < v.size() + 1) { dev = h->dalloc<int32_t>(v.size() + 1); capn = v.size() + 1; }
-        if (!v.empty()) HIPCHK(hipMemcpyAsync(dev, v.data(), v.size() * 4, hipMemcpyHostToDevice, h->stream));
-    };
-    put(h->lk_small_dev, h->lk_small_cap, ls);
-    put(h->lk_big_dev, h->lk_big_cap, lb);
-    put(h->rv_small_dev, h->rv_small_cap, rs);
-    put(h->rv_big_dev, h->rv_big_cap, rb);
-    // nodes by the lane group that holds their merge candidates and out-links
-    std::vector<int32_t> nd[3];
-    for (int v = 0; v < h->Nn; ++v) {
-        const int need = std::max((h->in_off[v + 1] - h->in_off[v]) * h->maxl + (h->org_off[v + 1] - h->org_off[v]),
-                                  h->out_off[v + 1] - h->out_off[v]);
-        const int gv = std::max(h->g_node, need <= 16 ? 16 : (need <= 32 ? 32 : 64));
-        nd[gv == 16 ? 0 : (gv == 32 ? 1 : 2)].push_back(v);
-    }
-    for (int c = 0; c < 3; ++c) put(h->nd_dev[c], h->nd_cap[c], nd[c]);
     Dev &d = h->d;
-    for (int c = 0; c < 3; ++c) { d.nd_list[c] = h->nd_dev[c]; d.nd_n[c] = (int)nd[c].size(); }
-    d.lk_small = h->lk_small_dev; d.lk_big = h->lk_big_dev; d.lk_n_small = (int)ls.size(); d.lk_n_big = (int)lb.size();
-    d.rv_small = h->rv_small_dev; d.rv_big = h->rv_big_dev; d.rv_n_small = (int)rs.size(); d.rv_n_big = (int)rb.size();
-    HIPCHK(hipStreamSynchronize(h->stream));
+    d.lk_n_small = d.rv_n_small = h->n_small_links;
+    d.lk_n_big = d.rv_n_big = h->L - h->n_small_links;
+    // node roles of 8, 16, 32 and 64 lanes; the schedule's floor moves smaller classes up
+    const int r1 = h->g_node <= 8 ? h->nd_off[1] : 0;
+    const int r2 = h->g_node <= 16 ? h->nd_off[2] : 0;
+    const int r3 = h->g_node <= 32 ? h->nd_off[3] : 0;
+    d.nd_begin[0] = 0;  d.nd_n[0] = r1;
+    d.nd_begin[1] = r1; d.nd_n[1] = r2 - r1;
+    d.nd_begin[2] = r2; d.nd_n[2] = r3 - r2;
+    d.nd_begin[3] = r3; d.nd_n[3] = h->Nn - r3;
 }
 
 void derive(sim_t *h)
@@ -464,6 +497,7 @@ void ckpt_alloc(sim_t *h, Ckpt &c)
     const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
     c.ring_pos = h->dalloc<float>(SR);
     c.ring_agent = h->dalloc<int32_t>(SR);
+    c.ring_aux = h->dalloc<int2>(SR);
     c.rhead = h->dalloc<int32_t>(SL);
     c.rtail = h->dalloc<int32_t>(SL);
     c.B = h->dalloc<double>(SL);
@@ -487,6 +521,7 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save)
     };
     cp(c.ring_pos, d.ring_pos, SR * 4);
     cp(c.ring_agent, d.ring_agent, SR * 4);
+    cp(c.ring_aux, d.ring_aux, SR * 8);
     cp(c.rhead, d.rhead, SL * 4);
     cp(c.rtail, d.rtail, SL * 4);
     cp(c.B, d.B, SL * 8);
@@ -640,30 +675,54 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     build_csr(Nn, h->head, h->in_off, h->in_lnk);
     build_csr(Nn, h->origin_node, h->org_off, h->org_list);
     build_csr(L, h->det_link, h->det_off, h->det_list);
+    // a node's out-links in original id order: the route-choice candidate index (which picks the
+    // Gumbel draw) is the caller's CSR position
     for (int v = 0; v < Nn; ++v) {
-        const int nc = (h->in_off[v + 1] - h->in_off[v]) * maxl + (h->org_off[v + 1] - h->org_off[v]);
+        std::sort(h->out_lnk.begin() + h->out_off[v], h->out_lnk.begin() + h->out_off[v + 1],
+                  [&](int a, int b) { return h->lperm[a] < h->lperm[b]; });
+        std::sort(h->in_lnk.begin() + h->in_off[v], h->in_lnk.begin() + h->in_off[v + 1],
+                  [&](int a, int b) { return h->lperm[a] < h->lperm[b]; });
+    }
+    for (int v = 0; v < Nn; ++v) {
+        int nc = h->org_off[v + 1] - h->org_off[v];
+        for (int k = h->in_off[v]; k < h->in_off[v + 1]; ++k) nc += h->lanes[h->in_lnk[k]];
         if (nc > sim::kWave) fail(SIM_EUNSUPPORTED, "node " + std::to_string(v) + ": more than 64 merge candidates");
         if (h->out_off[v + 1] - h->out_off[v] > sim::kWave) fail(SIM_EUNSUPPORTED, "node out-degree above 64");
     }
     for (int j = 0; j < L; ++j)
         if (h->det_off[j + 1] - h->det_off[j] > sim::kMaxDetPerLink) fail(SIM_EUNSUPPORTED, "more than 4 detectors on a link");
-    // lanes per node: a floor; each node gets the smallest group (16, 32, 64) above it that holds
+    // lanes per node: a floor; each node gets the smallest group (8, 16, 32, 64) above it that holds
     // its candidates and out-links
-    h->g_node = 16;
+    h->g_node = 8;
+    (void)maxl;
     for (int v = 0; v < Nn; ++v) {
         h->max_in = std::max(h->max_in, h->in_off[v + 1] - h->in_off[v]);
         h->max_out = std::max(h->max_out, h->out_off[v + 1] - h->out_off[v]);
         h->max_org = std::max(h->max_org, h->org_off[v + 1] - h->org_off[v]);
     }
     if (h->max_in > 255 || h->max_out > 255 || h->max_org > 255) fail(SIM_EUNSUPPORTED, "node degree above 255");
+    for (int v = 0; v < Nn; ++v) {
+        int nl = 0;
+        for (int k = h->in_off[v]; k < h->in_off[v + 1]; ++k) nl += h->lanes[h->in_lnk[k]];
+        h->max_cand = std::max(h->max_cand, nl);
+    }
     h->node_cnt.resize(Nn);
     h->in_pad.assign((size_t)Nn * h->max_in, -1);
+    h->in_loff.assign((size_t)Nn * h->max_in, 0);
     h->out_pad.assign((size_t)Nn * h->max_out, -1);
+    h->cand.assign((size_t)Nn * h->max_cand, make_int2(0, 0));
     for (int v = 0; v < Nn; ++v) {
         const int di = h->in_off[v + 1] - h->in_off[v], dout = h->out_off[v + 1] - h->out_off[v];
         const int no = h->org_off[v + 1] - h->org_off[v];
-        h->node_cnt[v] = di | (dout << 8) | (no << 16);
-        for (int k = 0; k < di; ++k) h->in_pad[(size_t)v * h->max_in + k] = h->in_lnk[h->in_off[v] + k];
+        int nl = 0;
+        for (int k = 0; k < di; ++k) {
+            const int j = h->in_lnk[h->in_off[v] + k];
+            h->in_pad[(size_t)v * h->max_in + k] = j;
+            h->in_loff[(size_t)v * h->max_in + k] = nl;
+            for (int r = 0; r < h->lanes[j]; ++r) h->cand[(size_t)v * h->max_cand + nl + r] = make_int2(j, k | (r << 8));
+            nl += h->lanes[j];
+        }
+        h->node_cnt[v] = di | (dout << 8) | (no << 16) | (nl << 24);
         for (int k = 0; k < dout; ++k) h->out_pad[(size_t)v * h->max_out + k] = h->out_lnk[h->out_off[v] + k];
     }
     // rings: a link holds at most lanes * (floor(L / spacing) + 1) agents; two extra rows of slack
@@ -672,12 +731,8 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     h->min_spacing.resize(L);
     int64_t tot = 0;
     for (int j = 0; j < L; ++j) {
-        const float sp = (float)h->platoon / h->jam_density[j];
-        h->min_spacing[j] = sp;
-        // a lane chain holds at most floor(L / spacing) + 2 agents under float rounding; one
-        // more row per lane keeps `lanes` slots free for the step's leavers
-        const double rows = std::floor((double)h->length[j] / (double)sp) + 4.0;
-        const double c = rows * h->lanes[j];
+        h->min_spacing[j] = (float)h->platoon / h->jam_density[j];
+        const double c = ring_slots(h->length[j], h->lanes[j], h->jam_density[j], h->platoon);
         if (c > 1e8) fail(SIM_EUNSUPPORTED, "link too long for its jam spacing");
         h->cap[j] = (int32_t)c;
         h->ring_base[j] = (int32_t)tot;
@@ -706,14 +761,14 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     // ---------------- memory budget ----------------
     const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
     const size_t SR = (size_t)h->S * h->ring_total;
-    size_t bytes = SR * 8 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
+    size_t bytes = SR * 16 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
                    h->dist.size() * 8 + (size_t)h->S * h->D * h->nb * 8;
     int n_ck = 0;
     if (h->record) {
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
         h->W = h->ckpt_every;
-        bytes += (size_t)n_ck * (SR * 8 + SL * 24 + SO * 16 + SN);
-        bytes += (size_t)(h->W + 1) * (SR * 8 + SL * 8 + SL * maxl * 4) + SR * 4 + SN * 4 + SL * 16;
+        bytes += (size_t)n_ck * (SR * 16 + SL * 32 + SO * 16 + SN);
+        bytes += 2 * (size_t)(h->W + 1) * (SR * 8 + SL * 8 + SL * maxl * 8) + SR * 4 + SN * 4 + SL * 24;
     }
     h->footprint = bytes;
     h->n_ck = n_ck;
@@ -734,6 +789,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.fixed_mode = h->fixed_mode; d.allow_uturn = cfg->allow_uturn; d.platoon = h->platoon;
     d.g_link = h->g_link; d.g_node = h->g_node; d.g_rev = h->g_rev;
     d.ring_total = h->ring_total; d.dt = h->dt; d.theta = cfg->dest_logit_coef; d.rate_bin_s = h->rate_bin_s;
+    d.rate_bin_steps = h->fixed_mode ? 1 : std::max(1, (int)std::lround(h->rate_bin_s / h->dt));
     d.tail = h->upload(h->tail); d.head = h->upload(h->head); d.lanes = h->upload(h->lanes);
     h->linv_dev = h->upload(h->linv);
     d.cap = h->upload(h->cap); d.ring_base = h->upload(h->ring_base);
@@ -759,6 +815,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
     d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev; d.org_pad = h->org_pad_dev;
     d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
+    d.in_loff = h->upload(h->in_loff); d.cand = h->upload(h->cand); d.max_cand = h->max_cand;
     d.max_in = h->max_in; d.max_out = h->max_out; d.max_org = h->max_org;
     d.seed = h->upload(h->seeds);
     // parameters, scenario-major
@@ -778,7 +835,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     h->util = h->dalloc<double>(SL); h->acc = h->dalloc<double>(SL);
     d.vfree = h->vfree; d.spacing = h->spacing; d.util = h->util; d.acc = h->acc;
     // state
-    d.ring_pos = h->dalloc<float>(SR); d.ring_agent = h->dalloc<int32_t>(SR);
+    d.ring_pos = h->dalloc<float>(SR); d.ring_agent = h->dalloc<int32_t>(SR); d.ring_aux = h->dalloc<int2>(SR);
     d.rhead = h->dalloc<int32_t>(SL); d.rtail = h->dalloc<int32_t>(SL);
     d.B = h->dalloc<double>(SL); d.E = h->dalloc<int64_t>(SL);
     d.slots = h->dalloc<int32_t>(SL); d.nheads = h->dalloc<int32_t>(SL);
@@ -794,15 +851,24 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     if (h->record) {
         h->ckpts.resize(n_ck + 1);
         for (auto &c : h->ckpts) ckpt_alloc(h, c);
-        d.tape_pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
-        d.tape_agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
-        d.tape_head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
-        d.tape_tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+        for (auto &ts : h->tapes) {
+            ts.pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
+            ts.agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
+            ts.head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+            ts.tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+            ts.dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
+            ts.dstg = h->dalloc<float>((size_t)(h->W + 1) * SL * maxl);
+        }
+        d.tape_pos = h->tapes[0].pos; d.tape_agent = h->tapes[0].agent;
+        d.tape_head = h->tapes[0].head; d.tape_tail = h->tapes[0].tail;
+        HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+        h->bw_events.resize(2 * (size_t)n_ck + 2, nullptr);
+        for (auto &e : h->bw_events) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         d.adj_ring = h->dalloc<float>(SR); d.depg = h->dalloc<float>(SN);
-        d.tape_dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
+        d.tape_dst = h->tapes[0].dst;
         d.gu = h->dalloc<double>(SL); d.gk = h->dalloc<double>(SL);
         d.dB = h->dalloc<double>(SL);
-        h->tape_dstg_buf = h->dalloc<float>((size_t)(h->W + 1) * SL * maxl);
+        h->tape_dstg_buf = h->tapes[0].dstg;
         h->gm_buf = h->dalloc<double>(SL);
         d.tape_dstg = nullptr; d.gm = nullptr;
         h->gQ_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
@@ -1041,6 +1107,7 @@ int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_d
 int sim_reset(sim_t *h)
 {
     return guarded(h, [&] {
+        h->placed.clear();
         build_queues(h, nullptr);
         upload_queues(h);
         zero_state(h);
@@ -1053,7 +1120,8 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
     return guarded(h, [&] {
         if (h->t != 0) fail(SIM_ESTATE, "sim_place is only allowed at t = 0");
         if (n < 0 || (n > 0 && (!agent || !link || !pos))) fail(SIM_EINVAL, "bad placement arrays");
-        std::vector<uint8_t> placed(h->N, 0);
+        std::vector<uint8_t> placed = h->placed;
+        if (placed.empty()) placed.assign(h->N, 0);
         std::vector<int32_t> cnt(h->L, 0), lk(n > 0 ? n : 1);
         for (int k = 0; k < n; ++k) {
             if (agent[k] < 0 || agent[k] >= h->N || placed[agent[k]]) fail(SIM_EINVAL, "bad or repeated agent");
@@ -1067,6 +1135,8 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
         std::vector<float> rp(SR, 0.f);
         std::vector<int32_t> ra(SR, 0), rt(SL, 0), rh(SL, 0);
+        std::vector<int2> rx(SR);
+        HIPCHK(hipMemcpyAsync(rx.data(), h->d.ring_aux, SR * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(rh.data(), h->d.rhead, SL * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(rt.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(rp.data(), h->d.ring_pos, SR * 4, hipMemcpyDeviceToHost, h->stream));
@@ -1085,6 +1155,7 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
                 const size_t seg = (size_t)s * h->L + j;
                 const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (rt[seg] % h->cap[j]);
                 ra[slot] = agent[k];
+                rx[slot] = make_int2(h->agent_dest[agent[k]], h->agent_didx[agent[k]]);
                 rp[slot] = pos[k];
                 rt[seg] += 1;
                 const size_t ga = (size_t)s * h->N + agent[k];
@@ -1098,11 +1169,13 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         HIPCHK(hipMemcpyAsync(h->d.rtail, rt.data(), SL * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ring_pos, rp.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ring_agent, ra.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.ring_aux, rx.data(), SR * 8, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.status, st.data(), SN, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.rel_t, relt.data(), SN * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.dep_t, dept.data(), SN * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ctr, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice, h->stream));
-        build_queues(h, &placed);
+        h->placed = placed;
+        build_queues(h, &h->placed);
         upload_queues(h);
         HIPCHK(hipStreamSynchronize(h->stream));
     });
@@ -1184,17 +1257,42 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         Ckpt &fin = h->ckpts.back();
         ckpt_copy(h, fin, true);
         const int nw = (T + h->ckpt_every - 1) / h->ckpt_every;
-        for (int w = nw - 1; w >= 0; --w) {
-            const int t0 = w * h->ckpt_every;
-            const int Ww = std::min(h->ckpt_every, T - t0);
+        // Window w is replayed from its checkpoint into tape set w % 2 on the replay stream, then
+        // swept in reverse on the main stream.  The replay of window w - 1 runs while window w is
+        // swept: it writes the live state and the other tape set, which the sweep does not read;
+        // it waits for the sweep of window w + 1, the last reader of that set.  Events order the two.
+        hipEvent_t *rp_done = h->bw_events.data(), *rv_done = h->bw_events.data() + nw;
+        hipEvent_t start = h->bw_events[2 * (size_t)nw];
+        HIPCHK(hipEventRecord(start, st));
+        HIPCHK(hipStreamWaitEvent(h->aux, start, 0));
+        auto use_tapes = [&](Dev &dv, int set) {
+            const auto &ts = h->tapes[set];
+            dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_head = ts.head; dv.tape_tail = ts.tail;
+            dv.tape_dst = ts.dst;
+            dv.tape_dstg = want_m ? ts.dstg : nullptr;
+        };
+        auto replay = [&](int w) {
+            const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
+            if (w + 2 <= nw - 1) HIPCHK(hipStreamWaitEvent(h->aux, rv_done[w + 2], 0));
+            const hipStream_t main_stream = h->stream;
+            h->stream = h->aux;
+            use_tapes(h->d, w & 1);
             hipEvent_t e = nullptr;
             h->time_begin(3, &e);
             ckpt_copy(h, h->ckpts[w], false);
             h->time_end(3, e);
             h->t = t0;
-            h->d.gQ = d.gQ; h->d.gT = d.gT; h->d.gx = d.gx;
             for (int k = 0; k < Ww; ++k) do_step(h, k);
-            sim::launch_tape_snapshot(d, Ww, st);
+            sim::launch_tape_snapshot(h->d, Ww, h->aux);
+            HIPCHK(hipEventRecord(rp_done[w], h->aux));
+            h->stream = main_stream;
+        };
+        replay(nw - 1);
+        for (int w = nw - 1; w >= 0; --w) {
+            const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
+            if (w >= 1) replay(w - 1);
+            HIPCHK(hipStreamWaitEvent(st, rp_done[w], 0));
+            use_tapes(d, w & 1);
             if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
             for (int k = Ww - 1; k >= 0; --k) {
                 hipEvent_t e2 = nullptr;
@@ -1202,8 +1300,10 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
                 sim::launch_reverse(d, t0 + k, k, 0, st);
                 h->time_end(2, e2);
             }
+            HIPCHK(hipEventRecord(rv_done[w], st));
             HIPCHK(hipGetLastError());
         }
+        use_tapes(h->d, 0);
         ckpt_copy(h, fin, false);
         h->t = T;
         h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
@@ -1283,6 +1383,110 @@ int sim_get_stats(sim_t *h, int64_t *vehicle_steps)
         sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(vehicle_steps, dv, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t version, S, L, N, O, D, nb, t, has_dB, has_placed, pad;
+    int64_t ring_total;
+};
+constexpr uint64_t kStateMagic = 0x31544154534d4953ull;   // "SIMSTAT1"
+
+// (device pointer, bytes) of every array of the mutable simulation state
+std::vector<std::pair<void *, size_t>> state_arrays(sim_t *h)
+{
+    Dev &d = h->d;
+    const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
+    const size_t SN = (size_t)h->S * h->N, nc = (size_t)h->S * h->D * std::max(h->nb, 1);
+    std::vector<std::pair<void *, size_t>> a = {
+        {d.ring_pos, SR * 4}, {d.ring_agent, SR * 4}, {d.ring_aux, SR * 8}, {d.rhead, SL * 4}, {d.rtail, SL * 4}, {d.B, SL * 8},
+        {d.E, SL * 8}, {d.Dacc, SO * 8}, {d.rel_ptr, SO * 4}, {d.dep_ptr, SO * 4},
+        {d.ctr, (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8}, {d.status, SN}, {d.tstar, SN * 8},
+        {d.rel_t, SN * 4}, {d.dep_t, SN * 4}, {d.exit_t, SN * 4}, {d.cum, nc * 4}};
+    if (d.dB) a.push_back({d.dB, SL * 8});
+    return a;
+}
+
+size_t state_bytes(sim_t *h)
+{
+    size_t n = sizeof(StateHeader) + (size_t)h->N;
+    for (auto &x : state_arrays(h)) n += x.second;
+    return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_get_full_state(sim_t *h, void *blob, size_t cap, size_t *n)
+{
+    return guarded(h, [&] {
+        const size_t need = state_bytes(h);
+        if (n) *n = need;
+        if (!blob) return;
+        if (cap < need) fail(SIM_EINVAL, "state buffer too small: need " + std::to_string(need) + " bytes");
+        StateHeader hd{kStateMagic, 1, h->S, h->L, h->N, h->O, h->D, h->nb, h->t, h->d.dB ? 1 : 0,
+                       h->placed.empty() ? 0 : 1, 0, h->ring_total};
+        char *p = static_cast<char *>(blob);
+        std::memcpy(p, &hd, sizeof hd);
+        p += sizeof hd;
+        for (auto &x : state_arrays(h)) {
+            HIPCHK(hipMemcpyAsync(p, x.first, x.second, hipMemcpyDeviceToHost, h->stream));
+            p += x.second;
+        }
+        if (h->placed.empty()) std::memset(p, 0, (size_t)h->N);
+        else std::memcpy(p, h->placed.data(), (size_t)h->N);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_set_full_state(sim_t *h, const void *blob, size_t n)
+{
+    return guarded(h, [&] {
+        if (!blob || n < sizeof(StateHeader)) fail(SIM_EINVAL, "state blob too small");
+        StateHeader hd;
+        std::memcpy(&hd, blob, sizeof hd);
+        if (hd.magic != kStateMagic || hd.version != 1) fail(SIM_EINVAL, "not a state blob of this library");
+        if (hd.S != h->S || hd.L != h->L || hd.N != h->N || hd.O != h->O || hd.D != h->D || hd.nb != h->nb ||
+            hd.ring_total != h->ring_total)
+            fail(SIM_EINVAL, "state blob of a different network, agent pool or configuration");
+        if (hd.t < 0) fail(SIM_EINVAL, "bad step counter in state blob");
+        // the blob's layout: header, the arrays (dB only when its source recorded), placed mask
+        size_t need = sizeof hd + (size_t)h->N;
+        auto arr = state_arrays(h);
+        const bool mine_dB = h->d.dB != nullptr;
+        for (size_t k = 0; k < arr.size(); ++k)
+            if (!(mine_dB && k + 1 == arr.size())) need += arr[k].second;
+        if (hd.has_dB) need += (size_t)h->S * h->L * 8;
+        if (n != need) fail(SIM_EINVAL, "state blob size does not match its header");
+        const char *p = static_cast<const char *>(blob) + sizeof hd;
+        const size_t base_n = mine_dB ? arr.size() - 1 : arr.size();
+        for (size_t k = 0; k < base_n; ++k) {
+            HIPCHK(hipMemcpyAsync(arr[k].first, p, arr[k].second, hipMemcpyHostToDevice, h->stream));
+            p += arr[k].second;
+        }
+        const size_t SL8 = (size_t)h->S * h->L * 8;
+        if (hd.has_dB) {
+            if (mine_dB) HIPCHK(hipMemcpyAsync(h->d.dB, p, SL8, hipMemcpyHostToDevice, h->stream));
+            p += SL8;
+        } else if (mine_dB) {
+            HIPCHK(hipMemsetAsync(h->d.dB, 0, SL8, h->stream));
+        }
+        const uint8_t *pl = reinterpret_cast<const uint8_t *>(p);
+        bool any = false;
+        for (int i = 0; i < h->N; ++i) any |= pl[i] != 0;
+        if (any) h->placed.assign(pl, pl + h->N);
+        else h->placed.clear();
+        build_queues(h, any ? &h->placed : nullptr);
+        upload_queues(h);
+        h->t = hd.t;
+        h->rec_valid = h->record && hd.t == 0;
         HIPCHK(hipStreamSynchronize(h->stream));
     });
 }
@@ -1381,11 +1585,8 @@ std::map<std::string, std::array<int, 3>> g_tune_mem;
 int node_group_need(const sim_t *h)
 {
     int need = 1;
-    for (int v = 0; v < h->Nn; ++v) {
-        need = std::max(need, (h->in_off[v + 1] - h->in_off[v]) * h->maxl + (h->org_off[v + 1] - h->org_off[v]));
-        need = std::max(need, h->out_off[v + 1] - h->out_off[v]);
-    }
-    return need;
+    for (int v = 0; v < h->Nn; ++v) need = std::max(need, (h->node_cnt[v] >> 24) + ((h->node_cnt[v] >> 16) & 0xff));
+    return std::max(need, h->max_out);
 }
 
 std::string shape_key(const sim_t *h)
@@ -1474,7 +1675,7 @@ int sim_autotune(sim_t *h, int32_t probe_steps, const char *cache_path, int32_t 
         std::array<int, 3> best = {h->g_link, h->g_node, h->g_rev};
         auto valid = [&](const std::array<int, 3> &v) {
             auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
-            return ok(v[0]) && ok(v[1]) && ok(v[2]);
+            return (ok(v[0]) || v[0] == 8) && (ok(v[1]) || v[1] == 8) && (ok(v[2]) || v[2] == 8);
         };
         std::array<int, 3> cached;
         if (!(flags & 1) && cache_lookup(path, key, cached) && valid(cached)) {
@@ -1510,7 +1711,7 @@ int sim_autotune(sim_t *h, int32_t probe_steps, const char *cache_path, int32_t 
             for (int dim = 0; dim < 2; ++dim) {
                 double bms = 1e300;
                 std::array<int, 3> bv = best;
-                for (int g : {16, 32, 64}) {
+                for (int g : {8, 16, 32, 64}) {
                     std::array<int, 3> v = best;
                     v[dim] = g;
                     if (!valid(v)) continue;
@@ -1532,12 +1733,10 @@ int sim_autotune(sim_t *h, int32_t probe_steps, const char *cache_path, int32_t 
                 sim::launch_tape_snapshot(d, Ww, st);
                 double bms = 1e300;
                 int bg = best[2];
-                for (int g : {16, 32, 64}) {
+                for (int g : {8, 16, 32, 64}) {
                     h->g_rev = h->d.g_rev = g;
                     build_classes(h);
                     d.g_rev = g;
-                    d.rv_small = h->d.rv_small; d.rv_big = h->d.rv_big;
-                    d.rv_n_small = h->d.rv_n_small; d.rv_n_big = h->d.rv_n_big;
                     for (int rep = 0; rep < 2; ++rep) {   // first sweep warms up
                         HIPCHK(hipMemsetAsync(d.adj_ring, 0, (size_t)h->S * h->ring_total * 4, st));
                         HIPCHK(hipEventRecord(ea, st));
@@ -1571,7 +1770,8 @@ int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev)
 {
     return guarded(h, [&] {
         auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
-        if (!ok(g_link) || !ok(g_node) || !ok(g_rev)) fail(SIM_EINVAL, "group sizes must be 16, 32 or 64");
+        if (!(ok(g_link) || g_link == 8) || !(ok(g_node) || g_node == 8) || !(ok(g_rev) || g_rev == 8))
+            fail(SIM_EINVAL, "lanes per item must be 8, 16, 32 or 64");
         h->g_link = h->d.g_link = g_link;
         h->g_node = h->d.g_node = g_node;
         h->g_rev = h->d.g_rev = g_rev;

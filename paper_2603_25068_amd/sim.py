@@ -62,6 +62,9 @@ def lib():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch first, so that the library binds to the HIP runtime torch already loaded (one runtime per
+    # process: device memory and streams from torch are then valid in the library)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     sig = {
@@ -88,6 +91,8 @@ def lib():
         "sim_get_timing": ([vp, vp, vp, C.c_int, C.c_int], C.c_int),
         "sim_footprint": ([vp, vp, vp, vp], C.c_int),
         "sim_autotune": ([vp, i32, C.c_char_p, i32, vp, vp, vp], C.c_int),
+        "sim_get_full_state": ([vp, vp, C.c_size_t, vp], C.c_int),
+        "sim_set_full_state": ([vp, vp, C.c_size_t], C.c_int),
         "srv_create": ([C.c_int, C.c_size_t, i32, i32, vp], C.c_int),
         "srv_submit": ([vp, vp, vp, vp, i32, vp], C.c_int),
         "srv_poll": ([vp, i64, vp], C.c_int),
@@ -110,7 +115,8 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_segsort",
-            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune",
+            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
+            "sim_set_full_state",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
             "srv_stats", "srv_destroy"]
 
@@ -355,6 +361,17 @@ class Simulator:
         a, b, c = C.c_int(0), C.c_int(0), C.c_int(0)
         self._chk(self._L.sim_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
+
+    def full_state(self) -> bytes:
+        """The whole simulation state as an opaque blob (sim_get_full_state)."""
+        n = C.c_size_t()
+        self._chk(self._L.sim_get_full_state(self._h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._chk(self._L.sim_get_full_state(self._h, buf, n.value, C.byref(n)))
+        return buf.raw
+
+    def set_full_state(self, blob: bytes):
+        self._chk(self._L.sim_set_full_state(self._h, blob, len(blob)))
 
     def autotune(self, probe_steps: int = 20, cache_path: Optional[str] = None, force: bool = False):
         """Pick and apply the fastest lane-group schedule for this shape from the

@@ -207,7 +207,7 @@ def test_errors_are_reported():
     assert e.value.code == SIM_ESTATE
 
 
-@pytest.mark.parametrize("sched", [(16, 64, 16), (32, 64, 32), (64, 64, 64), (16, 32, 64)])
+@pytest.mark.parametrize("sched", [(16, 64, 16), (32, 64, 32), (64, 64, 64), (16, 32, 64), (8, 16, 8)])
 def test_schedules_give_identical_results(sched):
     w = W.random_small(12, nx=5, ny=5, n_agents=800, rates=True, steps=300, lanes_max=3)
     ref = _sim(w, record=True, ckpt_every=50).rollout()
@@ -313,3 +313,42 @@ def test_autotune_restores_state_and_caches(tmp_path):
     s2.step(20)
     assert tuple(s2.autotune(probe_steps=12, cache_path=str(path))) == tuple(sched)
     assert len(path.read_text().splitlines()) == 1
+
+
+def test_full_state_round_trip():
+    """A run saved half-way and restored into a fresh handle continues
+    exactly as the original; a blob of another network is rejected."""
+    from paper_2603_25068_amd.sim import SimError, SIM_EINVAL
+    w = W.random_small(15, nx=4, ny=4, n_agents=600, rates=True, steps=300)
+    a = _sim(w)
+    a.step(120)
+    blob = a.full_state()
+    b = _sim(w, record=True)
+    b.set_full_state(blob)
+    assert b.t == 120
+    a.step(180)
+    b.step(180)
+    sa, sb = a.state(), b.state()
+    for k in ("status", "link", "pos", "seq", "counters"):
+        assert np.array_equal(sa[k], sb[k]), k
+    la, lb = a.link_state(), b.link_state()
+    for k in la:
+        assert np.array_equal(la[k], lb[k]), k
+    ca, ta = a.observables()
+    cb, tb = b.observables()
+    assert np.array_equal(ca, cb) and np.array_equal(ta, tb)
+    with pytest.raises(SimError) as e:
+        b.backward(gT=[1.0])
+    other = _sim(W.random_small(16, nx=4, ny=5, n_agents=600, rates=True, steps=300))
+    with pytest.raises(SimError) as e:
+        other.set_full_state(blob)
+    assert e.value.code == SIM_EINVAL
+    # placed agents travel with the blob
+    t = W.tg_toy(2.0, 1.0)
+    p = _sim(t, max_steps=10)
+    p.place([0], [0], [3.0])
+    q = _sim(t, max_steps=10)
+    q.set_full_state(p.full_state())
+    p.step(6)
+    q.step(6)
+    assert np.array_equal(p.state()["pos"], q.state()["pos"])
