@@ -104,8 +104,12 @@ struct sim_t {
         float *pos = nullptr, *dstg = nullptr;
         int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *dst = nullptr;
     };
-    TapeSet tapes[2];
-    hipStream_t aux = nullptr;               // replay stream of the backward pass
+    std::vector<TapeSet> tapes;              // n_replay + 1 sets
+    // concurrent replays of the backward pass: each has its own copy of the mutable state and
+    // its own stream, so windows are replayed side by side while the main stream sweeps
+    int n_replay = 3;
+    std::vector<Dev> rp_dev;
+    std::vector<hipStream_t> rp_stream;
     std::vector<hipEvent_t> bw_events;       // replay-done and reverse-done events per window
     float *tape_dstg_buf = nullptr;   // admission-graft tape, attached only for cap_mult gradients
     double *gm_buf = nullptr;
@@ -174,7 +178,7 @@ struct sim_t {
         if (stream) (void)hipStreamSynchronize(stream);
         for (auto &e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (auto e : ev_pool) (void)hipEventDestroy(e);
-        if (aux) { (void)hipStreamSynchronize(aux); (void)hipStreamDestroy(aux); }
+        for (auto x : rp_stream) { (void)hipStreamSynchronize(x); (void)hipStreamDestroy(x); }
         for (auto e : bw_events) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
@@ -185,16 +189,16 @@ struct sim_t {
         HIPCHK(hipEventCreate(&e));
         return e;
     }
-    void time_begin(int kind, hipEvent_t *a) {
+    void time_begin(int kind, hipEvent_t *a, hipStream_t on = nullptr) {
         (void)kind;
         if (!timing) return;
         *a = get_event();
-        HIPCHK(hipEventRecord(*a, stream));
+        HIPCHK(hipEventRecord(*a, on ? on : stream));
     }
-    void time_end(int kind, hipEvent_t a) {
+    void time_end(int kind, hipEvent_t a, hipStream_t on = nullptr) {
         if (!timing) return;
         hipEvent_t b = get_event();
-        HIPCHK(hipEventRecord(b, stream));
+        HIPCHK(hipEventRecord(b, on ? on : stream));
         evs.push_back({a, b, kind});
     }
     void resolve_timing() {
@@ -510,11 +514,11 @@ void ckpt_alloc(sim_t *h, Ckpt &c)
     c.status = h->dalloc<uint8_t>((size_t)h->S * h->N);
 }
 
-void ckpt_copy(sim_t *h, Ckpt &c, bool save)
+void ckpt_copy(sim_t *h, Ckpt &c, bool save, Dev *target = nullptr, hipStream_t on = nullptr)
 {
-    Dev &d = h->d;
+    Dev &d = target ? *target : h->d;
     const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
-    const hipStream_t st = h->stream;
+    const hipStream_t st = on ? on : h->stream;
     auto cp = [&](void *ck, void *live, size_t bytes) {
         if (save) HIPCHK(hipMemcpyAsync(ck, live, bytes, hipMemcpyDeviceToDevice, st));
         else HIPCHK(hipMemcpyAsync(live, ck, bytes, hipMemcpyDeviceToDevice, st));
@@ -534,20 +538,36 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save)
     cp(c.status, d.status, (size_t)h->S * h->N);
 }
 
-void do_step(sim_t *h, int tape_k)
+// the mutable state arrays of `src`, put into `dst` (parameters, tables, tape stay dst's)
+void with_state(Dev &dst, const Dev &src)
 {
-    const int t = h->t;
+    dst.ring_pos = src.ring_pos; dst.ring_agent = src.ring_agent; dst.ring_aux = src.ring_aux;
+    dst.rhead = src.rhead; dst.rtail = src.rtail; dst.B = src.B; dst.dB = src.dB; dst.E = src.E;
+    dst.slots = src.slots; dst.nheads = src.nheads; dst.head_rec = src.head_rec;
+    dst.status = src.status; dst.tstar = src.tstar; dst.rel_t = src.rel_t; dst.dep_t = src.dep_t;
+    dst.exit_t = src.exit_t; dst.Dacc = src.Dacc; dst.rel_ptr = src.rel_ptr; dst.dep_ptr = src.dep_ptr;
+    dst.ctr = src.ctr; dst.cum = src.cum;
+}
+
+// one step of state set `dv` at step t on stream `on`
+void step_on(sim_t *h, const Dev &dv, hipStream_t on, int t, int tape_k)
+{
     int sb = -1;
     if (h->cbs > 0 && (t + 1) % h->cbs == 0 && (t + 1) / h->cbs <= h->nb) sb = (t + 1) / h->cbs - 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    h->time_begin(0, &e0);
-    sim::launch_link(h->d, t, sb, tape_k, h->stream);
-    h->time_end(0, e0);
-    h->time_begin(1, &e1);
-    sim::launch_node(h->d, t, tape_k, h->stream);
-    h->time_end(1, e1);
+    h->time_begin(0, &e0, on);
+    sim::launch_link(dv, t, sb, tape_k, on);
+    h->time_end(0, e0, on);
+    h->time_begin(1, &e1, on);
+    sim::launch_node(dv, t, tape_k, on);
+    h->time_end(1, e1, on);
     HIPCHK(hipGetLastError());
-    h->t = t + 1;
+}
+
+void do_step(sim_t *h, int tape_k)
+{
+    step_on(h, h->d, h->stream, h->t, tape_k);
+    h->t += 1;
 }
 
 int record_error(sim_t *h, int code, const std::string &msg)
@@ -768,7 +788,9 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
         h->W = h->ckpt_every;
         bytes += (size_t)n_ck * (SR * 16 + SL * 32 + SO * 16 + SN);
-        bytes += 2 * (size_t)(h->W + 1) * (SR * 8 + SL * 8 + SL * maxl * 8) + SR * 4 + SN * 4 + SL * 24;
+        bytes += (size_t)(h->n_replay + 1) * (h->W + 1) * (SR * 8 + SL * 8 + SL * maxl * 8) + SR * 4 + SN * 4 + SL * 24;
+        bytes += (size_t)h->n_replay * (SR * 16 + SL * (48 + maxl * 16) + SN * 21 + SO * 16 +
+                                        (size_t)h->S * h->D * std::max(h->nb, 1) * 4);
     }
     h->footprint = bytes;
     h->n_ck = n_ck;
@@ -851,6 +873,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     if (h->record) {
         h->ckpts.resize(n_ck + 1);
         for (auto &c : h->ckpts) ckpt_alloc(h, c);
+        h->tapes.resize((size_t)h->n_replay + 1);
         for (auto &ts : h->tapes) {
             ts.pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
             ts.agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
@@ -861,7 +884,21 @@ void allocate_device(sim_t *h, const sim_config *cfg)
         }
         d.tape_pos = h->tapes[0].pos; d.tape_agent = h->tapes[0].agent;
         d.tape_head = h->tapes[0].head; d.tape_tail = h->tapes[0].tail;
-        HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+        h->rp_dev.assign((size_t)h->n_replay, d);
+        h->rp_stream.assign((size_t)h->n_replay, nullptr);
+        for (int k = 0; k < h->n_replay; ++k) {
+            Dev &r = h->rp_dev[k];   // mutable state of replay slot k (errors go to the shared flags)
+            r.ring_pos = h->dalloc<float>(SR); r.ring_agent = h->dalloc<int32_t>(SR); r.ring_aux = h->dalloc<int2>(SR);
+            r.rhead = h->dalloc<int32_t>(SL); r.rtail = h->dalloc<int32_t>(SL);
+            r.B = h->dalloc<double>(SL); r.dB = h->dalloc<double>(SL); r.E = h->dalloc<int64_t>(SL);
+            r.slots = h->dalloc<int32_t>(SL); r.nheads = h->dalloc<int32_t>(SL); r.head_rec = h->dalloc<int4>(SL * maxl);
+            r.status = h->dalloc<uint8_t>(SN); r.tstar = h->dalloc<double>(SN);
+            r.rel_t = h->dalloc<int32_t>(SN); r.dep_t = h->dalloc<int32_t>(SN); r.exit_t = h->dalloc<int32_t>(SN);
+            r.Dacc = h->dalloc<double>(SO); r.rel_ptr = h->dalloc<int32_t>(SO); r.dep_ptr = h->dalloc<int32_t>(SO);
+            r.ctr = h->dalloc<int64_t>((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
+            r.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
+            HIPCHK(hipStreamCreateWithFlags(&h->rp_stream[k], hipStreamNonBlocking));
+        }
         h->bw_events.resize(2 * (size_t)n_ck + 2, nullptr);
         for (auto &e : h->bw_events) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         d.adj_ring = h->dalloc<float>(SR); d.depg = h->dalloc<float>(SN);
@@ -1254,17 +1291,15 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         HIPCHK(hipMemsetAsync(d.gk, 0, SL * 8, st));
         if (want_m) HIPCHK(hipMemsetAsync(d.gm, 0, SL * 8, st));
         const int T = h->t;
-        Ckpt &fin = h->ckpts.back();
-        ckpt_copy(h, fin, true);
         const int nw = (T + h->ckpt_every - 1) / h->ckpt_every;
-        // Window w is replayed from its checkpoint into tape set w % 2 on the replay stream, then
-        // swept in reverse on the main stream.  The replay of window w - 1 runs while window w is
-        // swept: it writes the live state and the other tape set, which the sweep does not read;
-        // it waits for the sweep of window w + 1, the last reader of that set.  Events order the two.
+        const int K = h->n_replay, NT = K + 1;
+        // Window w is replayed from its checkpoint by slot w % K (its own copy of the mutable state,
+        // on its own stream) into tape set w % (K + 1), then swept in reverse on the main stream.
+        // Up to K replays run at once beside the sweep; the live state is never touched.  A replay
+        // waits for the sweep that last read its tape set; a sweep waits for its window's replay.
         hipEvent_t *rp_done = h->bw_events.data(), *rv_done = h->bw_events.data() + nw;
         hipEvent_t start = h->bw_events[2 * (size_t)nw];
         HIPCHK(hipEventRecord(start, st));
-        HIPCHK(hipStreamWaitEvent(h->aux, start, 0));
         auto use_tapes = [&](Dev &dv, int set) {
             const auto &ts = h->tapes[set];
             dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_head = ts.head; dv.tape_tail = ts.tail;
@@ -1273,26 +1308,26 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         };
         auto replay = [&](int w) {
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
-            if (w + 2 <= nw - 1) HIPCHK(hipStreamWaitEvent(h->aux, rv_done[w + 2], 0));
-            const hipStream_t main_stream = h->stream;
-            h->stream = h->aux;
-            use_tapes(h->d, w & 1);
+            const int slot = w % K;
+            const hipStream_t rs = h->rp_stream[slot];
+            if (w >= nw - K) HIPCHK(hipStreamWaitEvent(rs, start, 0));   // first use of the slot in this call
+            if (w + NT <= nw - 1) HIPCHK(hipStreamWaitEvent(rs, rv_done[w + NT], 0));
+            Dev r = h->d;
+            with_state(r, h->rp_dev[slot]);
+            use_tapes(r, w % NT);
             hipEvent_t e = nullptr;
-            h->time_begin(3, &e);
-            ckpt_copy(h, h->ckpts[w], false);
-            h->time_end(3, e);
-            h->t = t0;
-            for (int k = 0; k < Ww; ++k) do_step(h, k);
-            sim::launch_tape_snapshot(h->d, Ww, h->aux);
-            HIPCHK(hipEventRecord(rp_done[w], h->aux));
-            h->stream = main_stream;
+            h->time_begin(3, &e, rs);
+            ckpt_copy(h, h->ckpts[w], false, &r, rs);
+            h->time_end(3, e, rs);
+            for (int k = 0; k < Ww; ++k) step_on(h, r, rs, t0 + k, k);
+            sim::launch_tape_snapshot(r, Ww, rs);
+            HIPCHK(hipEventRecord(rp_done[w], rs));
         };
-        replay(nw - 1);
+        for (int w = nw - 1; w >= std::max(0, nw - K); --w) replay(w);
         for (int w = nw - 1; w >= 0; --w) {
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
-            if (w >= 1) replay(w - 1);
             HIPCHK(hipStreamWaitEvent(st, rp_done[w], 0));
-            use_tapes(d, w & 1);
+            use_tapes(d, w % NT);
             if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
             for (int k = Ww - 1; k >= 0; --k) {
                 hipEvent_t e2 = nullptr;
@@ -1301,11 +1336,10 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
                 h->time_end(2, e2);
             }
             HIPCHK(hipEventRecord(rv_done[w], st));
+            if (w - K >= 0) replay(w - K);
             HIPCHK(hipGetLastError());
         }
-        use_tapes(h->d, 0);
-        ckpt_copy(h, fin, false);
-        h->t = T;
+        // the main stream has waited for every replay (each sweep waits for its own)
         h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
         h->d.tape_dstg = nullptr; h->d.gm = nullptr;
         const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
