@@ -45,7 +45,8 @@ struct Dev {
     const int32_t *det_off, *det_list;
     const float *det_pos;
     const double *tff;      // route-choice free-flow time per link
-    const double *dist;     // [n_dest x Nn] shortest free-flow time to destination
+    const double *route;    // per node and destination, per out-link m: t_ff(m) + shortest time from head(m)
+    const int64_t *route_base;  // [Nn] first entry of the node's block (n_dest x out-degree)
     const int32_t *agent_didx, *agent_dest, *agent_origin;
     const int32_t *q_off, *q_list;   // origin queues (agent ids in release order)
     const int32_t *q_dest, *q_didx;  // destination node / table row of each queue entry

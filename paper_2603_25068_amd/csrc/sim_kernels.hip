@@ -360,6 +360,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const int gl = g.gl;
     const int maxl = d.maxl;
     const int cnt = d.node_cnt[v];
+    const int64_t rbase_v = d.route_base[v];
     const int deg = cnt & 0xff, dego = (cnt >> 8) & 0xff, norg = (cnt >> 16) & 0xff;
     const int ncin = (cnt >> 24) & 0xff;   // head lanes of the in-links (sum of their lane counts)
     const int nc = ncin + norg;
@@ -378,11 +379,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const int off_res = d.in_loff[(int64_t)v * d.max_in + min(gl, d.max_in - 1)];   // first head lane of in-link gl
     // ---- out-link lanes ----
     int om = -1, ohead = -1, oslots = 0, otail = 0, obase = 0, ocap = 1;
-    double outil = 0.0, otff = 0.0;
+    double outil = 0.0;
     if (gl < dego) {
         om = om_raw;
         ohead = d.head[om];
-        otff = d.tff[om];
         outil = d.util[sL + om];
         oslots = d.slots[sL + om];
         otail = d.rtail[sL + om];
@@ -475,7 +475,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     // ---- route choice (group-uniform loop over out-link blocks of 4) ----
     const bool exiting = ag >= 0 && from >= 0 && dst == v;
     const bool chooser = ag >= 0 && !exiting;
-    const double *dist = d.dist + (int64_t)didx * d.Nn;
+    const double *route = d.route + rbase_v + (int64_t)didx * dego;   // this head's row
     // one pass per out-link block of 4: shortest times, Philox words, scores V + g
     auto choice_pass = [&](bool on, bool exact, double &best, double &second, int &arg, int &argk) {
         best = -INFINITY;
@@ -484,17 +484,16 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         argk = 0;
         for (int b0 = 0; b0 < dego; b0 += 4) {
             int hk[4], mk[4];
-            double tk[4], uk[4], dm[4];
+            double uk[4], rt[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int src = min(b0 + q, G - 1);
                 hk[q] = __shfl(ohead, src, G);
                 mk[q] = __shfl(om, src, G);
-                tk[q] = __shfl(otff, src, G);
                 uk[q] = __shfl(outil, src, G);
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dm[q] = (on && b0 + q < dego) ? dist[hk[q]] : INFINITY;
+            for (int q = 0; q < 4; ++q) rt[q] = (on && b0 + q < dego) ? route[b0 + q] : INFINITY;
             if (on) {
                 uint32_t w[4];
                 draw4(seed, ag, t, 0, b0 >> 2, w);
@@ -502,8 +501,8 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
                 for (int q = 0; q < 4; ++q) {
                     if (b0 + q >= dego) continue;
                     if (!d.allow_uturn && from >= 0 && hk[q] == ftail) continue;
-                    if (!(dm[q] < INFINITY)) continue;
-                    const double V = uk[q] - d.theta * (tk[q] + dm[q]);
+                    if (!(rt[q] < INFINITY)) continue;
+                    const double V = uk[q] - d.theta * rt[q];
                     const double gq = exact ? gumbel_of(w[q]) : (double)gumbel_fast(w[q]);
                     const double sc = V + gq;
                     if (sc > best) { second = best; best = sc; arg = mk[q]; argk = b0 + q; }

@@ -87,6 +87,8 @@ struct sim_t {
     int32_t *linv_dev = nullptr;
     std::vector<int32_t> dest_nodes, agent_didx;
     std::vector<double> dist, tff;
+    std::vector<double> route;        // [node][destination][out-link] t_ff(m) + shortest time from head(m)
+    std::vector<int64_t> route_base;  // per node: first entry of its block (n_dest * out_off)
     std::vector<int32_t> q_off, q_list;  // full queues (as built at create)
     std::vector<int32_t> q_dest, q_didx;
     std::vector<int64_t> q_rstep;
@@ -776,13 +778,31 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     }
     h->tff.resize(L);
     for (int m = 0; m < L; ++m) h->tff[m] = (double)h->length[m] / (double)h->free_speed[m];
+    // route table: the free-flow time of every (node, destination, out-link) choice, one contiguous
+    // row per (node, destination), so a head's route choice reads one row instead of one shortest-
+    // time entry per out-link; each entry is the same double sum the choice would form
+    {
+        const size_t nd = h->dest_nodes.size();
+        h->route.assign(nd * (size_t)L, std::numeric_limits<double>::infinity());
+        h->route_base.resize(Nn);
+        for (int v = 0; v < Nn; ++v) {
+            const int64_t base = (int64_t)nd * h->out_off[v];
+            const int dg = h->out_off[v + 1] - h->out_off[v];
+            h->route_base[v] = base;
+            for (size_t dd = 0; dd < nd; ++dd)
+                for (int k = 0; k < dg; ++k) {
+                    const int m = h->out_lnk[h->out_off[v] + k];
+                    h->route[base + dd * dg + k] = h->tff[m] + h->dist[dd * Nn + h->head[m]];
+                }
+        }
+    }
     build_queues(h, nullptr);
 
     // ---------------- memory budget ----------------
     const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
     const size_t SR = (size_t)h->S * h->ring_total;
     size_t bytes = SR * 16 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
-                   h->dist.size() * 8 + (size_t)h->S * h->D * h->nb * 8;
+                   h->route.size() * 8 + (size_t)Nn * 8 + (size_t)h->S * h->D * h->nb * 8;
     int n_ck = 0;
     if (h->record) {
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
@@ -824,7 +844,8 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.org_off = h->upload(h->org_off); d.org_list = h->upload(h->org_list);
     d.det_off = h->upload(h->det_off); d.det_list = h->upload(h->det_list);
     d.det_pos = h->upload(h->det_pos);
-    d.tff = h->upload(h->tff); d.dist = h->upload(h->dist);
+    d.tff = h->upload(h->tff);
+    d.route = h->upload(h->route); d.route_base = h->upload(h->route_base);
     d.agent_didx = h->upload(h->agent_didx); d.agent_dest = h->upload(h->agent_dest);
     d.agent_origin = h->upload(h->agent_origin);
     h->q_off_dev = h->upload(h->q_off);
