@@ -231,7 +231,7 @@ def main():
     ap.add_argument("--workload", default="metro", choices=["metro", "grid", "small"])
     ap.add_argument("--sim-steps", type=int, default=None, help="override simulated steps per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=900)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     ap.add_argument("--serve-requests", type=int, default=32, help="requests in the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
@@ -240,7 +240,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--profile-pass", action="store_true", help="one forward+adjoint pass only")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--schedule", default="", help="with --profile-pass: g_link,g_node,g_rev")
+    ap.add_argument("--schedule", default="", help="g_link,g_node,g_rev instead of the autotuner's choice")
+    ap.add_argument("--fwd-adj-only", action="store_true",
+                    help="skip the forward-only timing (profiled runs: every pass then has the same kernel mix)")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="with --profile-pass: time a plain copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -280,9 +282,15 @@ def main():
 
     for _ in range(args.warmup):
         fwd_adj(sim)
-        fwd_only(fwd)
+        if not args.fwd_adj_only:
+            fwd_only(fwd)
     schedule = None
-    if not args.no_autotune:
+    if args.schedule:
+        gs = [int(x) for x in args.schedule.split(",")]
+        sim.set_schedule(*gs)
+        fwd.set_schedule(*gs)
+        schedule = {"fwd+adj": list(gs), "fwd": list(gs)}
+    elif not args.no_autotune:
         # tune on the loaded end-of-rollout state (restored afterwards; results do not change)
         schedule = {"fwd+adj": sim.autotune(probe_steps=30), "fwd": fwd.autotune(probe_steps=30)}
     torch.cuda.synchronize()
@@ -293,18 +301,20 @@ def main():
     el = time.perf_counter() - t0
     vs = int(sim.vehicle_steps()[0])
     st = sim.state()["counters"][0]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        fwd_only(fwd)
-    torch.cuda.synchronize()
-    el_f = time.perf_counter() - t1
-    vs_f = int(fwd.vehicle_steps()[0])
-    assert vs_f == vs
+    el_f, vs_f = None, None
+    if not args.fwd_adj_only:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            fwd_only(fwd)
+        torch.cuda.synchronize()
+        el_f = time.perf_counter() - t1
+        vs_f = int(fwd.vehicle_steps()[0])
+        assert vs_f == vs
 
     ms_per_step = 1000.0 * el / args.steps
     value = vs * args.steps / el
-    fwd_value = vs_f * args.steps / el_f
+    fwd_value = vs_f * args.steps / el_f if el_f else None
 
     # per-kernel device time with HIP events on the library's stream (one extra pass)
     sim.set_timing(True)
@@ -325,6 +335,13 @@ def main():
                 "kernel_ms": {k: [round(v[0], 3), v[1]] for k, v in tm.items()}}
 
     roofline["traffic"] = measured_traffic(f"k_{dom}", w.name)
+    # whole-pass figure with the per-unit model of the hot path: 92 B per agent-step on the network
+    # for forward + adjoint (28 B forward, 40 B replay with its tape, 24 B reverse), 68 B per head
+    # that moves and 48 B per link or origin and step in each forward sweep (forward and replay)
+    pass_bytes = 92.0 * vs + 2 * (68.0 * moves + 48.0 * (L + O) * T)
+    roofline["pass"] = {"model": "92 B/agent-step + 2 x (68 B/move + 48 B/(link|origin)-step)",
+                        "bytes": int(pass_bytes), "achieved": round(pass_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+                        "frac": round(pass_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)}
 
     serving = None
     if args.serve_requests > 0:
@@ -342,8 +359,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "agents": w.dem.n_agents, "links": L, "nodes": Nn, "origins": O,
                    "sim_steps": T, "ckpt_every": w.cfg.ckpt_every, "pass": "forward+adjoint",
-                   "vehicle_steps_per_pass": vs, "forward_only_vehicle_steps_per_s": round(fwd_value, 1),
-                   "forward_only_ms": round(1000.0 * el_f / args.steps, 3),
+                   "vehicle_steps_per_pass": vs,
+                   "forward_only_vehicle_steps_per_s": round(fwd_value, 1) if fwd_value else None,
+                   "forward_only_ms": round(1000.0 * el_f / args.steps, 3) if el_f else None,
                    "counters": st, "generate_s": round(gen_s, 2),
                    "schedule_g_link_g_node_g_rev": schedule},
         "roofline": roofline,

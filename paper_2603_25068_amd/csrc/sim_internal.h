@@ -99,6 +99,7 @@ struct Dev {
     const float *gQ;                 // [S*D*nb] dL/dcounts (device copy)
     const double *gT;                // [S]
     const float *gx;                 // [S*N]
+    unsigned long long *kstamp;      // kernel timing: this launch's record, (start, end) per wave; or null
 };
 
 }  // namespace sim
@@ -126,6 +127,11 @@ void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st);
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st);
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st);
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st);
+int link_blocks(const Dev &d);
+int node_blocks(const Dev &d);
+int reverse_blocks(const Dev &d);
+void launch_stamp_reduce(const int64_t *off, const int32_t *waves, int n, const unsigned long long *st,
+                         unsigned long long *out, hipStream_t s);
 void launch_rate_grad(const Dev &d, float *g_rates, hipStream_t st);
 void launch_philox(int n, const uint32_t *ctr, const uint32_t *key, uint32_t *out, hipStream_t st);
 int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,

@@ -309,9 +309,26 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     if (gl < h) d.head_rec[(int64_t)seg * d.maxl + gl] = make_int4(hag, hdst, hdidx, 0);
 }
 
+// Kernel timing (only when d.kstamp is set): every wave stores its start and end, read from the
+// real-time counter, into its own pair of the launch's record (plain stores, no contention);
+// k_stamp_reduce later folds a record into the first start and the last end, the kernel's
+// execution interval without the dispatch gaps around it.
+__device__ __forceinline__ unsigned long long stamp_begin(const Dev &d)
+{
+    return d.kstamp ? wall_clock64() : 0ull;
+}
+__device__ __forceinline__ void stamp_end(const Dev &d, unsigned long long t0)
+{
+    if (d.kstamp && (threadIdx.x & 63) == 0) {
+        const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+        d.kstamp[2 * w] = t0;
+        d.kstamp[2 * w + 1] = wall_clock64();
+    }
+}
+
 // blocks [0, small_blocks): G lanes per small segment; the rest: one wavefront per big segment
 template <int G>
-__global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int tape_k)
+__device__ __forceinline__ void link_launch(Dev &d, int t, int sample_b, int tape_k)
 {
     __shared__ float lds[4 * kBigLds];
     constexpr int per = 256 / G;
@@ -334,6 +351,14 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
         const int seg = s * d.L + d.lk_n_small + (item - s * d.lk_n_big);
         link_segment<64>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / 64) * kBigLds, kBigLds);
     }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int tape_k)
+{
+    const unsigned long long t0 = stamp_begin(d);
+    link_launch<G>(d, t, sample_b, tape_k);
+    stamp_end(d, t0);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,7 +714,7 @@ __host__ __device__ __forceinline__ int node_role_blocks(int n, int G, bool last
     return last ? b : ((b + 7) & ~7);   // inner roles in multiples of 8 keep the XCD pattern
 }
 
-__global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
+__device__ __forceinline__ void node_launch(Dev &d, int t, int tape_k)
 {
     int b = (int)blockIdx.x;
     const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
@@ -702,6 +727,13 @@ __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
     if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k); return; }
     b -= b32;
     node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k);
+}
+
+__global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
+{
+    const unsigned long long t0 = stamp_begin(d);
+    node_launch(d, t, tape_k);
+    stamp_end(d, t0);
 }
 
 // Tape entry without an update (the state at the end of a replay window).
@@ -881,7 +913,7 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
 }
 
 template <int G>
-__global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int init)
+__device__ __forceinline__ void reverse_launch(Dev &d, int t, int tape_k, int init)
 {
     __shared__ float lds[4 * kRevBigLds];
     constexpr int per = 256 / G;
@@ -904,6 +936,14 @@ __global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int i
         const int seg = s * d.L + d.rv_n_small + (item - s * d.rv_n_big);
         reverse_segment<64>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / 64) * kRevBigLds, kRevBigLds);
     }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int init)
+{
+    const unsigned long long t0 = stamp_begin(d);
+    reverse_launch<G>(d, t, tape_k, init);
+    stamp_end(d, t0);
 }
 
 // dL/d rates[s, o, b] = sum over departed agents of origin o of
@@ -1143,20 +1183,65 @@ static inline int class_blocks(int S, int n_small, int n_big, int G)
     return ((((S * n_small + per - 1) / per) + 7) & ~7) + (S * n_big + 3) / 4;
 }
 
+// one wavefront per launch record (offset, waves): first start and last end over its waves
+__global__ __launch_bounds__(256) void k_stamp_reduce(const int64_t *off, const int32_t *waves, int n,
+                                                      const unsigned long long *st, unsigned long long *out)
+{
+    const int r = (int)blockIdx.x * kWavesPerBlock + ((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+    if (r >= n) return;
+    const unsigned long long *p = st + 2 * off[r];
+    unsigned long long lo = ~0ull, hi = 0ull;
+    for (int w = lane; w < waves[r]; w += 64) {
+        lo = min(lo, p[2 * w]);
+        hi = max(hi, p[2 * w + 1]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (unsigned long long)__shfl_xor(lo, o));
+        hi = max(hi, (unsigned long long)__shfl_xor(hi, o));
+    }
+    if (lane == 0) { out[2 * r] = lo; out[2 * r + 1] = hi; }
+}
+void launch_stamp_reduce(const int64_t *off, const int32_t *waves, int n, const unsigned long long *st,
+                         unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stamp_reduce, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, s, off, waves,
+                       n, st, out);
+}
+
+int link_blocks(const Dev &d)
+{
+    return class_blocks(d.S, d.lk_n_small, d.lk_n_big, d.g_link);
+}
+int node_blocks(const Dev &d)
+{
+    return std::max(1, node_role_blocks(d.S * d.nd_n[0], 8, false) + node_role_blocks(d.S * d.nd_n[1], 16, false) +
+                       node_role_blocks(d.S * d.nd_n[2], 32, false) + node_role_blocks(d.S * d.nd_n[3], 64, true));
+}
+int reverse_blocks(const Dev &d)
+{
+    return class_blocks(d.S, d.rv_n_small, d.rv_n_big, d.g_rev);
+}
+
+template <typename K, typename... A>
+static void launch(K kernel, int blocks, hipStream_t st, A... args)
+{
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, st, args...);
+}
+
 void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 {
     switch (d.g_link) {
-    case 8: hipLaunchKernelGGL(k_link<8>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 8)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
-    case 16: hipLaunchKernelGGL(k_link<16>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 16)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
-    case 32: hipLaunchKernelGGL(k_link<32>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 32)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
-    default: hipLaunchKernelGGL(k_link<64>, dim3(class_blocks(d.S, d.lk_n_small, d.lk_n_big, 64)), dim3(256), 0, st, d, t, sample_b, tape_k); break;
+    case 8: launch(k_link<8>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 8), st, d, t, sample_b, tape_k); break;
+    case 16: launch(k_link<16>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 16), st, d, t, sample_b, tape_k); break;
+    case 32: launch(k_link<32>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 32), st, d, t, sample_b, tape_k); break;
+    default: launch(k_link<64>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 64), st, d, t, sample_b, tape_k); break;
     }
 }
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
 {
     const int blocks = node_role_blocks(d.S * d.nd_n[0], 8, false) + node_role_blocks(d.S * d.nd_n[1], 16, false) +
                        node_role_blocks(d.S * d.nd_n[2], 32, false) + node_role_blocks(d.S * d.nd_n[3], 64, true);
-    hipLaunchKernelGGL(k_node, dim3(std::max(blocks, 1)), dim3(256), 0, st, d, t, tape_k);
+    launch(k_node, std::max(blocks, 1), st, d, t, tape_k);
 }
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 {
@@ -1165,10 +1250,10 @@ void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st)
 {
     switch (d.g_rev) {
-    case 8: hipLaunchKernelGGL(k_reverse<8>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 8)), dim3(256), 0, st, d, t, tape_k, init); break;
-    case 16: hipLaunchKernelGGL(k_reverse<16>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 16)), dim3(256), 0, st, d, t, tape_k, init); break;
-    case 32: hipLaunchKernelGGL(k_reverse<32>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 32)), dim3(256), 0, st, d, t, tape_k, init); break;
-    default: hipLaunchKernelGGL(k_reverse<64>, dim3(class_blocks(d.S, d.rv_n_small, d.rv_n_big, 64)), dim3(256), 0, st, d, t, tape_k, init); break;
+    case 8: launch(k_reverse<8>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 8), st, d, t, tape_k, init); break;
+    case 16: launch(k_reverse<16>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 16), st, d, t, tape_k, init); break;
+    case 32: launch(k_reverse<32>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 32), st, d, t, tape_k, init); break;
+    default: launch(k_reverse<64>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 64), st, d, t, tape_k, init); break;
     }
 }
 void launch_rate_grad(const Dev &d, float *g, hipStream_t st)

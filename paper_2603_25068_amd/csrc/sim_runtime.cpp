@@ -203,10 +203,68 @@ struct sim_t {
         HIPCHK(hipEventRecord(b, on ? on : stream));
         evs.push_back({a, b, kind});
     }
+    // kernels time themselves: each launch gets a record of (start, end) per wave in a buffer
+    // allocated on the first timed launch; records are folded at resolve time
+    static constexpr int64_t kStampEntries = (int64_t)192 << 20;   // u64 entries (1.5 GB)
+    unsigned long long *stamps = nullptr, *stamp_out = nullptr;
+    int64_t *stamp_off_dev = nullptr;
+    int32_t *stamp_waves_dev = nullptr;
+    static constexpr int kStampRecords = 16384;
+    std::vector<int> stamp_kind;
+    std::vector<int64_t> stamp_off;
+    std::vector<int32_t> stamp_waves;
+    int64_t stamp_used = 0;
+    double wall_khz = 100000.0;
+    // the launch's Dev, with a timing record when timing is on (kind: 0 link, 1 node, 2 reverse)
+    Dev stamped(const Dev &dv, int kind, int blocks) {
+        Dev r = dv;
+        r.kstamp = nullptr;
+        if (!timing) return r;
+        if (!stamps) {
+            stamps = dalloc<unsigned long long>((size_t)kStampEntries);
+            stamp_out = dalloc<unsigned long long>(2 * (size_t)kStampRecords);
+            stamp_off_dev = dalloc<int64_t>(kStampRecords);
+            stamp_waves_dev = dalloc<int32_t>(kStampRecords);
+            int khz = 0;
+            if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+                wall_khz = khz;
+        }
+        const int64_t waves = (int64_t)blocks * sim::kWavesPerBlock;
+        if ((int)stamp_kind.size() == kStampRecords || stamp_used + 2 * waves > kStampEntries) return r;
+        r.kstamp = stamps + stamp_used;
+        stamp_kind.push_back(kind);
+        stamp_off.push_back(stamp_used / 2);
+        stamp_waves.push_back((int32_t)waves);
+        stamp_used += 2 * waves;
+        return r;
+    }
+    void sync_all() {
+        HIPCHK(hipStreamSynchronize(stream));
+        for (auto x : rp_stream) HIPCHK(hipStreamSynchronize(x));
+    }
     void resolve_timing() {
+        if (!stamp_kind.empty()) {
+            sync_all();
+            const int n = (int)stamp_kind.size();
+            HIPCHK(hipMemcpy(stamp_off_dev, stamp_off.data(), (size_t)n * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(stamp_waves_dev, stamp_waves.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+            sim::launch_stamp_reduce(stamp_off_dev, stamp_waves_dev, n, stamps, stamp_out, stream);
+            std::vector<unsigned long long> v(2 * (size_t)n);
+            HIPCHK(hipMemcpyAsync(v.data(), stamp_out, v.size() * 8, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            for (int k = 0; k < n; ++k) {
+                if (v[2 * k + 1] < v[2 * k]) continue;
+                ms_acc[stamp_kind[k]] += (double)(v[2 * k + 1] - v[2 * k]) / wall_khz;
+                n_acc[stamp_kind[k]] += 1;
+            }
+            stamp_kind.clear();
+            stamp_off.clear();
+            stamp_waves.clear();
+            stamp_used = 0;
+        }
         if (evs.empty()) return;
-        HIPCHK(hipEventSynchronize(evs.back().b));
-        for (auto &e : evs) {
+        for (auto &e : evs) {   // events may sit on several streams
+            HIPCHK(hipEventSynchronize(e.b));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
             ms_acc[e.kind] += ms;
@@ -556,13 +614,8 @@ void step_on(sim_t *h, const Dev &dv, hipStream_t on, int t, int tape_k)
 {
     int sb = -1;
     if (h->cbs > 0 && (t + 1) % h->cbs == 0 && (t + 1) / h->cbs <= h->nb) sb = (t + 1) / h->cbs - 1;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    h->time_begin(0, &e0, on);
-    sim::launch_link(dv, t, sb, tape_k, on);
-    h->time_end(0, e0, on);
-    h->time_begin(1, &e1, on);
-    sim::launch_node(dv, t, tape_k, on);
-    h->time_end(1, e1, on);
+    sim::launch_link(h->stamped(dv, 0, sim::link_blocks(dv)), t, sb, tape_k, on);
+    sim::launch_node(h->stamped(dv, 1, sim::node_blocks(dv)), t, tape_k, on);
     HIPCHK(hipGetLastError());
 }
 
@@ -1350,12 +1403,8 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             HIPCHK(hipStreamWaitEvent(st, rp_done[w], 0));
             use_tapes(d, w % NT);
             if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
-            for (int k = Ww - 1; k >= 0; --k) {
-                hipEvent_t e2 = nullptr;
-                h->time_begin(2, &e2);
-                sim::launch_reverse(d, t0 + k, k, 0, st);
-                h->time_end(2, e2);
-            }
+            for (int k = Ww - 1; k >= 0; --k)
+                sim::launch_reverse(h->stamped(d, 2, sim::reverse_blocks(d)), t0 + k, k, 0, st);
             HIPCHK(hipEventRecord(rv_done[w], st));
             if (w - K >= 0) replay(w - K);
             HIPCHK(hipGetLastError());
