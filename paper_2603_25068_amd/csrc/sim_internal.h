@@ -139,7 +139,7 @@ int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing,
                    hipStream_t st);
-void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, hipStream_t st);
+void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st);
 void launch_counts(const Dev &d, float *out, hipStream_t st);
 void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st);
 void launch_gather_links(const double *src, const int32_t *linv, float *dst, int S, int L, hipStream_t st);

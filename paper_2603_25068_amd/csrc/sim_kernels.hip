@@ -960,19 +960,31 @@ __global__ __launch_bounds__(256) void k_rate_grad(Dev d, float *g)
     const int qb = d.q_off[o], qn = d.q_off[o + 1] - qb;
     const int64_t sN = (int64_t)s * d.N;
     const float *rates = d.rates + ((int64_t)s * d.O + o) * nbins;
+    // lanes take the queue's agents 64 at a time; per bin, a fixed-order wave sum (deterministic)
+    double accb = 0.0;   // lane b < nbins (in its round of 64 bins) holds bin b's total
     for (int b0 = 0; b0 < nbins; b0 += kWave) {
-        const int b = b0 + lane;
-        double acc = 0.0;
-        const double lo = b * d.rate_bin_s, hi = (b + 1) * d.rate_bin_s;
-        for (int k = 0; k < qn; ++k) {
-            const int a = d.q_list[qb + k];
-            if (d.dep_t[sN + a] < 0) continue;
-            const double ts = d.tstar[sN + a];
-            const int rb = min(nbins - 1, max(0, (int)floor((double)d.rel_t[sN + a] * d.dt / d.rate_bin_s)));
-            const double ov = fmin(hi, ts) - lo;
-            if (b < nbins && ov > 0) acc += (double)d.depg[sN + a] * ov / (double)rates[rb];
+        accb = 0.0;
+        for (int k0 = 0; k0 < qn; k0 += kWave) {
+            const int k = k0 + lane;
+            double dg = 0.0, rt = 1.0, ts = 0.0;
+            if (k < qn) {
+                const int a = d.q_list[qb + k];
+                if (d.dep_t[sN + a] >= 0) {
+                    ts = d.tstar[sN + a];
+                    const int rb = min(nbins - 1, max(0, (int)floor((double)d.rel_t[sN + a] * d.dt / d.rate_bin_s)));
+                    dg = (double)d.depg[sN + a];
+                    rt = (double)rates[rb];
+                }
+            }
+            for (int bb = 0; bb < kWave && b0 + bb < nbins; ++bb) {
+                const int b = b0 + bb;
+                const double ov = fmin((b + 1) * d.rate_bin_s, ts) - b * d.rate_bin_s;
+                double c = (dg != 0.0 && ov > 0) ? dg * ov / rt : 0.0;
+                for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+                if (lane == bb) accb += c;
+            }
         }
-        if (b < nbins) g[((int64_t)s * d.O + o) * nbins + b] = (float)acc;
+        if (b0 + lane < nbins) g[((int64_t)s * d.O + o) * nbins + b0 + lane] = (float)accb;
     }
 }
 
@@ -994,29 +1006,43 @@ __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, co
 // or on the network after each step, and sum over departed agents of
 // ((exit step or T) - departure step), the agent-steps on the network.  One
 // workgroup per scenario, fixed reduction order.
-__global__ __launch_bounds__(256) void k_ttt(Dev d, int T, double *out, int64_t *vsteps)
+// Total travel time and vehicle-steps: integer sums over agents of (exit or T) - release and
+// (exit or T) - departure, exact in int64 whatever the order; each block adds its sum with one
+// atomic, and k_ttt_final scales by dt.
+__global__ __launch_bounds__(256) void k_ttt(Dev d, int T, unsigned long long *acc)
 {
-    __shared__ double part[256];
-    __shared__ long long vpart[256];
-    const int s = blockIdx.x;
+    const int s = blockIdx.y;
     const int64_t sN = (int64_t)s * d.N;
-    double acc = 0.0;
-    long long vs = 0;
-    for (int i = threadIdx.x; i < d.N; i += 256) {
+    long long tt = 0, vs = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < d.N; i += gridDim.x * 256) {
         const uint8_t st = d.status[sN + i];
         if (st == AG_WAIT) continue;
         const int e = (st == AG_EXITED) ? d.exit_t[sN + i] : T;
-        acc += (double)(e - d.rel_t[sN + i]);
+        tt += e - d.rel_t[sN + i];
         if (st != AG_QUEUED) vs += e - (d.dep_t[sN + i] >= 0 ? d.dep_t[sN + i] : 0);  // placed agents: from t = 0
     }
-    part[threadIdx.x] = acc;
-    vpart[threadIdx.x] = vs;
+    for (int o = 32; o > 0; o >>= 1) { tt += __shfl_xor(tt, o); vs += __shfl_xor(vs, o); }
+    __shared__ long long p[2][kWavesPerBlock];
+    if ((threadIdx.x & 63) == 0) { p[0][threadIdx.x >> 6] = tt; p[1][threadIdx.x >> 6] = vs; }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) { part[threadIdx.x] += part[threadIdx.x + o]; vpart[threadIdx.x] += vpart[threadIdx.x + o]; }
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        long long a = 0, b = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) { a += p[0][w]; b += p[1][w]; }
+        atomicAdd(&acc[2 * s], (unsigned long long)a);
+        atomicAdd(&acc[2 * s + 1], (unsigned long long)b);
     }
-    if (threadIdx.x == 0) { out[s] = part[0] * d.dt; if (vsteps) vsteps[s] = vpart[0]; }
+}
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+__global__ void k_ttt_final(int S, double dt, const unsigned long long *acc, double *out, int64_t *vsteps)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    out[s] = (double)(long long)acc[2 * s] * dt;
+    if (vsteps) vsteps[s] = (int64_t)(long long)acc[2 * s + 1];
 }
 
 // Interval counts from cumulative samples.
@@ -1267,9 +1293,13 @@ void launch_derive(const Dev &d, const float *cap_mult, const float *capacity, c
     hipLaunchKernelGGL(k_derive, dim3((int)((n + 255) / 256)), dim3(256), 0, st, d, cap_mult, capacity, beta, cost,
                        util, acc, vfree, spacing);
 }
-void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, hipStream_t st)
+void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ttt, dim3(d.S), dim3(256), 0, st, d, T, out, vsteps);
+    // acc: 2 x S zeroed here with a fill kernel (no memset node, so the sequence can sit in a graph)
+    hipLaunchKernelGGL(k_zero_u64, dim3((2 * d.S + 255) / 256), dim3(256), 0, st, acc, 2 * d.S);
+    const int nb = std::max(1, std::min(1024, (d.N + 2047) / 2048));
+    hipLaunchKernelGGL(k_ttt, dim3(nb, d.S), dim3(256), 0, st, d, T, acc);
+    hipLaunchKernelGGL(k_ttt_final, dim3((d.S + 255) / 256), dim3(256), 0, st, d.S, d.dt, acc, out, vsteps);
 }
 void launch_counts(const Dev &d, float *out, hipStream_t st)
 {

@@ -133,6 +133,7 @@ struct sim_t {
     // adjoint buffers
     float *gQ_dev = nullptr, *gx_dev = nullptr;
     double *gT_dev = nullptr, *ttt_dev = nullptr;
+    unsigned long long *ttt_acc = nullptr;   // [2 x S] integer sums behind the travel time
     float *counts_dev = nullptr, *grad_tmp = nullptr;
     int64_t *vsteps_dev = nullptr;
     int64_t *dalloc_scratch_i64(size_t n) {
@@ -943,6 +944,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
     d.err = h->dalloc<int32_t>(sim::ERR_N);
     h->ttt_dev = h->dalloc<double>(h->S);
+    h->ttt_acc = h->dalloc<unsigned long long>(2 * (size_t)h->S);
     h->counts_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
     if (h->record) {
         h->ckpts.resize(n_ck + 1);
@@ -1073,7 +1075,7 @@ int results_enqueue(sim_t *h, float *counts, double *ttt, int64_t *vsteps, std::
             HIPCHK(hipMemcpyAsync(counts, h->counts_dev, (size_t)h->S * h->D * h->nb * 4, hipMemcpyDeviceToHost, h->stream));
         }
         int64_t *dv = h->dalloc_scratch_i64(h->S);
-        sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->stream);
+        sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->ttt_acc, h->stream);
         if (ttt) HIPCHK(hipMemcpyAsync(ttt, h->ttt_dev, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
         if (vsteps) HIPCHK(hipMemcpyAsync(vsteps, dv, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipGetLastError());
@@ -1328,7 +1330,7 @@ int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device)
             copy_out(h, counts, h->counts_dev, (size_t)h->S * h->D * h->nb * 4, on_device);
         }
         if (ttt) {
-            sim::launch_ttt(h->d, h->t, h->ttt_dev, nullptr, h->stream);
+            sim::launch_ttt(h->d, h->t, h->ttt_dev, nullptr, h->ttt_acc, h->stream);
             copy_out(h, ttt, h->ttt_dev, (size_t)h->S * 8, on_device);
         }
         HIPCHK(hipGetLastError());
@@ -1484,7 +1486,7 @@ int sim_get_stats(sim_t *h, int64_t *vehicle_steps)
     return guarded(h, [&] {
         if (!vehicle_steps) fail(SIM_EINVAL, "null output");
         int64_t *dv = h->dalloc_scratch_i64(h->S);
-        sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->stream);
+        sim::launch_ttt(h->d, h->t, h->ttt_dev, dv, h->ttt_acc, h->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(vehicle_steps, dv, (size_t)h->S * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
