@@ -194,6 +194,47 @@ def serving_leg(n_requests: int, rate: float, steps: int, max_slots: int, budget
     }
 
 
+def control_leg(repeats: int = 2):
+    """Batched control: 16 candidate scenarios of capacity multipliers on the 32x32 lattice, 3,600
+    steps, one launch per step for all scenarios, then the adjoint of each scenario's total travel
+    time in its multipliers.  Reports vehicle-steps/s of that forward+adjoint pass over all scenarios
+    and the same for one scenario alone (scenario 0) for comparison."""
+    import numpy as np
+    import torch
+    from paper_2603_25068_amd import workloads as W
+    from paper_2603_25068_amd.sim import Simulator
+    w = W.batched_control()
+    S, T = int(w.extra["n_scenarios"]), w.cfg.steps
+    m = w.extra["cap_mult"]
+    dev = torch.device("cuda", 0)
+    out = {}
+    for label, n_s, mult in (("batched", S, m), ("single", 1, m[:1])):
+        sim = Simulator(w, n_scenarios=n_s, record=True, max_steps=T, params={"cap_mult": mult})
+        gT = torch.ones(n_s, dtype=torch.float64, device=dev)
+
+        def one():
+            sim.reset()
+            sim.step(T)
+            return sim.backward_device(gT=gT, groups=("cap_mult",))
+
+        one()
+        sim.autotune(probe_steps=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            g = one()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / repeats
+        vs = int(sim.vehicle_steps().sum())
+        out[label] = {"scenarios": n_s, "ms_per_pass": round(1000.0 * el, 2),
+                      "vehicle_steps_per_s": round(vs / el, 1),
+                      "grad_norm": float(torch.linalg.vector_norm(g["cap_mult"].double()).item())}
+        sim.close()
+    out["workload"] = (f"{w.name}: {S} scenarios x {w.dem.n_agents} agents, {w.net.n_links} links, {T} steps, "
+                       f"TTT gradient in {len(w.extra['controlled_links'])} controlled capacity multipliers")
+    return out
+
+
 def profile_pass(args):
     """One forward+adjoint pass of the workload and nothing else (for counter
     runs), or a plain device copy of known size (the counters' calibration)."""
@@ -240,6 +281,7 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--profile-pass", action="store_true", help="one forward+adjoint pass only")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-control", action="store_true", help="skip the batched-control leg")
     ap.add_argument("--schedule", default="", help="g_link,g_node,g_rev instead of the autotuner's choice")
     ap.add_argument("--fwd-adj-only", action="store_true",
                     help="skip the forward-only timing (profiled runs: every pass then has the same kernel mix)")
@@ -343,6 +385,10 @@ def main():
                         "bytes": int(pass_bytes), "achieved": round(pass_bytes / (ms_per_step * 1e-3) / 1e9, 2),
                         "frac": round(pass_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)}
 
+    control = None
+    if not args.no_control:
+        control = control_leg()
+
     serving = None
     if args.serve_requests > 0:
         serving = serving_leg(args.serve_requests, args.serve_rate, args.serve_steps, args.serve_slots,
@@ -367,6 +413,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "batched_control": control,
     }
     print(json.dumps(line), flush=True)
 

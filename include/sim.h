@@ -223,16 +223,22 @@ int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, con
 
 /* Launch schedule: lanes per work item of the link-phase and reverse
  * kernels for rings of at most 128 slots (8, 16, 32 or 64; larger rings run
- * on a whole wavefront), and the floor of the node-phase lane group (16, 32
- * or 64: each node runs on the smallest group, not below the floor, that
+ * on a whole wavefront), and the floor of the node-phase lane group (8, 16,
+ * 32 or 64: each node runs on the smallest group, not below the floor, that
  * holds its merge candidates and out-links).  Results do not depend on it. */
 int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev);
 int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
 
 /* Device time (ms) and launch count of each kernel kind accumulated since
- * the last call with reset = 1, measured with HIP events on the handle's
- * stream when timing is enabled (sim_set_timing). kinds: 0 link phase,
- * 1 node phase, 2 reverse, 3 tape/checkpoint copies. */
+ * the last call with reset = 1, while timing is enabled (sim_set_timing).
+ * Kinds 0 link phase, 1 node phase, 2 reverse: each launch's execution
+ * interval, first wave start to last wave end, which the kernels record
+ * themselves; kind 3 tape/checkpoint copies: HIP events around the copy.
+ * While timing is enabled the backward pass runs its windows one after
+ * another instead of overlapping replays with the reverse sweep, so each
+ * kernel's time is its own.  Within one sim_rollout or sim_backward call at
+ * most 16384 launches are timed (their records take up to 1.5 GB of device
+ * memory, allocated on first use); later launches of the call run untimed. */
 int sim_set_timing(sim_t *h, int enable);
 int sim_get_timing(sim_t *h, double *ms, int64_t *launches, int n_kinds, int reset);
 

@@ -1368,7 +1368,9 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         if (want_m) HIPCHK(hipMemsetAsync(d.gm, 0, SL * 8, st));
         const int T = h->t;
         const int nw = (T + h->ckpt_every - 1) / h->ckpt_every;
-        const int K = h->n_replay, NT = K + 1;
+        // in timing mode the windows run one after another (one replay slot, each replay after the
+        // previous sweep), so that per-kernel times are not stretched by concurrent kernels
+        const int K = h->timing ? 1 : h->n_replay, NT = K + 1;
         // Window w is replayed from its checkpoint by slot w % K (its own copy of the mutable state,
         // on its own stream) into tape set w % (K + 1), then swept in reverse on the main stream.
         // Up to K replays run at once beside the sweep; the live state is never touched.  A replay
@@ -1388,6 +1390,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             const hipStream_t rs = h->rp_stream[slot];
             if (w >= nw - K) HIPCHK(hipStreamWaitEvent(rs, start, 0));   // first use of the slot in this call
             if (w + NT <= nw - 1) HIPCHK(hipStreamWaitEvent(rs, rv_done[w + NT], 0));
+            if (h->timing && w + 1 <= nw - 1) HIPCHK(hipStreamWaitEvent(rs, rv_done[w + 1], 0));
             Dev r = h->d;
             with_state(r, h->rp_dev[slot]);
             use_tapes(r, w % NT);
