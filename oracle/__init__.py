@@ -85,9 +85,9 @@ def _lib(variant: str):
     L.orc_get_origin_state.argtypes = [vp, vp, vp, vp]
     L.orc_time.argtypes = [vp]
     L.orc_time.restype = i32
-    L.orc_frozen_eval.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
+    L.orc_frozen_eval.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
     L.orc_frozen_eval.restype = C.c_int
-    L.orc_backward.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, C.c_int]
+    L.orc_backward.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
     L.orc_backward.restype = C.c_int
     L.orc_philox4x32_10.argtypes = [vp, vp, vp]
     L.orc_gumbel.argtypes = [C.c_uint64, i32, i32, i32, i32]
@@ -249,14 +249,18 @@ class Oracle:
         return out
 
     # -- frozen surrogate and adjoint -------------------------------------
-    def frozen(self, u=None, kappa=None, rates=None, cap_mult=None, record_base: bool = False):
+    def frozen(self, u=None, kappa=None, rates=None, cap_mult=None, beta=None, cost=None, alpha=None, theta=None,
+               record_base: bool = False):
         f64 = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
         u, kappa, rates, cap_mult = f64(u), f64(kappa), f64(rates), f64(cap_mult)
+        beta, cost, alpha = f64(beta), f64(cost), f64(alpha)
+        theta = None if theta is None else np.ascontiguousarray(np.reshape(theta, (1,)), np.float64)
         Dd = self.w.net.n_detectors
         cnt = np.zeros((Dd, self.n_count_bins), np.float64)
         ttt = C.c_double(0.0)
         pos = np.zeros(self.w.dem.n_agents, np.float64)
-        rc = self._L.orc_frozen_eval(self._h, _ptr(u), _ptr(kappa), _ptr(rates), _ptr(cap_mult), int(record_base),
+        rc = self._L.orc_frozen_eval(self._h, _ptr(u), _ptr(kappa), _ptr(rates), _ptr(cap_mult), _ptr(beta),
+                                     _ptr(cost), _ptr(alpha), _ptr(theta), int(record_base),
                                      _ptr(cnt), C.byref(ttt), _ptr(pos))
         if rc != 0:
             raise RuntimeError(f"frozen_eval failed ({rc}); run with log=True first")
@@ -271,9 +275,10 @@ class Oracle:
         nb = self.w.dem.n_rate_bins
         g_r = np.zeros((net.n_origins, max(nb, 1)))
         g_m = np.zeros(net.n_links)
+        g_b, g_c, g_a, g_t = np.zeros(net.n_links), np.zeros(net.n_links), np.zeros(net.n_links), np.zeros(1)
         rc = self._L.orc_backward(self._h, _ptr(gQ), float(gT), _ptr(gx), _ptr(g_u), _ptr(g_k), _ptr(g_r),
-                                   _ptr(g_m), 0 if transfer_graft else 1)
+                                   _ptr(g_m), _ptr(g_b), _ptr(g_c), _ptr(g_a), _ptr(g_t), 0 if transfer_graft else 1)
         if rc != 0:
             raise RuntimeError("backward needs a logged rollout")
         return {"free_speed": g_u, "jam_density": g_k, "rates": g_r[:, :nb] if nb else g_r[:, :0],
-                "cap_mult": g_m}
+                "cap_mult": g_m, "beta": g_b, "cost": g_c, "alpha": g_a, "theta": g_t}

@@ -142,7 +142,11 @@ typedef struct {
 typedef struct { int32_t agent, link, leader, branch, capped; double x0, x1; } cf_rec;
 typedef struct { int32_t agent, kind, from, to, tok_k; double tstar, bacc; int32_t rate_bin, qidx; int64_t cfi; int32_t rel_t; double dbacc; } mv_rec;
 typedef struct { int32_t det, agent; double x; } smp_rec;
-typedef struct { int32_t t, n_cf, n_mv, n_smp; int64_t cf0, mv0, smp0; int32_t sample_k; } step_rec;
+typedef struct { int32_t t, n_cf, n_mv, n_smp; int64_t cf0, mv0, smp0; int32_t sample_k; int64_t ch0, mg0; int32_t n_ch, n_mg; } step_rec;
+/* route choice of one head or origin front: its valid candidate links [c0, c0 + n) */
+typedef struct { int32_t agent, from, chosen, n; int64_t c0; double xh; } ch_rec;
+/* merge of one target link with free entry slots: candidates [c0, c0 + n) in key order, k winners */
+typedef struct { int32_t link, n, k; int64_t c0; } mg_rec;
 
 #define VEC(T) struct { T *p; int64_t n, cap; }
 #define VPUSH(v, val) do { if ((v).n == (v).cap) { (v).cap = (v).cap ? 2 * (v).cap : 1024; \
@@ -186,6 +190,17 @@ typedef struct orc {
     VEC(mv_rec) mv;
     VEC(smp_rec) smp;
     VEC(step_rec) steps;
+    /* straight-through log: choosers (candidate links, route term t_ff + D, Gumbel noise) and merge
+     * groups (chooser record, merge noise, moved flag of each candidate) */
+    VEC(ch_rec) chs;
+    VEC(int32_t) chl;
+    VEC(double) chr, chg;
+    VEC(mg_rec) mgs;
+    VEC(int32_t) mgc, mgmv;
+    VEC(double) mgg;
+    int64_t *chidx;     /* per agent: its chooser record this step */
+    double *base_pi;    /* per chooser record: pi at the chosen link (base) */
+    double *base_pim;   /* per merge group, stage and remaining candidate: pi' (base) */
     VEC(uint8_t) capf;  /* per logged step and link: 1 if the idle cap clipped the bucket */
     /* scratch */
     int32_t *bucket_off, *bucket, *rank, *leader_of, *branch, *capped, *choice, *won, *head_cnt, *slots, *cfidx;
@@ -413,6 +428,7 @@ orc_t *orc_create(const orc_inputs *in)
     o->cfidx = malloc(4 * (size_t)(N + 1));
     o->xhat = malloc(sizeof(pos_t) * (size_t)(N + 1));
     o->mkey = malloc(8 * (size_t)(N + 1)); o->bacc = malloc(8 * (size_t)(L + 1));
+    o->chidx = malloc(8 * (size_t)(N + 1));
     return o;
 }
 
@@ -427,6 +443,7 @@ void orc_destroy(orc_t *o)
         o->pos, o->tstar, o->tstar_bin, o->qidx, o->rel_t, o->B, o->dB, o->E, o->next_seq, o->cprev, o->counts,
         o->bucket_off, o->bucket, o->rank, o->leader_of, o->branch, o->capped, o->choice, o->won,
         o->head_cnt, o->slots, o->cfidx, o->xhat, o->mkey, o->bacc, o->cf.p, o->mv.p, o->smp.p, o->steps.p, o->capf.p,
+        o->chs.p, o->chl.p, o->chr.p, o->chg.p, o->mgs.p, o->mgc.p, o->mgmv.p, o->mgg.p, o->chidx, o->base_pi, o->base_pim,
         o->base_x1, o->base_xhat, o->base_psi, o->base_sig };
     for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
     free(o);
@@ -489,6 +506,7 @@ static int32_t choose(orc_t *o, int32_t a, int32_t v, int32_t from)
     const double *dist = o->dist + (int64_t)d * o->in.n_nodes;
     double best = -INFINITY, second = -INFINITY;
     int32_t arg = CH_STUCK;
+    ch_rec cr = { a, from, CH_STUCK, 0, o->chl.n, from >= 0 ? (double)o->xhat[a] : 0.0 };
     for (int32_t k = o->out_off[v]; k < o->out_off[v + 1]; ++k) {
         int32_t m = o->out_lnk[k], c = k - o->out_off[v];
         if (!o->in.allow_uturn && from >= 0 && o->head[m] == o->tail[from]) continue;
@@ -496,11 +514,14 @@ static int32_t choose(orc_t *o, int32_t a, int32_t v, int32_t from)
         if (!(dm < INFINITY)) continue;
         double tff = (double)o->length[m] / (double)o->rspeed[m];
         double V = (double)o->beta[m] / (double)o->cost[m] - o->in.dest_logit_coef * (tff + dm);
-        double s = V + orc_gumbel(o->in.seed, a, o->t, 0, c);
+        double g = orc_gumbel(o->in.seed, a, o->t, 0, c);
+        double s = V + g;
         if (s > best) { second = best; best = s; arg = m; }
         else if (s > second) second = s;
+        if (o->log_on) { VPUSH(o->chl, m); VPUSH(o->chr, tff + dm); VPUSH(o->chg, g); cr.n++; }
     }
     if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) o->ctr[5]++;
+    if (o->log_on) { cr.chosen = arg; o->chidx[a] = o->chs.n; VPUSH(o->chs, cr); }
     return arg;
 }
 
@@ -510,7 +531,7 @@ int orc_step(orc_t *o)
     int32_t L = in->n_links, N = in->n_agents, O = in->n_origins, Nn = in->n_nodes;
     int32_t t = o->t;
     double dt = in->dt;
-    step_rec sr = { t, 0, 0, 0, o->cf.n, o->mv.n, o->smp.n, 0 };
+    step_rec sr = { t, 0, 0, 0, o->cf.n, o->mv.n, o->smp.n, 0, o->chs.n, o->mgs.n, 0, 0 };
 
     /* ---- release ---- */
     for (int32_t k = 0; k < O; ++k) {
@@ -662,6 +683,15 @@ int orc_step(orc_t *o)
             for (int32_t c = 0; c + 1 < nc; ++c)
                 if (cand[c].key - cand[c + 1].key < 1e-12 * (1.0 + fabs(cand[c].key))) o->ctr[5]++;
             int32_t kwin = nc < o->slots[m] ? nc : o->slots[m];
+            if (o->log_on && kwin > 0) {
+                mg_rec g = { m, nc, kwin, o->mgc.n };
+                for (int32_t c = 0; c < nc; ++c) {
+                    VPUSH(o->mgc, (int32_t)o->chidx[cand[c].agent]);
+                    VPUSH(o->mgg, orc_gumbel(in->seed, cand[c].agent, t, 1, 0));
+                    VPUSH(o->mgmv, 0);
+                }
+                VPUSH(o->mgs, g);
+            }
             w_beg[m] = wn;
             for (int32_t c = 0; c < kwin; ++c) { o->won[cand[c].agent] = 1; winners[wn++] = cand[c].agent; }
             w_end[m] = wn;
@@ -688,6 +718,12 @@ int orc_step(orc_t *o)
         }
     }
     for (int32_t k = 0; k < O; ++k) if (front[k] >= 0 && o->choice[front[k]] >= 0 && o->won[front[k]]) passed[front[k]] = 1;
+    if (o->log_on)   /* which merge candidates of this step actually moved */
+        for (int64_t gi = sr.mg0; gi < o->mgs.n; ++gi)
+            for (int32_t c = 0; c < o->mgs.p[gi].n; ++c) {
+                int64_t q = o->mgs.p[gi].c0 + c;
+                o->mgmv.p[q] = passed[o->chs.p[o->mgc.p[q]].agent];
+            }
 
     /* ---- apply: stayers take the capped position, movers change link ---- */
     for (int32_t j = 0; j < L; ++j) {
@@ -772,6 +808,8 @@ int orc_step(orc_t *o)
         sr.n_cf = (int32_t)(o->cf.n - sr.cf0);
         sr.n_mv = (int32_t)(o->mv.n - sr.mv0);
         sr.n_smp = (int32_t)(o->smp.n - sr.smp0);
+        sr.n_ch = (int32_t)(o->chs.n - sr.ch0);
+        sr.n_mg = (int32_t)(o->mgs.n - sr.mg0);
         VPUSH(o->steps, sr);
     }
     free(front); free(cand); free(winners); free(w_beg); free(w_end);
@@ -847,8 +885,39 @@ int64_t orc_log_sizes(const orc_t *o, int64_t *out)
 /* ------------------------------------------------------------------------ */
 static double sigm(double z) { return 1.0 / (1.0 + exp(-z)); }
 
+/* Straight-through terms of the node model (SI-B).  Link choice: pi = softmax((V + g)/tau) over
+ * the chooser's valid candidate links, V = beta/c - theta (t_ff + D); the sample is
+ * onehot(pi) + pi - sg(pi).  Merge of a target link: V' = alpha_from * l (l the chooser's link-
+ * choice entry for the target), pi' = softmax((V' + g')/tau) over the candidates; with k winners,
+ * k stages, stage s over the candidates not picked before it (s = 0 alone is the paper's case).
+ * pi at the chosen link of chooser record r, with parameters (beta, cost, theta); all n in p. */
+static double choice_pi(const orc_t *o, int64_t r, const double *beta, const double *cost, double theta, double *p)
+{
+    const ch_rec *c = &o->chs.p[r];
+    double tau = o->in.gumbel_tau, mx = -INFINITY, sum = 0.0, at = 0.0;
+    for (int32_t k = 0; k < c->n; ++k) {
+        int32_t m = o->chl.p[c->c0 + k];
+        double y = (beta[m] / cost[m] - theta * o->chr.p[c->c0 + k] + o->chg.p[c->c0 + k]) / tau;
+        p[k] = y;
+        if (y > mx) mx = y;
+    }
+    for (int32_t k = 0; k < c->n; ++k) { p[k] = exp(p[k] - mx); sum += p[k]; }
+    for (int32_t k = 0; k < c->n; ++k) { p[k] /= sum; if (o->chl.p[c->c0 + k] == c->chosen) at = p[k]; }
+    return at;
+}
+
+/* softmax of y/tau over entries [s, n) (a merge stage) into q[s..n) */
+static void stage_softmax(const double *y, int32_t s, int32_t n, double tau, double *q)
+{
+    double mx = -INFINITY, sum = 0.0;
+    for (int32_t c = s; c < n; ++c) if (y[c] / tau > mx) mx = y[c] / tau;
+    for (int32_t c = s; c < n; ++c) { q[c] = exp(y[c] / tau - mx); sum += q[c]; }
+    for (int32_t c = s; c < n; ++c) q[c] /= sum;
+}
+
 int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const double *rates_in,
-                    const double *capm_in, int record_base, double *out_counts, double *out_ttt, double *out_pos)
+                    const double *capm_in, const double *beta_in, const double *cost_in, const double *alpha_in,
+                    const double *theta_in, int record_base, double *out_counts, double *out_ttt, double *out_pos)
 {
     const orc_inputs *in = &o->in;
     int32_t L = in->n_links, N = in->n_agents, O = in->n_origins, Bn = in->n_rate_bins;
@@ -870,6 +939,30 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
     }
     /* token buckets replayed with the logged consumption and idle-cap clips */
     double *Bf = calloc((size_t)L + 1, 8), *Bacc = calloc((size_t)L + 1, 8);
+    /* straight-through parameters and per-agent merge perturbation of this step */
+    double *bet = malloc(8 * (size_t)L), *cst = malloc(8 * (size_t)L), *alp = malloc(8 * (size_t)L);
+    for (int32_t j = 0; j < L; ++j) {
+        bet[j] = beta_in ? beta_in[j] : (double)o->beta[j];
+        cst[j] = cost_in ? cost_in[j] : (double)o->cost[j];
+        alp[j] = alpha_in ? alpha_in[j] : (double)o->alpha[j];
+    }
+    const double theta = theta_in ? *theta_in : in->dest_logit_coef, bigm = in->big_m, tau = in->gumbel_tau;
+    double *dA = calloc((size_t)N + 1, 8), *pw = malloc(8 * 256), *yv = NULL, *qv = NULL;
+    int64_t ycap = 0, pim_k = 0;
+    if (record_base) {
+        free(o->base_pi); free(o->base_pim);
+        int64_t npim = 0;
+        for (int64_t gi = 0; gi < o->mgs.n; ++gi)
+            for (int32_t st = 0; st < o->mgs.p[gi].k; ++st) npim += o->mgs.p[gi].n - st;
+        o->base_pi = malloc(8 * (size_t)(o->chs.n + 1));
+        o->base_pim = malloc(8 * (size_t)(npim + 1));
+        for (int64_t r = 0; r < o->chs.n; ++r) {
+            const ch_rec *c = &o->chs.p[r];
+            double *pp = malloc(8 * (size_t)(c->n + 1));
+            o->base_pi[r] = choice_pi(o, r, bet, cst, theta, pp);
+            free(pp);
+        }
+    }
     double *x = calloc((size_t)N, 8), *xn = calloc((size_t)N, 8);
     int32_t *on = calloc((size_t)N, 4);
     /* agents placed at t = 0 */
@@ -905,6 +998,35 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
             xn[r->agent] = xh;
         }
         for (int64_t c = s->cf0; c < s->cf0 + s->n_cf; ++c) x[o->cf.p[c].agent] = xn[o->cf.p[c].agent];
+        /* straight-through merge perturbations: da = sum over stages of pi' - sg(pi') */
+        for (int64_t gi = s->mg0; gi < s->mg0 + s->n_mg; ++gi) {
+            const mg_rec *g = &o->mgs.p[gi];
+            if (g->n > ycap) { ycap = 2 * g->n; yv = realloc(yv, 8 * (size_t)ycap); qv = realloc(qv, 8 * (size_t)ycap); }
+            for (int32_t c = 0; c < g->n; ++c) {
+                int64_t r = o->mgc.p[g->c0 + c];
+                const ch_rec *cr = &o->chs.p[r];
+                double *pp = cr->n <= 256 ? pw : malloc(8 * (size_t)cr->n);
+                double pi = choice_pi(o, r, bet, cst, theta, pp);
+                if (pp != pw) free(pp);
+                double l = 1.0 + pi - o->base_pi[r];
+                double al = cr->from >= 0 ? alp[cr->from] : 1.0;
+                yv[c] = al * l + o->mgg.p[g->c0 + c];
+                dA[cr->agent] = 0.0;
+            }
+            for (int32_t st = 0; st < g->k; ++st) {
+                stage_softmax(yv, st, g->n, tau, qv);
+                for (int32_t c = st; c < g->n; ++c) {
+                    if (record_base) o->base_pim[pim_k] = qv[c];
+                    dA[o->chs.p[o->mgc.p[g->c0 + c]].agent] += qv[c] - o->base_pim[pim_k];
+                    ++pim_k;
+                }
+            }
+            /* candidates that stayed on their link: X - (M + x) I_remove */
+            for (int32_t c = 0; c < g->n; ++c) {
+                const ch_rec *cr = &o->chs.p[o->mgc.p[g->c0 + c]];
+                if (!o->mgmv.p[g->c0 + c] && cr->from >= 0) x[cr->agent] -= (bigm + x[cr->agent]) * dA[cr->agent];
+            }
+        }
         for (int64_t c = s->mv0; c < s->mv0 + s->n_mv; ++c) {
             const mv_rec *m = &o->mv.p[c];
             if (m->kind == MV_TRANSFER) {
@@ -918,8 +1040,10 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
                 double psi = -(double)o->u[m->to] * ttok;
                 if (record_base) o->base_psi[c] = psi;
                 Bf[j] -= 1.0;
-                /* grafted entry: value 0, history of the capped position and of the token time */
-                x[m->agent] = 0.0 + (x[m->agent] - o->base_xhat[m->cfi]) + (psi - o->base_psi[c]);
+                /* grafted entry: value 0, history of the capped position and of the token time;
+                 * straight-through add: (M + x - sg x) (1 + da) at the new link */
+                double tg = x[m->agent] - o->base_xhat[m->cfi];
+                x[m->agent] = 0.0 + tg + (psi - o->base_psi[c]) + tg * dA[m->agent] + bigm * dA[m->agent];
             } else if (m->kind == MV_EXIT) {
                 /* exit earlier by (xhat - sg xhat)/u of the last link */
                 ttt_soft -= (x[m->agent] - o->base_xhat[m->cfi]) / (double)o->u[m->from];
@@ -945,7 +1069,7 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
                 }
                 double psi = -(double)o->u[m->to] * tst;
                 if (record_base) o->base_psi[c] = psi;
-                x[m->agent] = 0.0 + (psi - o->base_psi[c]);
+                x[m->agent] = 0.0 + (psi - o->base_psi[c]) + bigm * dA[m->agent];
                 on[m->agent] = 1;
             }
         }
@@ -974,6 +1098,7 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
     if (out_pos) for (int32_t i = 0; i < N; ++i) out_pos[i] = (o->status[i] == ST_ON) ? x[i] : 0.0;
     if (record_base) o->have_base = 1;
     free(u); free(kap); free(capm); free(Bf); free(Bacc); free(x); free(xn); free(on); free(cint); free(csoft);
+    free(bet); free(cst); free(alp); free(dA); free(pw); free(yv); free(qv);
     (void)O;
     return 0;
 }
@@ -983,16 +1108,21 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
 /* at the base parameters (the straight-through and grafting conventions    */
 /* of SI-A/SI-B/SI-C/SI-D).  Cotangents: dL/dcounts [det x bins], dL/dTTT,  */
 /* dL/d(final positions) [N].  Gradients (accumulated, caller zeroes):      */
-/* g_u[L], g_kappa[L], g_rates[O x B], g_capm[L].                          */
-/* flags bit 0: no transfer graft.                                          */
+/* g_u[L], g_kappa[L], g_rates[O x B], g_capm[L], and through the         */
+/* straight-through node model g_beta[L], g_cost[L], g_alpha[L], g_theta[1] */
+/* (each may be NULL).  flags bit 0: no transfer graft.                     */
 /* ------------------------------------------------------------------------ */
 int orc_backward(orc_t *o, const double *gQ, double gT, const double *gx,
-                 double *g_u, double *g_kappa, double *g_rates, double *g_capm, int flags)
+                 double *g_u, double *g_kappa, double *g_rates, double *g_capm,
+                 double *g_beta, double *g_cost, double *g_alpha, double *g_theta, int flags)
 {
     const orc_inputs *in = &o->in;
     int32_t N = in->n_agents, Bn = in->n_rate_bins, nb = in->n_count_bins;
     if (!o->log_on) return -1;
     double *adj = calloc((size_t)N, 8), *nadj = calloc((size_t)N, 8);
+    const int ste = g_beta || g_cost || g_alpha || g_theta;
+    double *bb = malloc(8 * (size_t)(in->n_links + 1)), *cc = malloc(8 * (size_t)(in->n_links + 1));
+    for (int32_t j = 0; j < in->n_links; ++j) { bb[j] = (double)o->beta[j]; cc[j] = (double)o->cost[j]; }
     if (gx) for (int32_t i = 0; i < N; ++i) if (o->status[i] == ST_ON) adj[i] = gx[i];
     for (int64_t si = o->steps.n - 1; si >= 0; --si) {
         const step_rec *s = &o->steps.p[si];
@@ -1006,6 +1136,48 @@ int orc_backward(orc_t *o, const double *gQ, double gT, const double *gx,
                 double sc = 5.0 / (double)o->length[j];
                 double sg = sigm(sc * (r->x - (double)o->det_pos[d]));
                 adj[r->agent] += gC * sc * sg * (1.0 - sg);
+            }
+        }
+        /* straight-through node model (SI-B), adjoints of the positions after the step:
+         * a merge candidate's share of the transfer update is G = M adj(new) if it moved, and
+         * -(M + x_hat) adj(stay) if it stayed on its link (an origin front that stayed has none) */
+        if (ste) {
+            const double bigm = in->big_m, tau = in->gumbel_tau, theta = in->dest_logit_coef;
+            for (int64_t gi = s->mg0; gi < s->mg0 + s->n_mg; ++gi) {
+                const mg_rec *g = &o->mgs.p[gi];
+                double *y = malloc(8 * (size_t)g->n), *G = malloc(8 * (size_t)g->n);
+                double *q = malloc(8 * (size_t)g->n), *dVp = calloc((size_t)g->n, 8);
+                for (int32_t c = 0; c < g->n; ++c) {
+                    const ch_rec *cr = &o->chs.p[o->mgc.p[g->c0 + c]];
+                    double al = cr->from >= 0 ? (double)o->alpha[cr->from] : 1.0;
+                    y[c] = al + o->mgg.p[g->c0 + c];
+                    if (o->mgmv.p[g->c0 + c]) G[c] = bigm * adj[cr->agent];
+                    else G[c] = cr->from >= 0 ? -(bigm + cr->xh) * adj[cr->agent] : 0.0;
+                }
+                for (int32_t st = 0; st < g->k; ++st) {
+                    stage_softmax(y, st, g->n, tau, q);
+                    double sg = 0.0;
+                    for (int32_t c = st; c < g->n; ++c) sg += q[c] * G[c];
+                    for (int32_t c = st; c < g->n; ++c) dVp[c] += q[c] / tau * (G[c] - sg);
+                }
+                for (int32_t c = 0; c < g->n; ++c) {
+                    int64_t r = o->mgc.p[g->c0 + c];
+                    const ch_rec *cr = &o->chs.p[r];
+                    double al = cr->from >= 0 ? (double)o->alpha[cr->from] : 1.0;
+                    if (g_alpha && cr->from >= 0) g_alpha[cr->from] += dVp[c];   /* dV'/d alpha = l = 1 */
+                    double gam = al * dVp[c];                                      /* dL/d l at the target */
+                    double *p = malloc(8 * (size_t)(cr->n + 1));
+                    double ps = choice_pi(o, r, bb, cc, theta, p);
+                    for (int32_t k = 0; k < cr->n; ++k) {
+                        int32_t m2 = o->chl.p[cr->c0 + k];
+                        double dV = gam / tau * ps * ((m2 == cr->chosen ? 1.0 : 0.0) - p[k]);
+                        if (g_beta) g_beta[m2] += dV / (double)o->cost[m2];
+                        if (g_cost) g_cost[m2] -= (double)o->beta[m2] / ((double)o->cost[m2] * (double)o->cost[m2]) * dV;
+                        if (g_theta) g_theta[0] -= o->chr.p[cr->c0 + k] * dV;
+                    }
+                    free(p);
+                }
+                free(y); free(G); free(q); free(dVp);
             }
         }
         /* moves */
@@ -1054,6 +1226,6 @@ int orc_backward(orc_t *o, const double *gQ, double gT, const double *gx,
         }
         for (int64_t c = s->cf0; c < s->cf0 + s->n_cf; ++c) adj[o->cf.p[c].agent] = nadj[o->cf.p[c].agent];
     }
-    free(adj); free(nadj);
+    free(adj); free(nadj); free(bb); free(cc);
     return 0;
 }

@@ -424,6 +424,22 @@ def tg_toy(u1: float = 2.0, u2: float = 1.0) -> Workload:
     return Workload("tg_toy", net, dem, cfg)
 
 
+def merge_toy(alpha=(1.0, 1.0), length: float = 100.0, speed: float = 10.0, seed: int = 0,
+              tau: float = 0.5) -> Workload:
+    """Two one-lane links 0->2 and 1->2 merging into 2->3; one agent placed at
+    the end of each in-link at t = 0, both bound for node 3, so in the first
+    step both heads want the single entry slot of 2->3 and the merge decides."""
+    net = Network(
+        n_nodes=4, tail=_i32([0, 1, 2]), head=_i32([2, 2, 3]), lanes=_i32([1, 1, 1]),
+        length=_f32([length] * 3), free_speed=_f32([speed] * 3),
+        jam_density=_f32([JAM_DENSITY_PER_LANE] * 3), capacity=_f32([10.0] * 3),
+        beta=_f32([0, 0, 0]), alpha=_f32(list(alpha) + [1.0]), cost=_f32([1, 1, 1]),
+        origin_node=_i32([0]), detector_link=_i32([2]), detector_pos=_f32([length / 2]))
+    dem = Demand(agent_origin=_i32([0, 0]), agent_dest=_i32([3, 3]), ready_time=_f32([1e9, 1e9]))
+    cfg = Config(dt=1.0, steps=1, count_bin_steps=1, ckpt_every=60, seed=seed, gumbel_tau=tau)
+    return Workload("merge_toy", net, dem, cfg)
+
+
 def diamond(n_agents: int = 200, lanes: int = 1, seed: int = 7, length: float = 100.0,
             horizon_s: float = 300.0, capacity: float = 0.5) -> Workload:
     """Four-node diamond A(0)->B(1)->D(3), A->C(2)->D with reverse links;

@@ -645,3 +645,67 @@ def test_dead_end_without_uturn_is_stuck():
     c = o.counters()
     assert c["stuck"] > 0
     assert o.state()["link"][0] == 1
+
+
+@pytest.mark.parametrize("seed", [4, 10])
+def test_straight_through_adjoint_matches_frozen_surrogate_fd(seed):
+    """Gradients in the route-choice utility (beta, cost, theta) and the merge
+    priority (alpha) reach the loss only through the straight-through
+    estimator of the node model (SI-B): the adjoint equals central differences
+    of the frozen surrogate in which every sample is onehot + p - sg(p)."""
+    w = W.random_small(seed, nx=3, ny=3, n_agents=250, rates=True, steps=200)
+    rng = np.random.default_rng(seed)
+    L = w.net.n_links
+    prm = {"beta": rng.uniform(0.5, 2.0, L).astype(np.float32), "cost": rng.uniform(1.0, 3.0, L).astype(np.float32),
+           "alpha": rng.uniform(0.5, 2.0, L).astype(np.float32)}
+    o = Oracle(w, variant="f64", log=True, params=prm)
+    o.run()
+    base = {"beta": prm["beta"].astype(np.float64), "cost": prm["cost"].astype(np.float64),
+            "alpha": prm["alpha"].astype(np.float64), "theta": np.array([w.cfg.dest_logit_coef], np.float64)}
+    c0, t0, x0 = o.frozen(**base, record_base=True)
+    cnt, ttt = o.counts()
+    np.testing.assert_allclose(c0, cnt, atol=1e-9)
+    assert t0 == pytest.approx(ttt, abs=1e-9)
+    gQ = rng.normal(size=c0.shape)
+    gT = 0.3
+    st = o.state()
+    gx = rng.normal(size=x0.shape) * (st["status"] == ST_ON)
+    g = o.backward(gQ=gQ, gT=gT, gx=gx)
+    for which in ("beta", "cost", "alpha", "theta"):
+        assert np.abs(g[which]).max() > 0, which
+        d = rng.normal(size=base[which].shape)
+        h = 1e-7
+        dc, dt_, dx = _fd_directional(o, base, d, which, h)
+        fd = (gQ * dc).sum() + gT * dt_ + (gx * dx).sum()
+        ad = (g[which] * d).sum()
+        assert ad == pytest.approx(fd, rel=1e-5, abs=1e-6), which
+
+
+@pytest.mark.parametrize("alpha,seed", [((1.0, 1.0), 0), ((1.3, 0.6), 5), ((0.8, 1.1), 9)])
+def test_merge_priority_gradient_closed_form(alpha, seed):
+    """Two heads, one entry slot.  In the paper's transfer update X - (M + x)
+    I_remove + (M + x - sg x) I_add with a = onehot(p') + p' - sg(p'),
+    p' = softmax((alpha_from + g')/tau) over the two heads, the winner w moved
+    (its share of the update is M adj_w) and the loser l stayed at its link
+    end x = L (share -(M + L) adj_l), so
+    dL/d alpha_w = -dL/d alpha_l = p'_w p'_l / tau (M adj_w + (M + L) adj_l);
+    the link choice has one candidate (p = 1), so beta gets nothing."""
+    w = W.merge_toy(alpha=alpha, seed=seed)
+    o = Oracle(w, variant="f64", log=True)
+    length, tau, bigm = 100.0, w.cfg.gumbel_tau, w.cfg.big_m
+    o.place([0, 1], [0, 1], [length, length])
+    o.run(1)
+    st = o.state()
+    win = int(np.where(st["link"] == 2)[0][0])
+    lose = 1 - win
+    assert st["link"][lose] == lose and st["pos"][lose] == length and st["pos"][win] == 0.0
+    adj = np.array([0.7, -1.3])
+    g = o.backward(gx=adj)
+    keys = np.array([float(np.float32(alpha[a])) + oracle.gumbel(w.cfg.seed, a, 0, 1, 0) for a in (0, 1)])
+    assert keys[win] > keys[lose]
+    p = np.exp(keys / tau - (keys / tau).max())
+    p /= p.sum()
+    expect = p[win] * p[lose] / tau * (bigm * adj[win] + (bigm + length) * adj[lose])
+    assert g["alpha"][win] == pytest.approx(expect, rel=1e-9)
+    assert g["alpha"][lose] == pytest.approx(-expect, rel=1e-9)
+    assert np.all(g["beta"] == 0.0) and np.all(g["cost"] == 0.0)
