@@ -52,7 +52,9 @@ enum sim_param {
     SIM_P_COST = 4,      /* link cost c, SI-B link utility */
     SIM_P_RATES = 5,     /* departure rate per (origin, time bin), veh/s */
     SIM_P_CAP_MULT = 6,  /* outflow capacity multiplier per link */
-    SIM_P_COUNT = 7
+    SIM_P_THETA = 7,     /* destination-time coefficient theta of the link utility (gradient only: [S],
+                            one value per scenario; the value itself is sim_config.dest_logit_coef) */
+    SIM_P_COUNT = 8
 };
 
 /* Counters per scenario (sim_get_state): */
@@ -165,13 +167,20 @@ int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device);
  * Cotangents (each may be NULL): dL_dcounts [S x det x bins] float,
  * dL_dttt [S] double, dL_dpos [S x n_agents] float (final positions of
  * agents on the network).  grads[k] (for each bit k set in param_mask,
- * SIM_P_U, SIM_P_KAPPA, SIM_P_RATES, SIM_P_CAP_MULT supported) receives
- * dL/d(group k), overwritten, float, same layout as sim_set_params.  Rates
- * reach the loss through departure-time grafting and capacity multipliers
- * through admission-time grafting: a vehicle released, or let through a
- * link's outflow token bucket, carries the time at which its release count
- * or token was reached into its entry position, in the manner of the
- * trajectory grafting of SI-C.  Other groups: SIM_EUNSUPPORTED. */
+ * every group below SIM_P_COUNT) receives dL/d(group k), overwritten, float,
+ * same layout as sim_set_params (SIM_P_THETA: [S]).  Rates reach the loss
+ * through departure-time grafting and capacity multipliers through
+ * admission-time grafting: a vehicle released, or let through a link's
+ * outflow token bucket, carries the time at which its release count or
+ * token was reached into its entry position, in the manner of the
+ * trajectory grafting of SI-C.  beta, cost, alpha and theta reach it
+ * through the straight-through estimator of SI-B: the relaxed route-choice
+ * and merge weights (softmax at temperature gumbel_tau of the same scores
+ * plus the same Gumbel noise) enter the transfer update with value zero and
+ * the softmax's gradient, scaled by big_m; a merge with k winners is k
+ * sequential softmax stages over the candidates not yet picked.  Unknown
+ * bits: SIM_EINVAL; straight-through groups with gumbel_tau <= 0:
+ * SIM_EINVAL. */
 int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const float *dL_dpos,
                  uint32_t param_mask, float *const *grads, int on_device);
 

@@ -37,6 +37,7 @@ struct Dev {
     int32_t nd_begin[4], nd_n[4];    // node id ranges of the node kernel's 8-, 16-, 32- and 64-lane roles
     int64_t ring_total;
     double dt, theta, rate_bin_s;
+    double big_m, tau;               // M and the Gumbel-softmax temperature (straight-through gradients only)
 
     // network (shared by scenarios)
     const int32_t *tail, *head, *lanes, *cap, *ring_base;
@@ -56,12 +57,15 @@ struct Dev {
     const int2 *cand;                // [Nn x max_cand] head lane -> (in-link, in-link index | rank << 8)
     int32_t max_cand;
     const int2 *org_pad;             // [Nn x max_org] (origin, first queue entry)
+    const int32_t *cbase;            // [Nn] first candidate record of each node (candidate lanes in order)
+    int32_t n_cand;                  // candidate records per scenario and step (sum over nodes)
     int32_t max_in, max_out, max_org;
     const int64_t *q_rstep;          // fixed mode: release step of each queue entry
     const uint64_t *seed;            // [S]
 
     // parameters [S x L] / [S x O x B]
     const float *u, *kappa, *alpha, *rates;
+    const float *beta, *cost;        // [S*L] route-choice weight and link cost
     const float *vfree, *spacing;    // derived: u*dt, platoon/kappa
     const double *util;              // beta / cost
     const double *acc;               // cap_mult * capacity * lanes * dt
@@ -93,9 +97,13 @@ struct Dev {
     int32_t *tape_head, *tape_tail;  // [(W+1) * S * L]
     int32_t *tape_dst;               // [(W+1) * S * L * maxl] entry slot of each leaving head (-1: exit)
     float *tape_dstg;                // same shape as tape_dst: admission-graft factor -u_to dt_tok/dm
+    int4 *tape_ste;                  // [(W+1) * S * n_cand] per node candidate: (agent, chosen out-link index |
+                                     // slots << 8 | moved << 16, in-link or -1, ring slot of its adjoint or -1)
     float *adj_ring;                 // [S * ring_total] adjoint of the position of each ring slot's agent
     float *depg;                     // [S*N] adjoint reaching a departure graft, times u of the first link
     double *gu, *gk, *gm;            // [S*L] accumulated parameter gradients (u, kappa, cap_mult)
+    double *gbeta, *gcost, *galpha;  // [S*L] straight-through gradients (beta, cost, alpha)
+    double *gth;                     // [S*Nn] per-node part of the theta gradient
     const float *gQ;                 // [S*D*nb] dL/dcounts (device copy)
     const double *gT;                // [S]
     const float *gx;                 // [S*N]
@@ -127,6 +135,8 @@ void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st);
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st);
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st);
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st);
+void launch_ste(const Dev &d, int t, int tape_k, hipStream_t st);
+void launch_theta_sum(const Dev &d, float *out, hipStream_t st);
 int link_blocks(const Dev &d);
 int node_blocks(const Dev &d);
 int reverse_blocks(const Dev &d);

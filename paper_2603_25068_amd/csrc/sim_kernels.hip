@@ -491,7 +491,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         inc[CTR_RELEASED] += newrel - rel;
         if (dp0 < newrel) { ag = fa; dst = fdst; didx = fdidx; }
     }
+    const bool ste_rec = tape_k >= 0 && d.tape_ste != nullptr;   // straight-through tape (recording replay)
+    const int64_t ste_i = ((int64_t)tape_k * d.S + s) * d.n_cand + (ste_rec ? d.cbase[v] : 0) + gl;
     if (g.count(ag >= 0) == 0) {   // nothing to move at this node this step
+        if (ste_rec && gl < nc) d.tape_ste[ste_i] = make_int4(-1, 0, -1, -1);
         add_counters<G>(d, g, s, item, inc);
         return;
     }
@@ -660,6 +663,19 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
                 const double dtdm = -dBq / mqn + (Bq - (double)tok - 1.0) / (mm * mqn);
                 gfac = (float)(-(double)d.u[sL + ch] * dtdm);
             }
+        }
+    }
+    if (ste_rec) {   // this candidate's choice, outcome and the ring slot its adjoint will hold at t+1
+        const int hq = __shfl(hq0, q_of_lane, G);   // in-link's head counter before this step
+        if (gl < nc) {
+            int4 rec = make_int4(-1, 0, -1, -1);
+            if (ag >= 0 && ch >= 0) {
+                int loc = -1;
+                if (passed) loc = (int)(slot - (int64_t)s * d.ring_total);
+                else if (from >= 0) loc = d.ring_base[from] + (hq + hr_r) % d.cap[from];
+                rec = make_int4(ag, argk | (min(sl, 255) << 8) | (passed << 16), from, loc);
+            }
+            d.tape_ste[ste_i] = rec;
         }
     }
     if (tape_k >= 0 && passed && from >= 0) {   // where each leaving head went (-1: left the network)
@@ -944,6 +960,221 @@ __global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int i
     const unsigned long long t0 = stamp_begin(d);
     reverse_launch<G>(d, t, tape_k, init);
     stamp_end(d, t0);
+}
+
+// ---------------------------------------------------------------------------
+// Straight-through gradients of step t (SI-B), per node, launched before the
+// reverse of step t overwrites the adjoints: adj_ring holds dL/dx(t+1).  The
+// hard route choices and merge winners of the forward are held; their relaxed
+// weights (value 0, gradient of the softmax) enter the transfer update, so a
+// candidate whose weight for its chosen link changes by dw changes the loss by
+// G dw with
+//   G = M adj(entry slot)            if it moved (entry position M + x - sg x),
+//   G = -(M + x_hat) adj(own slot)   if it stayed on its in-link,
+//   G = 0                            if an origin front stayed.
+// Merge onto one link with k winners: k Plackett-Luce stages, stage s a
+// softmax of (alpha_from l + g')/tau over the candidates ranked s and below
+// (k = 1 is the single-winner merge of the text), l = 1 the candidate's
+// relaxed weight of that link.  dL/d(merge utility) of a candidate is the sum
+// over its stages of q (G - sum q G) / tau; alpha takes it directly and the
+// route weight l takes alpha times it, which flows through the chosen link's
+// softmax weight pi = softmax((V + g)/tau) into V_m = beta_m/c_m - theta r_m
+// (r_m the link's free-flow time plus the shortest time to the destination).
+// One lane group per (scenario, node) in the node classes of the forward;
+// every accumulator has this node as its only writer (beta, cost: its
+// out-links; alpha: its in-links; theta: its own entry), so the sums are
+// deterministic.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void ste_work(Dev &d, const Group<G> &g, int s, int v, int t, int tape_k,
+                                         double *sy, double *sg, double *sd, int *sk, int *sr, int *sa)
+{
+    const int gl = g.gl;
+    const int cnt = d.node_cnt[v];
+    const int deg = cnt & 0xff, dego = (cnt >> 8) & 0xff, norg = (cnt >> 16) & 0xff;
+    const int nc = ((cnt >> 24) & 0xff) + norg;
+    const int64_t sL = (int64_t)s * d.L, sR = (int64_t)s * d.ring_total;
+    const int4 rc = gl < nc ? d.tape_ste[((int64_t)tape_k * d.S + s) * d.n_cand + d.cbase[v] + gl]
+                            : make_int4(-1, 0, -1, -1);
+    if (g.count(rc.x >= 0) < 2) return;   // a lone candidate has weight 1 in every softmax
+    const int ag = rc.x, argk = rc.y & 0xff, kst = (rc.y >> 8) & 0xff, moved = (rc.y >> 16) & 1;
+    const int from = rc.z, loc = rc.w;
+    const bool cand = ag >= 0;
+    const double tau = d.tau;
+    const uint64_t seed = d.seed[s];
+    double Gc = 0.0, y = 0.0, al = 1.0;
+    int ftail = -1;
+    if (cand) {
+        if (from >= 0) { al = (double)d.alpha[sL + from]; ftail = d.tail[from]; }
+        uint32_t w[4];
+        draw4(seed, ag, t, 1, 0, w);
+        y = al + gumbel_of(w[0]);
+        if (loc >= 0) {
+            const double A = (double)d.adj_ring[sR + loc];
+            if (moved) {
+                Gc = d.big_m * A;
+            } else {
+                const double xh = (double)d.tape_pos[(int64_t)(tape_k + 1) * d.S * d.ring_total + sR + loc];
+                Gc = -(d.big_m + xh) * A;
+            }
+        }
+    }
+    sy[gl] = y;
+    sg[gl] = Gc;
+    sk[gl] = cand ? argk : -1;
+    sa[gl] = ag;
+    wave_lds_sync();
+    // place in the merge order of its target (key descending, agent id on ties) and group size
+    int rho = 0, n = 1;
+    if (cand) {
+        for (int e = 0; e < nc; ++e) {
+            if (e == gl || sk[e] != argk) continue;
+            ++n;
+            const double y2 = sy[e];
+            if (y2 > y || (y2 == y && sa[e] < ag)) ++rho;
+        }
+    }
+    sr[gl] = rho;
+    wave_lds_sync();
+    double dVp = 0.0;
+    if (cand && n >= 2) {
+        const int K = min(n, kst);
+        for (int st = 0; st < K && st <= rho; ++st) {
+            double mx = -INFINITY;
+            for (int e = 0; e < nc; ++e)
+                if (sk[e] == argk && sr[e] >= st) mx = fmax(mx, sy[e] / tau);
+            double Z = 0.0, ZG = 0.0;
+            for (int e = 0; e < nc; ++e) {
+                if (sk[e] != argk || sr[e] < st) continue;
+                const double q = exp(sy[e] / tau - mx);
+                Z += q;
+                ZG += q * sg[e];
+            }
+            const double q = exp(y / tau - mx) / Z;
+            dVp += q / tau * (Gc - ZG / Z);
+        }
+    }
+    sd[gl] = dVp;
+    wave_lds_sync();
+    if (gl < deg) {   // alpha of in-link gl: its candidate lanes in order
+        const int jin = d.in_pad[(int64_t)v * d.max_in + gl];
+        const int off = d.in_loff[(int64_t)v * d.max_in + gl], ln = d.lanes[jin];
+        double a = 0.0;
+        bool any = false;
+        for (int r = 0; r < ln; ++r) { a += sd[off + r]; any |= sk[off + r] >= 0; }
+        if (any) d.galpha[sL + jin] += a;
+    }
+    const double gam = al * dVp;
+    if (g.count(gam != 0.0) == 0) return;
+    // route choice: softmax of (V + g)/tau over the admissible out-links, then dV_m per out-link
+    int om = -1, ohead = -1;
+    double outil = 0.0;
+    if (gl < dego) {
+        om = d.out_pad[(int64_t)v * d.max_out + gl];
+        ohead = d.head[om];
+        outil = d.util[sL + om];
+    }
+    const double *route = d.route + d.route_base[v] + (int64_t)(cand ? d.agent_didx[ag] : 0) * dego;
+    const bool on = cand && gam != 0.0;
+    auto scores = [&](int b0, double (&yk)[4], double (&rk)[4]) {
+        int hk[4];
+        double uk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int src = min(b0 + q, G - 1);
+            hk[q] = __shfl(ohead, src, G);
+            uk[q] = __shfl(outil, src, G);
+        }
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (on) draw4(seed, ag, t, 0, b0 >> 2, w);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            yk[q] = -INFINITY;
+            rk[q] = (on && b0 + q < dego) ? route[b0 + q] : INFINITY;
+            if (!on || b0 + q >= dego) continue;
+            if (!d.allow_uturn && from >= 0 && hk[q] == ftail) continue;
+            if (!(rk[q] < INFINITY)) continue;
+            yk[q] = (uk[q] - d.theta * rk[q] + gumbel_of(w[q])) / tau;
+        }
+    };
+    double mx = -INFINITY, Z = 0.0, ych = -INFINITY;
+    for (int b0 = 0; b0 < dego; b0 += 4) {
+        double yk[4], rk[4];
+        scores(b0, yk, rk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (yk[q] == -INFINITY) continue;
+            if (b0 + q == argk) ych = yk[q];
+            if (yk[q] > mx) { Z = Z * exp(mx - yk[q]) + 1.0; mx = yk[q]; }
+            else Z += exp(yk[q] - mx);
+        }
+    }
+    const double ps = on ? exp(ych - mx) / Z : 0.0;   // weight of the chosen link
+    double mys = 0.0, th = 0.0;
+    for (int b0 = 0; b0 < dego; b0 += 4) {
+        double yk[4], rk[4];
+        scores(b0, yk, rk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double dv = 0.0;
+            if (yk[q] != -INFINITY) {
+                const double p = exp(yk[q] - mx) / Z;
+                dv = gam / tau * ps * ((b0 + q == argk ? 1.0 : 0.0) - p);
+                th -= rk[q] * dv;
+            }
+            const double sum = g.sum(dv);
+            if (gl == b0 + q) mys = sum;
+        }
+    }
+    if (gl < dego && mys != 0.0) {
+        const double c = (double)d.cost[sL + om], b = (double)d.beta[sL + om];
+        d.gbeta[sL + om] += mys / c;
+        d.gcost[sL + om] -= b / (c * c) * mys;
+    }
+    th = g.sum(th);
+    if (gl == 0) d.gth[(int64_t)s * d.Nn + v] += th;
+}
+
+template <int G>
+__device__ __forceinline__ void ste_role(Dev &d, int c, int b, int nblk, int t, int tape_k, double *sy, double *sg,
+                                         double *sd, int *sk, int *sr, int *sa)
+{
+    const Group<G> g;
+    const int per = 256 / G;
+    const int n = d.S * d.nd_n[c];
+    const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / G;
+    if (item >= n) return;
+    const int s = item / d.nd_n[c];
+    const int o = (int)threadIdx.x & ~(G - 1);
+    ste_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), t, tape_k, sy + o, sg + o, sd + o, sk + o, sr + o,
+                sa + o);
+}
+
+__global__ __launch_bounds__(256) void k_ste(Dev d, int t, int tape_k)
+{
+    __shared__ double sy[256], sg[256], sd[256];
+    __shared__ int sk[256], sr[256], sa[256];
+    int b = (int)blockIdx.x;
+    const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
+    if (b < b8) { ste_role<8>(d, 0, b, b8, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
+    b -= b8;
+    const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
+    if (b < b16) { ste_role<16>(d, 1, b, b16, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
+    b -= b16;
+    const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
+    if (b < b32) { ste_role<32>(d, 2, b, b32, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
+    b -= b32;
+    ste_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, sy, sg, sd, sk, sr, sa);
+}
+
+// theta gradient of each scenario: the per-node parts summed in node order by one wavefront
+__global__ __launch_bounds__(64) void k_theta_sum(Dev d, float *out)
+{
+    const int s = blockIdx.x;
+    double a = 0.0;
+    for (int v = lane_id(); v < d.Nn; v += kWave) a += d.gth[(int64_t)s * d.Nn + v];
+    a = wave_sum_d(a);
+    if (lane_id() == 0) out[s] = (float)a;
 }
 
 // dL/d rates[s, o, b] = sum over departed agents of origin o of
@@ -1281,6 +1512,14 @@ void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st)
     case 32: launch(k_reverse<32>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 32), st, d, t, tape_k, init); break;
     default: launch(k_reverse<64>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 64), st, d, t, tape_k, init); break;
     }
+}
+void launch_ste(const Dev &d, int t, int tape_k, hipStream_t st)
+{
+    launch(k_ste, std::max(node_blocks(d), 1), st, d, t, tape_k);
+}
+void launch_theta_sum(const Dev &d, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_theta_sum, dim3(d.S), dim3(64), 0, st, d, out);
 }
 void launch_rate_grad(const Dev &d, float *g, hipStream_t st)
 {

@@ -105,6 +105,7 @@ struct sim_t {
     struct TapeSet {
         float *pos = nullptr, *dstg = nullptr;
         int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *dst = nullptr;
+        int4 *ste = nullptr;   // node candidates' choices and outcomes (straight-through gradients)
     };
     std::vector<TapeSet> tapes;              // n_replay + 1 sets
     // concurrent replays of the backward pass: each has its own copy of the mutable state and
@@ -115,6 +116,7 @@ struct sim_t {
     std::vector<hipEvent_t> bw_events;       // replay-done and reverse-done events per window
     float *tape_dstg_buf = nullptr;   // admission-graft tape, attached only for cap_mult gradients
     double *gm_buf = nullptr;
+    double *gbeta_buf = nullptr, *gcost_buf = nullptr, *galpha_buf = nullptr, *gth_buf = nullptr;
     // autotuner snapshot of the live state (allocated on first use)
     bool tune_alloc = false;
     Ckpt tune_ck;
@@ -130,6 +132,8 @@ struct sim_t {
     int32_t max_in = 1, max_out = 1, max_org = 1, max_cand = 1;
     std::vector<int32_t> in_loff;
     std::vector<int2> cand;
+    std::vector<int32_t> cbase;   // first straight-through record of each node
+    int32_t n_cand = 0;
     // adjoint buffers
     float *gQ_dev = nullptr, *gx_dev = nullptr;
     double *gT_dev = nullptr, *ttt_dev = nullptr;
@@ -787,6 +791,8 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     h->in_loff.assign((size_t)Nn * h->max_in, 0);
     h->out_pad.assign((size_t)Nn * h->max_out, -1);
     h->cand.assign((size_t)Nn * h->max_cand, make_int2(0, 0));
+    h->cbase.assign(Nn, 0);
+    h->n_cand = 0;
     for (int v = 0; v < Nn; ++v) {
         const int di = h->in_off[v + 1] - h->in_off[v], dout = h->out_off[v + 1] - h->out_off[v];
         const int no = h->org_off[v + 1] - h->org_off[v];
@@ -799,6 +805,8 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
             nl += h->lanes[j];
         }
         h->node_cnt[v] = di | (dout << 8) | (no << 16) | (nl << 24);
+        h->cbase[v] = h->n_cand;
+        h->n_cand += nl + no;
         for (int k = 0; k < dout; ++k) h->out_pad[(size_t)v * h->max_out + k] = h->out_lnk[h->out_off[v] + k];
     }
     // rings: a link holds at most lanes * (floor(L / spacing) + 1) agents; two extra rows of slack
@@ -885,6 +893,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.fixed_mode = h->fixed_mode; d.allow_uturn = cfg->allow_uturn; d.platoon = h->platoon;
     d.g_link = h->g_link; d.g_node = h->g_node; d.g_rev = h->g_rev;
     d.ring_total = h->ring_total; d.dt = h->dt; d.theta = cfg->dest_logit_coef; d.rate_bin_s = h->rate_bin_s;
+    d.big_m = cfg->big_m; d.tau = cfg->gumbel_tau;
     d.rate_bin_steps = h->fixed_mode ? 1 : std::max(1, (int)std::lround(h->rate_bin_s / h->dt));
     d.tail = h->upload(h->tail); d.head = h->upload(h->head); d.lanes = h->upload(h->lanes);
     h->linv_dev = h->upload(h->linv);
@@ -913,6 +922,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev; d.org_pad = h->org_pad_dev;
     d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
     d.in_loff = h->upload(h->in_loff); d.cand = h->upload(h->cand); d.max_cand = h->max_cand;
+    d.cbase = h->upload(h->cbase); d.n_cand = h->n_cand;
     d.max_in = h->max_in; d.max_out = h->max_out; d.max_org = h->max_org;
     d.seed = h->upload(h->seeds);
     // parameters, scenario-major
@@ -928,6 +938,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     h->capacity_dev = h->upload(h->capacity);
     d.capm = h->p_capm; d.capacity = h->capacity_dev;
     d.u = h->p_u; d.kappa = h->p_kappa; d.alpha = h->p_alpha; d.rates = h->p_rates;
+    d.beta = h->p_beta; d.cost = h->p_cost;
     h->vfree = h->dalloc<float>(SL); h->spacing = h->dalloc<float>(SL);
     h->util = h->dalloc<double>(SL); h->acc = h->dalloc<double>(SL);
     d.vfree = h->vfree; d.spacing = h->spacing; d.util = h->util; d.acc = h->acc;
@@ -957,6 +968,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
             ts.tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
             ts.dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
             ts.dstg = h->dalloc<float>((size_t)(h->W + 1) * SL * maxl);
+            ts.ste = h->dalloc<int4>((size_t)(h->W + 1) * h->S * std::max(h->n_cand, 1));
         }
         d.tape_pos = h->tapes[0].pos; d.tape_agent = h->tapes[0].agent;
         d.tape_head = h->tapes[0].head; d.tape_tail = h->tapes[0].tail;
@@ -984,6 +996,9 @@ void allocate_device(sim_t *h, const sim_config *cfg)
         h->tape_dstg_buf = h->tapes[0].dstg;
         h->gm_buf = h->dalloc<double>(SL);
         d.tape_dstg = nullptr; d.gm = nullptr;
+        h->gbeta_buf = h->dalloc<double>(SL); h->gcost_buf = h->dalloc<double>(SL);
+        h->galpha_buf = h->dalloc<double>(SL); h->gth_buf = h->dalloc<double>((size_t)h->S * Nn);
+        d.tape_ste = nullptr; d.gbeta = d.gcost = d.galpha = d.gth = nullptr;
         h->gQ_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
         h->gx_dev = h->dalloc<float>(SN);
         h->gT_dev = h->dalloc<double>(h->S);
@@ -1345,11 +1360,17 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         if (!h->record) fail(SIM_ESTATE, "handle was created without record_for_backward");
         if (!h->rec_valid || h->t == 0 || h->ckpts[0].t != 0)
             fail(SIM_ESTATE, "sim_backward needs a recorded rollout from t = 0 (at most max_steps)");
-        const uint32_t ok = (1u << SIM_P_U) | (1u << SIM_P_KAPPA) | (1u << SIM_P_RATES) | (1u << SIM_P_CAP_MULT);
-        if (param_mask & ~ok) fail(SIM_EUNSUPPORTED, "gradient groups supported: u, kappa, rates, cap_mult");
+        if (param_mask >> SIM_P_COUNT) fail(SIM_EINVAL, "unknown gradient group in param_mask");
         const bool want_m = (param_mask & (1u << SIM_P_CAP_MULT)) != 0;
+        const uint32_t ste_mask = (1u << SIM_P_BETA) | (1u << SIM_P_COST) | (1u << SIM_P_ALPHA) | (1u << SIM_P_THETA);
+        const bool want_ste = (param_mask & ste_mask) != 0;
+        if (want_ste && !(h->d.tau > 0.0)) fail(SIM_EINVAL, "straight-through gradients need gumbel_tau > 0");
         h->d.tape_dstg = want_m ? h->tape_dstg_buf : nullptr;
         h->d.gm = want_m ? h->gm_buf : nullptr;
+        h->d.gbeta = want_ste ? h->gbeta_buf : nullptr;
+        h->d.gcost = want_ste ? h->gcost_buf : nullptr;
+        h->d.galpha = want_ste ? h->galpha_buf : nullptr;
+        h->d.gth = want_ste ? h->gth_buf : nullptr;
         if ((param_mask & (1u << SIM_P_RATES)) && h->fixed_mode) fail(SIM_EINVAL, "rates need departure-rate mode");
         if (param_mask && !grads) fail(SIM_EINVAL, "grads is NULL");
         Dev d = h->d;
@@ -1366,6 +1387,12 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         HIPCHK(hipMemsetAsync(d.gu, 0, SL * 8, st));
         HIPCHK(hipMemsetAsync(d.gk, 0, SL * 8, st));
         if (want_m) HIPCHK(hipMemsetAsync(d.gm, 0, SL * 8, st));
+        if (want_ste) {
+            HIPCHK(hipMemsetAsync(d.gbeta, 0, SL * 8, st));
+            HIPCHK(hipMemsetAsync(d.gcost, 0, SL * 8, st));
+            HIPCHK(hipMemsetAsync(d.galpha, 0, SL * 8, st));
+            HIPCHK(hipMemsetAsync(d.gth, 0, (size_t)h->S * h->Nn * 8, st));
+        }
         const int T = h->t;
         const int nw = (T + h->ckpt_every - 1) / h->ckpt_every;
         // in timing mode the windows run one after another (one replay slot, each replay after the
@@ -1383,6 +1410,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_head = ts.head; dv.tape_tail = ts.tail;
             dv.tape_dst = ts.dst;
             dv.tape_dstg = want_m ? ts.dstg : nullptr;
+            dv.tape_ste = want_ste ? ts.ste : nullptr;
         };
         auto replay = [&](int w) {
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
@@ -1408,8 +1436,10 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             HIPCHK(hipStreamWaitEvent(st, rp_done[w], 0));
             use_tapes(d, w % NT);
             if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
-            for (int k = Ww - 1; k >= 0; --k)
+            for (int k = Ww - 1; k >= 0; --k) {
+                if (want_ste) sim::launch_ste(d, t0 + k, k, st);   // reads dL/dx(t+1) before the reverse replaces it
                 sim::launch_reverse(h->stamped(d, 2, sim::reverse_blocks(d)), t0 + k, k, 0, st);
+            }
             HIPCHK(hipEventRecord(rv_done[w], st));
             if (w - K >= 0) replay(w - K);
             HIPCHK(hipGetLastError());
@@ -1417,6 +1447,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         // the main stream has waited for every replay (each sweep waits for its own)
         h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
         h->d.tape_dstg = nullptr; h->d.gm = nullptr;
+        h->d.gbeta = h->d.gcost = h->d.galpha = h->d.gth = nullptr;
         const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         if (param_mask & (1u << SIM_P_U)) {
             sim::launch_gather_links(d.gu, h->linv_dev, h->grad_tmp, h->S, h->L, st);
@@ -1429,6 +1460,17 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         if (want_m) {
             sim::launch_gather_links(d.gm, h->linv_dev, h->grad_tmp, h->S, h->L, st);
             HIPCHK(hipMemcpyAsync(grads[SIM_P_CAP_MULT], h->grad_tmp, SL * 4, kout, st));
+        }
+        const std::pair<int, double *> ste_links[3] = {
+            {SIM_P_BETA, d.gbeta}, {SIM_P_COST, d.gcost}, {SIM_P_ALPHA, d.galpha}};
+        for (const auto &pg : ste_links) {
+            if (!(param_mask & (1u << pg.first))) continue;
+            sim::launch_gather_links(pg.second, h->linv_dev, h->grad_tmp, h->S, h->L, st);
+            HIPCHK(hipMemcpyAsync(grads[pg.first], h->grad_tmp, SL * 4, kout, st));
+        }
+        if (param_mask & (1u << SIM_P_THETA)) {
+            sim::launch_theta_sum(d, h->grad_tmp, st);
+            HIPCHK(hipMemcpyAsync(grads[SIM_P_THETA], h->grad_tmp, (size_t)h->S * 4, kout, st));
         }
         if (param_mask & (1u << SIM_P_RATES)) {
             const size_t nr = (size_t)h->S * h->O * h->B;

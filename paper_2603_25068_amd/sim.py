@@ -17,7 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsim.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PARAMS = {"free_speed": 0, "jam_density": 1, "beta": 2, "alpha": 3, "cost": 4, "rates": 5, "cap_mult": 6}
+PARAMS = {"free_speed": 0, "jam_density": 1, "beta": 2, "alpha": 3, "cost": 4, "rates": 5, "cap_mult": 6,
+          "theta": 7}   # theta: gradient only (its value is the config's dest_logit_coef)
+N_GROUPS = 8
 PARAM_NAMES = {v: k for k, v in PARAMS.items()}
 COUNTER_NAMES = ("released", "departed", "on_net", "exited", "transfers", "ties", "stuck", "order_viol")
 WAIT, QUEUED, ON, EXITED = 0, 1, 2, 3
@@ -220,6 +222,8 @@ class Simulator:
     def n_per(self, group: str) -> int:
         if group == "rates":
             return self.w.net.n_origins * self.w.dem.n_rate_bins
+        if group == "theta":
+            return 1
         return self.w.net.n_links
 
     # -- control ----------------------------------------------------------
@@ -283,7 +287,7 @@ class Simulator:
         gx = None if gx is None else _f32(np.asarray(gx, np.float32).reshape(S, -1))
         mask = 0
         bufs = {}
-        arr = (C.c_void_p * 7)()
+        arr = (C.c_void_p * N_GROUPS)()
         for g in groups:
             k = PARAMS[g]
             mask |= 1 << k
@@ -297,7 +301,7 @@ class Simulator:
         dev = torch.device("cuda", self.device)
         mask = 0
         out = {}
-        arr = (C.c_void_p * 7)()
+        arr = (C.c_void_p * N_GROUPS)()
         for g in groups:
             k = PARAMS[g]
             mask |= 1 << k
@@ -494,34 +498,45 @@ class Server:
 def make_rollout_function():
     """torch.autograd.Function around one recorded rollout: forward sets the
     parameters and runs T steps, returning detector counts and total travel
-    time; backward runs the checkpointed adjoint.  `rates` and `cap_mult` may
-    be None (left as they are, no gradient)."""
+    time; backward runs the checkpointed adjoint.  `rates`, `cap_mult`,
+    `beta`, `cost` and `alpha` may be None (left as they are, no gradient);
+    the last three take their gradient through the straight-through node
+    model."""
     import torch
+
+    optional = ("rates", "cap_mult", "beta", "cost", "alpha")
 
     class SimRollout(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, sim: Simulator, T: int, free_speed, jam_density, rates=None, cap_mult=None):
+        def forward(ctx, sim: Simulator, T: int, free_speed, jam_density, rates=None, cap_mult=None,
+                    beta=None, cost=None, alpha=None):
             sim.set_params("free_speed", free_speed)
             sim.set_params("jam_density", jam_density)
-            if rates is not None and rates.numel() > 0:
-                sim.set_params("rates", rates)
-            if cap_mult is not None:
-                sim.set_params("cap_mult", cap_mult)
+            given = {"rates": rates, "cap_mult": cap_mult, "beta": beta, "cost": cost, "alpha": alpha}
+            ctx.groups = ("free_speed", "jam_density")
+            ctx.shapes = {"free_speed": free_speed.shape, "jam_density": jam_density.shape}
+            for name in optional:
+                v = given[name]
+                if v is not None and v.numel() > 0:
+                    sim.set_params(name, v)
+                    ctx.groups += (name,)
+                    ctx.shapes[name] = v.shape
             sim.reset()
             sim.step(T)
             counts, ttt = sim.observables_device()
             ctx.sim = sim
-            ctx.has_rates = rates is not None and rates.numel() > 0
-            ctx.has_capm = cap_mult is not None
             return counts, ttt
 
         @staticmethod
         def backward(ctx, g_counts, g_ttt):
-            sim = ctx.sim
-            groups = ("free_speed", "jam_density") + (("rates",) if ctx.has_rates else ()) + \
-                (("cap_mult",) if ctx.has_capm else ())
-            g = sim.backward_device(gQ=g_counts.float() if g_counts is not None else None,
-                                    gT=g_ttt.double() if g_ttt is not None else None, groups=groups)
-            return None, None, g["free_speed"], g["jam_density"], g.get("rates"), g.get("cap_mult")
+            g = ctx.sim.backward_device(gQ=g_counts.float() if g_counts is not None else None,
+                                        gT=g_ttt.double() if g_ttt is not None else None, groups=ctx.groups)
+
+            def shaped(name):   # [S, n] -> the input's shape; one set shared by all scenarios sums them
+                if name not in g:
+                    return None
+                x, shp = g[name], ctx.shapes[name]
+                return (x if x.numel() == shp.numel() else x.sum(0)).reshape(shp)
+            return (None, None, shaped("free_speed"), shaped("jam_density")) + tuple(shaped(n) for n in optional)
 
     return SimRollout

@@ -281,6 +281,79 @@ def test_batched_control_gradients_match_oracle():
         _grad_close(go, gg[k], f"cap_mult scenario {k}")
 
 
+@pytest.mark.parametrize("seed", [4, 10, 23])
+def test_straight_through_gradient_parity(seed):
+    """beta, cost, alpha and theta through the straight-through node model
+    (SI-B) on the GPU against the oracle, with every other group on the same
+    run; two scenarios with their own seeds and utilities in one launch."""
+    w = W.random_small(seed, nx=4, ny=4, n_agents=600, rates=True, steps=300)
+    rng = np.random.default_rng(seed)
+    L, S = w.net.n_links, 2
+    prm = {"beta": rng.uniform(0.5, 2.0, (S, L)).astype(np.float32),
+           "cost": rng.uniform(1.0, 3.0, (S, L)).astype(np.float32),
+           "alpha": rng.uniform(0.5, 2.0, (S, L)).astype(np.float32)}
+    seeds = [seed * 7 + k for k in range(S)]
+    s = _sim(w, n_scenarios=S, record=True, ckpt_every=41, params=prm, seeds=seeds).rollout()
+    groups = ("free_speed", "jam_density", "rates", "beta", "cost", "alpha", "theta")
+    cg, _ = s.observables()
+    gQ = rng.normal(size=cg.shape).astype(np.float32)
+    gT = np.array([0.3, -0.2])
+    gg = s.backward(gQ=gQ, gT=gT, groups=groups)
+    for k in range(S):
+        o = Oracle(w, log=True, params={n: prm[n][k] for n in prm}, seed=seeds[k]).run()
+        _compare_state(o, s, scen=k, ctx=f"scenario {k}")
+        go = o.backward(gQ=gQ[k].astype(np.float64), gT=float(gT[k]))
+        for g in ("beta", "cost", "alpha", "theta"):
+            assert np.abs(go[g]).max() > 0, g
+        for g in groups:
+            _grad_close(go[g], gg[g][k], f"{g} scenario {k}")
+
+
+@pytest.mark.parametrize("alpha,seed", [((1.0, 1.0), 0), ((1.3, 0.6), 5), ((0.8, 1.1), 9)])
+def test_merge_priority_gradient_closed_form_gpu(alpha, seed):
+    """Two heads, one entry slot: dL/d alpha_w = -dL/d alpha_l =
+    p'_w p'_l / tau (M adj_w + (M + L) adj_l) with p' the merge softmax of
+    (alpha_from + g')/tau; one route candidate, so beta and cost get nothing."""
+    w = W.merge_toy(alpha=alpha, seed=seed)
+    length, tau, bigm = 100.0, w.cfg.gumbel_tau, w.cfg.big_m
+    s = _sim(w, record=True, max_steps=1)
+    s.place([0, 1], [0, 1], [length, length])
+    s.step(1)
+    st = s.state()
+    win = int(np.where(st["link"][0] == 2)[0][0])
+    lose = 1 - win
+    assert st["link"][0][lose] == lose and st["pos"][0][lose] == length
+    adj = np.float32([0.7, -1.3])
+    g = s.backward(gx=adj[None], groups=("alpha", "beta", "cost", "theta"))
+    keys = np.array([float(np.float32(alpha[a])) + oracle.gumbel(w.cfg.seed, a, 0, 1, 0) for a in (0, 1)])
+    p = np.exp(keys / tau - (keys / tau).max())
+    p /= p.sum()
+    expect = p[win] * p[lose] / tau * (bigm * adj[win] + (bigm + length) * adj[lose])
+    assert g["alpha"][0][win] == pytest.approx(expect, rel=1e-5)
+    assert g["alpha"][0][lose] == pytest.approx(-expect, rel=1e-5)
+    assert np.all(g["beta"] == 0.0) and np.all(g["cost"] == 0.0) and np.all(g["theta"] == 0.0)
+
+
+def test_rollout_autograd_function_matches_backward():
+    """The torch.autograd wrapper returns exactly what a direct backward call
+    on the same recorded rollout returns, for every group it was given."""
+    import torch
+    from paper_2603_25068_amd.sim import make_rollout_function
+    w = W.random_small(6, nx=4, ny=4, n_agents=500, rates=True, steps=200)
+    s = _sim(w, record=True)
+    dev = torch.device("cuda", 0)
+    leaf = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev, requires_grad=True)
+    u, k, r = leaf(w.net.free_speed), leaf(w.net.jam_density), leaf(w.dem.rates)
+    beta, alpha = leaf(w.net.beta), leaf(w.net.alpha)
+    counts, ttt = make_rollout_function().apply(s, 200, u, k, r, None, beta, None, alpha)
+    wq = torch.randn(counts.shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    ((counts * wq).sum() + 0.1 * ttt.sum()).backward()
+    g = s.backward(gQ=wq.cpu().numpy(), gT=[0.1], groups=("free_speed", "jam_density", "rates", "beta", "alpha"))
+    for name, x in (("free_speed", u), ("jam_density", k), ("rates", r), ("beta", beta), ("alpha", alpha)):
+        assert np.array_equal(x.grad.cpu().numpy().ravel(), g[name][0]), name
+    assert np.abs(g["alpha"]).max() > 0
+
+
 def test_autotune_restores_state_and_caches(tmp_path):
     """The autotuner probes from the live state and puts it back: a rollout
     tuned half-way equals an untuned one (values and gradients), and a second
