@@ -1523,6 +1523,7 @@ void launch_theta_sum(const Dev &d, float *out, hipStream_t st)
 }
 void launch_rate_grad(const Dev &d, float *g, hipStream_t st)
 {
+    if ((int64_t)d.S * d.O == 0) return;
     hipLaunchKernelGGL(k_rate_grad, dim3(blocks_for((int64_t)d.S * d.O)), dim3(256), 0, st, d, g);
 }
 void launch_derive(const Dev &d, const float *cap_mult, const float *capacity, const float *beta,

@@ -231,7 +231,7 @@ class Simulator:
         import torch
         n = self.n_per(group)
         if isinstance(values, torch.Tensor) and values.is_cuda:
-            v = values.detach().to(torch.float32).contiguous()
+            v = values.detach().to(torch.float32).reshape(-1).contiguous()
             if v.numel() == n:
                 v = v.repeat(self.S)
             self._chk(self._L.sim_set_params(self._h, PARAMS[group], C.c_void_p(v.data_ptr()), v.numel(), 1))

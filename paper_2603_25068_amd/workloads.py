@@ -440,6 +440,48 @@ def merge_toy(alpha=(1.0, 1.0), length: float = 100.0, speed: float = 10.0, seed
     return Workload("merge_toy", net, dem, cfg)
 
 
+def hub(n_spokes: int = 8, lanes: int = 8, long_len: float = 1500.0, short_len: float = 60.0,
+        n_agents: int = 8000, steps: int = 600, capacity: float = 0.05, seed: int = 3) -> Workload:
+    """The kernels' largest cases in one network.  A hub node 0 with n_spokes
+    two-way roads of `lanes` lanes, so its in-links offer n_spokes * lanes
+    merge candidates (64: one full wavefront).  Even roads are long (rings of
+    lanes * (L / jam spacing + 4) slots, far above 128), odd roads short.  Low
+    outflow capacity makes queues fill every lane at the hub.  Spoke 1 has
+    four origin queues (one front each per step) releasing fast, so the long
+    link 1 -> 0 holds many hundreds of agents (several staging pieces); it also
+    carries four detectors, the per-link maximum.  One origin on every other
+    spoke; each agent is bound for another spoke through the hub; departure
+    rates per (origin, 4 bins)."""
+    rng = np.random.default_rng(seed)
+    roads = np.asarray([(0, k + 1) for k in range(n_spokes)], np.int64)
+    length = np.where(np.arange(n_spokes) % 2 == 0, long_len, short_len)
+    speed = rng.choice(np.asarray(SPEED_CHOICES), n_spokes)
+    origin_node = np.asarray([1, 1, 1, 1] + list(range(2, n_spokes + 1)))
+    net = make_network(n_spokes + 1, roads, length, np.full(n_spokes, lanes), speed,
+                       origin_node=origin_node, n_detectors=0, rng=rng,
+                       beta=np.repeat(rng.uniform(0.5, 2, n_spokes), 2),
+                       alpha=np.repeat(rng.uniform(0.5, 2, n_spokes), 2),
+                       cost=np.repeat(rng.uniform(0.5, 2, n_spokes), 2))
+    net.capacity = _f32(np.full(net.n_links, capacity))
+    # link 2k+1 is spoke k+1 -> hub: four detectors on link 1, one mid-link on every other in-link
+    det = [1, 1, 1, 1] + [2 * k + 1 for k in range(1, n_spokes)]
+    frac = [0.2, 0.4, 0.6, 0.8] + [0.5] * (n_spokes - 1)
+    net.detector_link = _i32(det)
+    net.detector_pos = _f32([net.length[j] * np.float32(f) for j, f in zip(det, frac)])
+    O = len(origin_node)
+    o = np.concatenate([np.arange(n_agents // 2) % 4, rng.integers(4, O, n_agents - n_agents // 2)])
+    dest = np.empty(n_agents, np.int64)
+    for i in range(n_agents):
+        home = origin_node[o[i]]
+        dest[i] = 1 + (home + rng.integers(n_spokes - 1)) % n_spokes   # any spoke but home
+    bins = 4
+    rates = rng.uniform(0.5, 1.0, (O, bins))
+    rates[:4, :2] = 1.5
+    dem = Demand(agent_origin=_i32(o), agent_dest=_i32(dest), rates=_f32(rates), rate_bin_s=steps / bins)
+    cfg = Config(dt=1.0, steps=steps, count_bin_steps=steps // 4, gumbel_tau=0.5, seed=seed, ckpt_every=60)
+    return Workload("hub64", net, dem, cfg)
+
+
 def diamond(n_agents: int = 200, lanes: int = 1, seed: int = 7, length: float = 100.0,
             horizon_s: float = 300.0, capacity: float = 0.5) -> Workload:
     """Four-node diamond A(0)->B(1)->D(3), A->C(2)->D with reverse links;

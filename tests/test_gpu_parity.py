@@ -354,6 +354,132 @@ def test_rollout_autograd_function_matches_backward():
     assert np.abs(g["alpha"]).max() > 0
 
 
+ALL_GROUPS = ("free_speed", "jam_density", "rates", "cap_mult", "beta", "cost", "alpha", "theta")
+
+
+def _link_invariants(w, s, scen=0):
+    """Properties that hold at any size: conservation, FIFO order, every agent
+    on the network within its link, and per link the agents on it equal its
+    entry sequence minus its cumulative outflow."""
+    st = s.state()
+    c = st["counters"][scen]
+    assert c["departed"] == c["on_net"] + c["exited"]
+    assert c["released"] >= c["departed"] and c["order_viol"] == 0
+    on = st["status"][scen] == oracle.ST_ON
+    assert int(on.sum()) == c["on_net"]
+    lk, ps = st["link"][scen][on], st["pos"][scen][on]
+    assert np.all(ps >= 0.0) and np.all(ps <= w.net.length[lk])
+    ls = s.link_state()
+    per_link = np.bincount(lk, minlength=w.net.n_links)
+    assert np.array_equal(ls["next_seq"][scen] - ls["E"][scen], per_link)
+    assert np.all(ls["B"][scen] <= 1.0 + 1e-12 + w.net.capacity * w.net.lanes * w.cfg.dt)
+
+
+def test_metro_full_size_in_bench_configuration():
+    """The 1M-agent metro workload (12k nodes, 35k links) at full size, in
+    the launch configuration the benchmark times (checkpoints every 60, the
+    autotuner's schedule chosen on the end-of-rollout state).  The full
+    1,800-step rollout is checked by invariants; the first 300 steps are
+    bit-exact against the oracle, and their gradients in every group match
+    the oracle's."""
+    w = W.metro()
+    T = w.cfg.steps
+    s = _sim(w, record=True, max_steps=T)
+    s.rollout()
+    _link_invariants(w, s)
+    s.autotune(probe_steps=30)
+    T0 = 300
+    s.reset()
+    s.step(T0)
+    o = Oracle(w, log=True)
+    o.run(T0)
+    _compare_state(o, s, ctx=f"metro after {T0} steps")
+    rng = np.random.default_rng(5)
+    cnt, _ = o.counts()
+    gQ = rng.normal(size=cnt.shape).astype(np.float32)
+    go = o.backward(gQ=gQ.astype(np.float64), gT=0.5)
+    gg = s.backward(gQ=gQ[None], gT=[0.5], groups=ALL_GROUPS)
+    for k in ALL_GROUPS:
+        _grad_close(go[k], gg[k][0], f"metro {k}")
+
+
+def test_grid_full_size_rollout_and_calibration_gradient():
+    """The 32x32 grid (3,968 links, 50k pool, 768 rate parameters, 400
+    detectors) over its full 1,800 steps: final state bit-exact against the
+    oracle and the gradient of the count loss against a ground truth drawn
+    with other rates, in every group."""
+    w = W.grid_rates()
+    truth = Oracle(w).run()
+    c_true, _ = truth.counts()
+    rng = np.random.default_rng(8)
+    rates = (w.dem.rates * rng.uniform(0.8, 1.25, w.dem.rates.shape)).astype(np.float32)
+    o = Oracle(w, log=True, params={"rates": rates}).run()
+    s = _sim(w, record=True, params={"rates": rates}).rollout()
+    _compare_state(o, s, ctx="grid full rollout")
+    _link_invariants(w, s)
+    cnt, _ = o.counts()
+    gQ = (2.0 * (cnt - c_true) / cnt.size).astype(np.float32)
+    go = o.backward(gQ=gQ.astype(np.float64))
+    gg = s.backward(gQ=gQ[None], groups=ALL_GROUPS)
+    assert np.abs(go["rates"]).max() > 0
+    for k in ALL_GROUPS:
+        _grad_close(go[k], gg[k][0], f"grid {k}")
+
+
+def test_kernel_limits_hub_parity():
+    """Largest cases of the kernels: a node with 64 merge candidates (8 in-links
+    of 8 lanes), rings far above 128 slots holding more agents than one
+    staging piece, four detectors on one link.  Forward bit-exact every 100
+    steps, then the gradients of the whole rollout in every group."""
+    w = W.hub()
+    o = Oracle(w)
+    s = _sim(w)
+    for t in range(100, w.cfg.steps + 1, 100):
+        o.run(100)
+        s.step(100)
+        _compare_state(o, s, ctx=f"hub t={t}")
+    _link_invariants(w, s)
+    o = Oracle(w, log=True).run()
+    r = _sim(w, record=True).rollout()
+    cnt, _ = o.counts()
+    gQ = np.random.default_rng(2).normal(size=cnt.shape).astype(np.float32)
+    go = o.backward(gQ=gQ.astype(np.float64), gT=0.1)
+    gg = r.backward(gQ=gQ[None], gT=[0.1], groups=ALL_GROUPS)
+    for k in ALL_GROUPS:
+        _grad_close(go[k], gg[k][0], f"hub {k}")
+
+
+def test_zero_agents():
+    """An empty demand: steps, observables and every gradient are zero."""
+    w = W.line(n_links=3, n_agents=0, steps=40)
+    s = _sim(w, record=True).rollout()
+    c = s.state()["counters"][0]
+    assert all(v == 0 for v in c.values())
+    cnt, ttt = s.observables()
+    assert np.all(cnt == 0) and np.all(ttt == 0)
+    g = s.backward(gT=[1.0], groups=("free_speed", "jam_density", "cap_mult", "beta", "alpha", "theta"))
+    assert all(np.all(v == 0) for v in g.values())
+
+
+def test_closed_links_hold_their_queues():
+    """Capacity multiplier 0 on a set of links: no token ever accrues, so no
+    transfer leaves them (agents whose destination is the link's head still
+    exit, which takes no token); state and every gradient match the oracle."""
+    w = W.random_small(12, nx=4, ny=4, n_agents=600, rates=True, steps=300)
+    rng = np.random.default_rng(12)
+    m = np.where(rng.uniform(size=w.net.n_links) < 0.25, 0.0, 1.0).astype(np.float32)
+    o = Oracle(w, log=True, params={"cap_mult": m}).run()
+    s = _sim(w, record=True, params={"cap_mult": m}).rollout()
+    _compare_state(o, s, ctx="closed links")
+    assert np.all(s.link_state()["B"][0][m == 0] == 0.0)
+    cnt, _ = o.counts()
+    gQ = rng.normal(size=cnt.shape).astype(np.float32)
+    go = o.backward(gQ=gQ.astype(np.float64), gT=0.2)
+    gg = s.backward(gQ=gQ[None], gT=[0.2], groups=ALL_GROUPS)
+    for k in ALL_GROUPS:
+        _grad_close(go[k], gg[k][0], f"closed {k}")
+
+
 def test_autotune_restores_state_and_caches(tmp_path):
     """The autotuner probes from the live state and puts it back: a rollout
     tuned half-way equals an untuned one (values and gradients), and a second

@@ -709,3 +709,29 @@ def test_merge_priority_gradient_closed_form(alpha, seed):
     assert g["alpha"][win] == pytest.approx(expect, rel=1e-9)
     assert g["alpha"][lose] == pytest.approx(-expect, rel=1e-9)
     assert np.all(g["beta"] == 0.0) and np.all(g["cost"] == 0.0)
+
+
+def test_hub_workload_reaches_the_kernel_limits():
+    """The hub workload drives the sizes the GPU kernels are built around:
+    a step in which all 64 head lanes of the hub's eight 8-lane in-links hold
+    a head (one full wavefront of merge candidates), more than 1,300 agents
+    on the long link 1 -> 0 (more than two staging pieces of its reverse),
+    and four detectors on that link; conservation holds throughout."""
+    w = W.hub()
+    net = w.net
+    assert np.count_nonzero(net.detector_link == 1) == 4
+    inl = [j for j in range(net.n_links) if net.head[j] == 0]
+    assert sum(int(net.lanes[j]) for j in inl) == 64
+    o = Oracle(w)
+    full_steps, most_on_1 = 0, 0
+    for _ in range(w.cfg.steps):
+        o.run(1)
+        st = o.state()
+        on = st["status"] == ST_ON
+        lk, ps = st["link"][on], st["pos"][on]
+        heads = sum(min(int(np.sum(ps[lk == j] >= net.length[j] - 0.01)), int(net.lanes[j])) for j in inl)
+        full_steps += heads == 64
+        most_on_1 = max(most_on_1, int(np.sum(lk == 1)))
+        c = o.counters()
+        assert c["departed"] == c["on_net"] + c["exited"]
+    assert full_steps > 0 and most_on_1 > 1300
