@@ -44,7 +44,12 @@
  *  - departures: origin FIFO queues play the paper's virtual inflow links;
  *    in departure-rate mode agents are released when the integrated rate
  *    crosses their queue index + 1; the gradient reaches the rates through a
- *    departure-time graft on the entry position.
+ *    departure-time graft on the entry position;
+ *  - straight-through node model: the relaxed route and merge weights enter
+ *    the transfer update with value zero and the softmax's gradient; a merge
+ *    with k winners is k sequential softmax stages over the candidates not
+ *    yet picked; the merge score is alpha_from times the chooser's relaxed
+ *    weight of the target link, plus its Gumbel noise.
  */
 #include <math.h>
 #include <stdint.h>
