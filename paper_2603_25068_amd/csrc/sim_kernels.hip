@@ -168,9 +168,11 @@ __device__ __forceinline__ void add_counters(Dev &d, const Group<G> &g, int s, i
 //   step's idle cap min(B, 1) is applied here, before the accrual), detector
 //   crossings, order check; records the heads (agent, destination) for the
 //   node phase.
-// Links are split by ring capacity: small rings (at most kSmallRing slots,
-// internal ids [0, lk_n_small)) are served by G lanes, the others by a whole
-// wavefront.  A segment is staged into LDS
+// Links are split by ring capacity into three contiguous id ranges (at most
+// kSmallRing slots, at most kMidRing, larger), served by G, max(G, 16) and
+// max(G, 32) lanes, so that a launch holds about as many waves as the chip
+// keeps resident.  Each lane group gets an equal share of the block's LDS.
+// A segment is staged into LDS
 // (a piece of up to bufcap ranks plus the leader halo) with all loads in
 // flight at once, then updated from that snapshot: every input is a time-t
 // position, so the update is a pure gather.  Pieces of very long segments
@@ -326,31 +328,62 @@ __device__ __forceinline__ void stamp_end(const Dev &d, unsigned long long t0)
     }
 }
 
-// blocks [0, small_blocks): G lanes per small segment; the rest: one wavefront per big segment
+// Ring classes as block roles: class c takes lane groups of ring_lanes(c, G); the first two roles'
+// block counts are multiples of 8, so every role keeps the XCD pattern.
+__host__ __device__ __forceinline__ constexpr int ring_lanes(int c, int G)
+{
+    return c == 0 ? G : (c == 1 ? (G > 16 ? G : 16) : (G > 32 ? G : 32));
+}
+__host__ __device__ __forceinline__ int ring_role_blocks(int items, int lanes, bool last)
+{
+    const int per = 256 / lanes;
+    const int b = (items + per - 1) / per;
+    return last ? b : ((b + 7) & ~7);
+}
+__host__ __device__ __forceinline__ int ring_blocks(const Dev &d, int G)
+{
+    return ring_role_blocks(d.S * d.lc_n[0], ring_lanes(0, G), false) +
+           ring_role_blocks(d.S * d.lc_n[1], ring_lanes(1, G), false) +
+           ring_role_blocks(d.S * d.lc_n[2], ring_lanes(2, G), true);
+}
+// block b of the launch -> (class, block within the class, blocks of the class)
+__device__ __forceinline__ int ring_role(const Dev &d, int G, int &b, int &nblk)
+{
+    b = (int)blockIdx.x;
+    const int b0 = ring_role_blocks(d.S * d.lc_n[0], ring_lanes(0, G), false);
+    if (b < b0) { nblk = b0; return 0; }
+    b -= b0;
+    const int b1 = ring_role_blocks(d.S * d.lc_n[1], ring_lanes(1, G), false);
+    if (b < b1) { nblk = b1; return 1; }
+    b -= b1;
+    nblk = (int)gridDim.x - b0 - b1;
+    return 2;
+}
+
+template <int GC>
+__device__ __forceinline__ void link_role(Dev &d, int c, int b, int nblk, int t, int sample_b, int tape_k, float *lds)
+{
+    const Group<GC> g;
+    constexpr int per = 256 / GC;
+    constexpr int sbuf = 4 * kBigLds / per;
+    const int n = d.S * d.lc_n[c];
+    const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / GC;
+    if (item >= n) return;
+    const int s = item / d.lc_n[c];
+    const int first = c == 0 ? 0 : (c == 1 ? d.lc_n[0] : d.lc_n[0] + d.lc_n[1]);
+    const int seg = s * d.L + first + (item - s * d.lc_n[c]);
+    link_segment<GC>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
+}
+
 template <int G>
 __device__ __forceinline__ void link_launch(Dev &d, int t, int sample_b, int tape_k)
 {
     __shared__ float lds[4 * kBigLds];
-    constexpr int per = 256 / G;
-    constexpr int sbuf = 8 * G + kMaxLanes;
-    static_assert(per * sbuf <= 4 * kBigLds, "small-segment staging exceeds LDS");
-    const int small_items = d.S * d.lk_n_small;
-    const int small_blocks = ((small_items + per - 1) / per + 7) & ~7;   // a multiple of 8: roles keep the XCD pattern
-    if ((int)blockIdx.x < small_blocks) {
-        const Group<G> g;
-        const int item = xcd_remap(blockIdx.x, small_blocks) * per + (int)threadIdx.x / G;
-        if (item >= small_items) return;
-        const int s = item / d.lk_n_small;
-        const int seg = s * d.L + (item - s * d.lk_n_small);
-        link_segment<G>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
-    } else {
-        const Group<64> g;
-        const int item = xcd_remap((int)blockIdx.x - small_blocks, (int)gridDim.x - small_blocks) * 4 + (int)threadIdx.x / 64;
-        if (item >= d.S * d.lk_n_big) return;
-        const int s = item / d.lk_n_big;
-        const int seg = s * d.L + d.lk_n_small + (item - s * d.lk_n_big);
-        link_segment<64>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / 64) * kBigLds, kBigLds);
-    }
+    int b, nblk;
+    const int c = ring_role(d, G, b, nblk);
+    if (c == 0) link_role<ring_lanes(0, G)>(d, 0, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 1) link_role<ring_lanes(1, G)>(d, 1, b, nblk, t, sample_b, tape_k, lds);
+    else link_role<ring_lanes(2, G)>(d, 2, b, nblk, t, sample_b, tape_k, lds);
 }
 
 template <int G>
@@ -794,8 +827,7 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
 // t (a ring keeps `lanes` slots free), so concurrent segments do not race.
 // init = 1: adj_ring = dL/dx(T) at the final state (no step).
 // ---------------------------------------------------------------------------
-constexpr int kRevSmall = 8;        // staging of a small segment: kRevSmall * G >= kSmallRing slots
-constexpr int kRevBigLds = 1280;    // LDS words per wavefront for big segments (two arrays)
+constexpr int kRevBigLds = 1280;    // LDS words per wavefront (two arrays), split evenly among its lane groups
 
 template <int G>
 __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
@@ -928,30 +960,31 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     }
 }
 
+template <int GC>
+__device__ __forceinline__ void reverse_role(Dev &d, int c, int b, int nblk, int t, int tape_k, int init, float *lds)
+{
+    const Group<GC> g;
+    constexpr int per = 256 / GC;
+    constexpr int sbuf = 4 * kRevBigLds / per;
+    static_assert(sbuf / 2 > 2 * kMaxLanes + GC, "reverse staging piece too small");
+    const int n = d.S * d.lc_n[c];
+    const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / GC;
+    if (item >= n) return;
+    const int s = item / d.lc_n[c];
+    const int first = c == 0 ? 0 : (c == 1 ? d.lc_n[0] : d.lc_n[0] + d.lc_n[1]);
+    const int seg = s * d.L + first + (item - s * d.lc_n[c]);
+    reverse_segment<GC>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
+}
+
 template <int G>
 __device__ __forceinline__ void reverse_launch(Dev &d, int t, int tape_k, int init)
 {
     __shared__ float lds[4 * kRevBigLds];
-    constexpr int per = 256 / G;
-    constexpr int sbuf = 2 * (kRevSmall * G + 2 * kMaxLanes);
-    static_assert(per * sbuf <= 4 * kRevBigLds, "small-segment staging exceeds LDS");
-    const int small_items = d.S * d.rv_n_small;
-    const int small_blocks = ((small_items + per - 1) / per + 7) & ~7;   // a multiple of 8: roles keep the XCD pattern
-    if ((int)blockIdx.x < small_blocks) {
-        const Group<G> g;
-        const int item = xcd_remap(blockIdx.x, small_blocks) * per + (int)threadIdx.x / G;
-        if (item >= small_items) return;
-        const int s = item / d.rv_n_small;
-        const int seg = s * d.L + (item - s * d.rv_n_small);
-        reverse_segment<G>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / G) * sbuf, sbuf);
-    } else {
-        const Group<64> g;
-        const int item = xcd_remap((int)blockIdx.x - small_blocks, (int)gridDim.x - small_blocks) * 4 + (int)threadIdx.x / 64;
-        if (item >= d.S * d.rv_n_big) return;
-        const int s = item / d.rv_n_big;
-        const int seg = s * d.L + d.rv_n_small + (item - s * d.rv_n_big);
-        reverse_segment<64>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / 64) * kRevBigLds, kRevBigLds);
-    }
+    int b, nblk;
+    const int c = ring_role(d, G, b, nblk);
+    if (c == 0) reverse_role<ring_lanes(0, G)>(d, 0, b, nblk, t, tape_k, init, lds);
+    else if (c == 1) reverse_role<ring_lanes(1, G)>(d, 1, b, nblk, t, tape_k, init, lds);
+    else reverse_role<ring_lanes(2, G)>(d, 2, b, nblk, t, tape_k, init, lds);
 }
 
 template <int G>
@@ -1434,12 +1467,6 @@ int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int64_t waves) { return (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock); }
 
-static inline int class_blocks(int S, int n_small, int n_big, int G)
-{
-    const int per = 256 / G;
-    return ((((S * n_small + per - 1) / per) + 7) & ~7) + (S * n_big + 3) / 4;
-}
-
 // one wavefront per launch record (offset, waves): first start and last end over its waves
 __global__ __launch_bounds__(256) void k_stamp_reduce(const int64_t *off, const int32_t *waves, int n,
                                                       const unsigned long long *st, unsigned long long *out)
@@ -1467,7 +1494,7 @@ void launch_stamp_reduce(const int64_t *off, const int32_t *waves, int n, const 
 
 int link_blocks(const Dev &d)
 {
-    return class_blocks(d.S, d.lk_n_small, d.lk_n_big, d.g_link);
+    return std::max(1, ring_blocks(d, d.g_link));
 }
 int node_blocks(const Dev &d)
 {
@@ -1476,7 +1503,7 @@ int node_blocks(const Dev &d)
 }
 int reverse_blocks(const Dev &d)
 {
-    return class_blocks(d.S, d.rv_n_small, d.rv_n_big, d.g_rev);
+    return std::max(1, ring_blocks(d, d.g_rev));
 }
 
 template <typename K, typename... A>
@@ -1488,10 +1515,10 @@ static void launch(K kernel, int blocks, hipStream_t st, A... args)
 void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 {
     switch (d.g_link) {
-    case 8: launch(k_link<8>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 8), st, d, t, sample_b, tape_k); break;
-    case 16: launch(k_link<16>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 16), st, d, t, sample_b, tape_k); break;
-    case 32: launch(k_link<32>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 32), st, d, t, sample_b, tape_k); break;
-    default: launch(k_link<64>, class_blocks(d.S, d.lk_n_small, d.lk_n_big, 64), st, d, t, sample_b, tape_k); break;
+    case 8: launch(k_link<8>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    case 16: launch(k_link<16>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    case 32: launch(k_link<32>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    default: launch(k_link<64>, link_blocks(d), st, d, t, sample_b, tape_k); break;
     }
 }
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
@@ -1507,10 +1534,10 @@ void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 void launch_reverse(const Dev &d, int t, int tape_k, int init, hipStream_t st)
 {
     switch (d.g_rev) {
-    case 8: launch(k_reverse<8>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 8), st, d, t, tape_k, init); break;
-    case 16: launch(k_reverse<16>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 16), st, d, t, tape_k, init); break;
-    case 32: launch(k_reverse<32>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 32), st, d, t, tape_k, init); break;
-    default: launch(k_reverse<64>, class_blocks(d.S, d.rv_n_small, d.rv_n_big, 64), st, d, t, tape_k, init); break;
+    case 8: launch(k_reverse<8>, reverse_blocks(d), st, d, t, tape_k, init); break;
+    case 16: launch(k_reverse<16>, reverse_blocks(d), st, d, t, tape_k, init); break;
+    case 32: launch(k_reverse<32>, reverse_blocks(d), st, d, t, tape_k, init); break;
+    default: launch(k_reverse<64>, reverse_blocks(d), st, d, t, tape_k, init); break;
     }
 }
 void launch_ste(const Dev &d, int t, int tape_k, hipStream_t st)
