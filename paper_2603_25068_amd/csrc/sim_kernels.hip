@@ -109,6 +109,7 @@ __device__ __forceinline__ float gumbel_fast(uint32_t w)
     return -__logf(y);
 }
 constexpr double kFastMargin = 1e-3;
+constexpr int kChoiceChunk = 16;   // out-links whose route entries and noise are requested together
 
 // ---------------------------------------------------------------------------
 // Lane groups: a work item (segment or node) is served by G consecutive
@@ -407,13 +408,21 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 //   out-link ring (SI-B eq. transfer; the graft itself lives in the adjoint).
 // Candidate lanes: the heads of in-link q take lanes [off_q, off_q + lanes_q)
 // (a per-node table gives each lane its in-link and head rank); then origins.
-// Out-link lanes k < out-degree hold the out-link's data, broadcast to the
-// candidates by shuffles; four shortest-time lookups are in flight at once.
+// Out-link lanes k < out-degree load the out-link's data and publish it in the
+// group's LDS table; candidates publish (key, choice, agent) the same way, so
+// choice, merge ranks and entry order are plain LDS reads.  A chooser requests
+// all route entries and Philox words of 16 out-links before its first score.
 // Per-node link lists are padded node-major tables, so every lane finds its
 // link in the first load.  `item` only spreads the counter atomics.
 // ---------------------------------------------------------------------------
+// Per-group LDS tables of the node phase: what a lane group's out-link lanes and candidate lanes
+// publish for the others, read with plain LDS loads (no cross-lane shuffles inside branchy loops).
+struct OutRec { double util; int om, head, slots, tail, base, cap; };   // out-link k of the node
+struct CandRec { double key; int ch, ag; };                               // candidate lane e
+
 template <int G>
-__device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k)
+__device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k,
+                                          OutRec *orc, CandRec *crc, int *ent)
 {
     const int gl = g.gl;
     const int maxl = d.maxl;
@@ -537,7 +546,47 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const bool exiting = ag >= 0 && from >= 0 && dst == v;
     const bool chooser = ag >= 0 && !exiting;
     const double *route = d.route + rbase_v + (int64_t)didx * dego;   // this head's row
-    // one pass per out-link block of 4: shortest times, Philox words, scores V + g
+    // merge-key words: independent of the choice, drawn first so they overlap its loads
+    uint32_t wm[4] = {0u, 0u, 0u, 0u};
+    if (ag >= 0) draw4(seed, ag, t, 1, 0, wm);
+    if (gl < dego) orc[gl] = OutRec{outil, om, ohead, oslots, otail, obase, ocap};
+    wave_lds_sync();
+    // fast pass on single-precision noise: for each chunk of out-links, every route entry and
+    // Philox word of the chunk is requested before the first score, so one memory round trip
+    // serves the chunk
+    auto choice_fast = [&](double &best, double &second, int &arg, int &argk) {
+        best = -INFINITY;
+        second = -INFINITY;
+        arg = CH_STUCK;
+        argk = 0;
+        for (int c0 = 0; c0 < dego; c0 += kChoiceChunk) {
+            double rt[kChoiceChunk];
+            uint32_t w[kChoiceChunk];
+#pragma unroll
+            for (int q = 0; q < kChoiceChunk; ++q) rt[q] = (chooser && c0 + q < dego) ? route[c0 + q] : INFINITY;
+#pragma unroll
+            for (int b = 0; b < kChoiceChunk / 4; ++b) {
+                if (chooser && c0 + 4 * b < dego) {
+                    draw4(seed, ag, t, 0, (c0 >> 2) + b, w + 4 * b);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) w[4 * b + q] = 0u;
+                }
+            }
+            if (!chooser) continue;
+#pragma unroll
+            for (int q = 0; q < kChoiceChunk; ++q) {
+                if (c0 + q >= dego) break;
+                const OutRec o = orc[c0 + q];
+                if (!d.allow_uturn && from >= 0 && o.head == ftail) continue;
+                if (!(rt[q] < INFINITY)) continue;
+                const double sc = o.util - d.theta * rt[q] + (double)gumbel_fast(w[q]);
+                if (sc > best) { second = best; best = sc; arg = o.om; argk = c0 + q; }
+                else if (sc > second) second = sc;
+            }
+        }
+    };
+    // one pass per out-link block of 4 (the double-precision redo)
     auto choice_pass = [&](bool on, bool exact, double &best, double &second, int &arg, int &argk) {
         best = -INFINITY;
         second = -INFINITY;
@@ -574,7 +623,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     };
     double best, second;
     int arg, argk;   // chosen link and its index among the node's out-links (the lane holding its data)
-    choice_pass(chooser, false, best, second, arg, argk);
+    choice_fast(best, second, arg, argk);
     // lanes whose winner is not clear on the fast noise redo the choice in double precision
     const bool redo = chooser && second > -INFINITY && best - second < kFastMargin;
     if (g.count(redo)) {
@@ -591,44 +640,37 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         ch = CH_EXIT;
     }
     // merge key alpha_from + g' on the fast noise; exact below where two keys for one link are close
-    uint32_t wm[4] = {0u, 0u, 0u, 0u};
     double key = 0.0;
-    if (ag >= 0) {
-        draw4(seed, ag, t, 1, 0, wm);
-        key = alpha + (double)gumbel_fast(wm[0]);
-    }
+    if (ag >= 0) key = alpha + (double)gumbel_fast(wm[0]);
 
     // ---- merge: rank among candidates wanting the same link ----
-    // the loops below visit only lanes that hold a candidate (group-uniform mask)
-    // rank among the choosers of the same out-link: one ballot per out-link, pairwise key
-    // comparisons only where at least two candidates want it
+    // every candidate lane publishes (key, choice, agent); a chooser counts the candidates of its
+    // own out-link that precede it in key order
     int rank = 0, close = 0;
     bool knear = false;
+    crc[gl] = CandRec{key, ag >= 0 ? ch : CH_NONE, ag};
+    wave_lds_sync();
     auto rank_pass = [&]() {
         rank = 0;
         close = 0;
-        for (int k = 0; k < dego; ++k) {
-            const int omk = __shfl(om, k, G);
-            const unsigned long long mk = g.mask(ag >= 0 && ch == omk);
-            if (__popcll(mk) < 2) continue;
-            for (unsigned long long mm = mk; mm; mm &= mm - 1) {
-                const int src = __ffsll((long long)mm) - 1;
-                const double k2 = __shfl(key, src, G);
-                const int a2 = __shfl(ag, src, G);
-                if (ag >= 0 && ch == omk && src != gl) {
-                    if (k2 > key || (k2 == key && a2 < ag)) ++rank;
-                    else if (key - k2 < 1e-12 * (1.0 + fabs(key))) close = 1;
-                    knear |= fabs(k2 - key) < kFastMargin;
-                }
-            }
+        if (ag < 0 || ch < 0) return;
+        for (int e = 0; e < nc; ++e) {
+            const CandRec o = crc[e];
+            if (e == gl || o.ch != ch) continue;
+            if (o.key > key || (o.key == key && o.ag < ag)) ++rank;
+            else if (key - o.key < 1e-12 * (1.0 + fabs(key))) close = 1;
+            knear |= fabs(o.key - key) < kFastMargin;
         }
     };
     rank_pass();
     if (g.count(knear)) {   // keys of competing candidates too close for the fast noise: all exact
         if (ag >= 0) key = alpha + gumbel_of(wm[0]);
+        wave_lds_sync();
+        crc[gl].key = key;
+        wave_lds_sync();
         rank_pass();
     }
-    const int sl = __shfl(oslots, min(argk, G - 1), G);
+    const int sl = ch >= 0 ? orc[argk].slots : 0;
     const int won = (ch >= 0) && rank < sl;
     if (ch >= 0) inc[CTR_TIES] += close;
 
@@ -659,22 +701,26 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     else passed = (origin >= 0 && ag >= 0 && won);
 
     // ---- entrants per out-link (lane k < dego counts link k's) and each entrant's place in key order ----
+    ent[gl] = (passed && ch >= 0) ? ch : CH_NONE;
+    wave_lds_sync();
     int nent = 0, erank = 0;
-    for (int k = 0; k < dego; ++k) {
-        const int omk = __shfl(om, k, G);
-        const unsigned long long pm = g.mask(passed && ch == omk);
-        if (gl == k) nent = __popcll(pm);
-        if (__popcll(pm) < 2) continue;
-        for (unsigned long long mm = pm; mm; mm &= mm - 1) {
-            const int src = __ffsll((long long)mm) - 1;
-            const double k2 = __shfl(key, src, G);
-            const int a2 = __shfl(ag, src, G);
-            if (passed && ch == omk && src != gl && (k2 > key || (k2 == key && a2 < ag))) ++erank;
+    if (gl < dego)
+        for (int e = 0; e < nc; ++e) nent += ent[e] == om;
+    if (passed && ch >= 0) {
+        for (int e = 0; e < nc; ++e) {
+            if (e == gl || ent[e] != ch) continue;
+            const CandRec o = crc[e];
+            if (o.key > key || (o.key == key && o.ag < ag)) ++erank;
         }
     }
     if (gl < dego && nent) d.rtail[sL + om] = otail + nent;
-    const int ksrc = min(argk, G - 1);
-    const int tbase = __shfl(otail, ksrc, G), rbase = __shfl(obase, ksrc, G), rcap = __shfl(ocap, ksrc, G);
+    int tbase = 0, rbase = 0, rcap = 1;
+    if (ch >= 0) {
+        const OutRec o = orc[argk];
+        tbase = o.tail;
+        rbase = o.base;
+        rcap = o.cap;
+    }
     const int64_t ga = (int64_t)s * d.N + (ag >= 0 ? ag : 0);
     const int64_t slot = (int64_t)s * d.ring_total + rbase + (tbase + erank) % rcap;
     // admission graft: a head leaving on a token carries the token's availability
@@ -744,7 +790,8 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
 // four classes as block roles, each role's block range remapped so that
 // neighbouring nodes share an XCD.
 template <int G>
-__device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t, int tape_k)
+__device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t, int tape_k, OutRec *orc,
+                                          CandRec *crc, int *ent)
 {
     const Group<G> g;
     const int per = 256 / G;
@@ -752,7 +799,8 @@ __device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t,
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / G;
     if (item >= n) return true;
     const int s = item / d.nd_n[c];
-    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k);
+    const int o = (int)threadIdx.x & ~(G - 1);
+    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k, orc + o, crc + o, ent + o);
     return true;
 }
 
@@ -765,17 +813,20 @@ __host__ __device__ __forceinline__ int node_role_blocks(int n, int G, bool last
 
 __device__ __forceinline__ void node_launch(Dev &d, int t, int tape_k)
 {
+    __shared__ OutRec orc[256];
+    __shared__ CandRec crc[256];
+    __shared__ int ent[256];
     int b = (int)blockIdx.x;
     const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
-    if (b < b8) { node_role<8>(d, 0, b, b8, t, tape_k); return; }
+    if (b < b8) { node_role<8>(d, 0, b, b8, t, tape_k, orc, crc, ent); return; }
     b -= b8;
     const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
-    if (b < b16) { node_role<16>(d, 1, b, b16, t, tape_k); return; }
+    if (b < b16) { node_role<16>(d, 1, b, b16, t, tape_k, orc, crc, ent); return; }
     b -= b16;
     const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
-    if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k); return; }
+    if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k, orc, crc, ent); return; }
     b -= b32;
-    node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k);
+    node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc, ent);
 }
 
 __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
