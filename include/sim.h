@@ -222,6 +222,15 @@ int sim_time(const sim_t *h, int32_t *t);
  * ctr [n x 4] with keys key [n x 2], host arrays; out [n x 4] host. */
 int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
 
+/* The single-precision Gumbel(0,1) transform the kernels take their fast
+ * route-choice and merge decisions on, evaluated on the device: for each of n
+ * host words w, g = -log(-log U) with U = ((w >> 8) + 1/2) 2^-24 (the same U
+ * as the double-precision draw).  out [n] host floats.  A decision is
+ * taken on these values only when it wins by more than twice their largest
+ * error; otherwise it is recomputed in double precision.  SIM_EINVAL for
+ * n < 0 or NULL arrays. */
+int sim_gumbel_fast(sim_t *h, int32_t n, const uint32_t *words, float *out);
+
 /* Segmented sort of n keys (segment id, position, sequence) into segment
  * order, position descending, sequence ascending; writes the permutation
  * perm [n] and segment offsets seg_off [n_segments + 1].  Device pointers,

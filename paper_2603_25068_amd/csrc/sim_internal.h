@@ -144,6 +144,7 @@ void launch_stamp_reduce(const int64_t *off, const int32_t *waves, int n, const 
                          unsigned long long *out, hipStream_t s);
 void launch_rate_grad(const Dev &d, float *g_rates, hipStream_t st);
 void launch_philox(int n, const uint32_t *ctr, const uint32_t *key, uint32_t *out, hipStream_t st);
+void launch_gumbel_fast(int n, const uint32_t *w, float *out, hipStream_t st);
 int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
                    int32_t *perm, int32_t *seg_off, int32_t *scratch, hipStream_t st);
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,

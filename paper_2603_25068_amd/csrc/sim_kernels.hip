@@ -93,8 +93,10 @@ __device__ __forceinline__ double gumbel_of(uint32_t w)
 // For U >= 1/2, 1 - U = (2^25 - 2k - 1) 2^-25 is an odd integer below 2^24
 // times a power of two, exact in float, and y = -log1p(-(1 - U)) keeps full
 // relative accuracy however close U is to 1.  The outer log then adds a few
-// ulp of |g| <= 18, so |g - g_double| < 1e-5.  A decision is taken on these
-// values only when it wins by kFastMargin (100 times that); otherwise it is
+// ulp of |g| <= 18, so |g - g_double| < 1e-5 (checked exhaustively over all
+// 2^24 values of k).  A decision compares two scores, each within that bound
+// of its double value, and is taken on them only when it wins by kFastMargin
+// (five times the largest possible error of the difference); otherwise it is
 // recomputed with gumbel_of, so every decision equals the double-precision one.
 __device__ __forceinline__ float gumbel_fast(uint32_t w)
 {
@@ -108,7 +110,7 @@ __device__ __forceinline__ float gumbel_fast(uint32_t w)
     }
     return -__logf(y);
 }
-constexpr double kFastMargin = 1e-3;
+constexpr double kFastMargin = 1e-4;
 constexpr int kChoiceChunk = 16;   // out-links whose route entries and noise are requested together
 
 // ---------------------------------------------------------------------------
@@ -1635,6 +1637,16 @@ void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st)
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_d2f, dim3((int)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+}
+__global__ void k_gumbel_fast(int n, const uint32_t *w, float *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = gumbel_fast(w[i]);
+}
+void launch_gumbel_fast(int n, const uint32_t *w, float *out, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gumbel_fast, dim3((n + 255) / 256), dim3(256), 0, st, n, w, out);
 }
 void launch_philox(int n, const uint32_t *ctr, const uint32_t *key, uint32_t *out, hipStream_t st)
 {

@@ -1707,6 +1707,24 @@ int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, ui
     });
 }
 
+int sim_gumbel_fast(sim_t *h, int32_t n, const uint32_t *words, float *out)
+{
+    return guarded(h, [&] {
+        if (n < 0 || (n > 0 && (!words || !out))) fail(SIM_EINVAL, "bad gumbel arrays");
+        if (n == 0) return;
+        uint32_t *dw = nullptr;
+        float *dout = nullptr;
+        HIPCHK(hipMalloc(&dw, (size_t)n * 4));
+        HIPCHK(hipMalloc(&dout, (size_t)n * 4));
+        HIPCHK(hipMemcpyAsync(dw, words, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+        sim::launch_gumbel_fast(n, dw, dout, h->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, dout, (size_t)n * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        (void)hipFree(dw); (void)hipFree(dout);
+    });
+}
+
 int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos, const int32_t *seq,
                 int32_t *perm, int32_t *seg_off)
 {

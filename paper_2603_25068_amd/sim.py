@@ -86,6 +86,7 @@ def lib():
         "sim_get_dist": ([vp, vp, vp], C.c_int),
         "sim_time": ([vp, vp], C.c_int),
         "sim_philox": ([vp, i32, vp, vp, vp], C.c_int),
+        "sim_gumbel_fast": ([vp, i32, vp, vp], C.c_int),
         "sim_segsort": ([vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
         "sim_set_schedule": ([vp, C.c_int, C.c_int, C.c_int], C.c_int),
         "sim_get_schedule": ([vp, vp, vp, vp], C.c_int),
@@ -116,7 +117,7 @@ def lib():
 def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
-            "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_segsort",
+            "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_gumbel_fast", "sim_segsort",
             "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
             "sim_set_full_state",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
@@ -345,6 +346,12 @@ class Simulator:
         k = np.ascontiguousarray(key, np.uint32).reshape(-1, 2)
         out = np.zeros_like(c)
         self._chk(self._L.sim_philox(self._h, c.shape[0], _p(c), _p(k), _p(out)))
+        return out
+
+    def gumbel_fast(self, words):
+        w = np.ascontiguousarray(words, np.uint32).reshape(-1)
+        out = np.zeros(w.shape, np.float32)
+        self._chk(self._L.sim_gumbel_fast(self._h, w.size, _p(w), _p(out)))
         return out
 
     def segsort(self, seg, pos, seq, n_segments: int):

@@ -551,3 +551,21 @@ def test_full_state_round_trip():
     p.step(6)
     q.step(6)
     assert np.array_equal(p.state()["pos"], q.state()["pos"])
+
+
+def test_fast_gumbel_error_bound_exhaustive():
+    """The single-precision Gumbel transform behind the fast decisions,
+    against -log(-log U) in double for every one of the 2^24 values of
+    U = (k + 1/2) 2^-24 it can take: the error stays below 1e-5, so a
+    difference of two scores is off by less than 2e-5, five times below the
+    1e-4 margin a fast decision must win by."""
+    w = W.line(n_links=1, n_agents=1, steps=1)
+    s = _sim(w)
+    k = np.arange(1 << 24, dtype=np.uint64)
+    words = ((k << np.uint64(8)) | np.uint64(0x5A)).astype(np.uint32)
+    g32 = s.gumbel_fast(words).astype(np.float64)
+    u = (k.astype(np.float64) + 0.5) * 2.0 ** -24
+    g64 = -np.log(-np.log(u))
+    err = np.abs(g32 - g64)
+    assert np.all(np.isfinite(g32))
+    assert err.max() < 1e-5, f"max error {err.max():.3g} at k={int(err.argmax())}"
