@@ -137,7 +137,9 @@ const char *sim_last_error(const sim_t *h);
 /* Set one parameter group for all scenarios: values [S x n] scenario-major,
  * n = n_links (per-link groups) or n_origins*n_rate_bins (rates).  Takes
  * effect from the next step; SIM_P_KAPPA must keep dn/kappa >= the jam
- * spacing the link rings were sized for (SIM_EINVAL otherwise). */
+ * spacing the link rings were sized for (SIM_EINVAL otherwise).  After
+ * t = 0 it ends a recording: the rollout so far was made under other
+ * parameters, so sim_backward needs a new one from t = 0 (SIM_ESTATE). */
 int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_device);
 
 /* Back to t = 0: empty network, all agents waiting, counters, buckets and

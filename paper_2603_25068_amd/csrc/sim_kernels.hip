@@ -202,7 +202,7 @@ __device__ __forceinline__ float cf_update(float x, float xl, bool has_leader, f
     return (xn > Lj) ? Lj : xn;
 }
 
-template <int G>
+template <int G, bool TAPE>
 __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg, int t, int sample_b, int tape_k,
                                              float *buf, int bufcap)
 {
@@ -233,7 +233,7 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
         if (sample_b >= 0) Ev = d.E[seg];
     }
     int64_t tb = -1;
-    if (tape_k >= 0) {
+    if (TAPE) {   // a recording step (tape_k >= 0)
         tb = (int64_t)tape_k * d.S * d.ring_total + base;
         if (gl == 0) {
             d.tape_head[(int64_t)tape_k * d.S * d.L + seg] = h0;
@@ -254,17 +254,27 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     for (int hi = n; hi > 0; hi -= piece) {
         const int lo = max(0, hi - piece);
         const int slo = max(0, lo - ln);
-        // stage ranks [slo, hi): four loads in flight per lane per round
+        // stage ranks [slo, hi): four loads in flight per lane per round; a recording replay also
+        // copies the time-t position and agent of ranks [lo, hi) to the tape here, with those loads
         for (int r = slo + gl; r < hi; r += 4 * G) {
             float v4[4];
+            int a4[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int rr = r + q * G;
                 v4[q] = rr < hi ? d.ring_pos[base + slot_of(rr)] : 0.f;
+                a4[q] = (TAPE && rr >= lo && rr < hi) ? d.ring_agent[base + slot_of(rr)] : 0;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (r + q * G < hi) buf[r + q * G - slo] = v4[q];
+            for (int q = 0; q < 4; ++q) {
+                const int rr = r + q * G;
+                if (rr >= hi) continue;
+                buf[rr - slo] = v4[q];
+                if (TAPE && rr >= lo) {
+                    d.tape_pos[tb + slot_of(rr)] = v4[q];
+                    d.tape_agent[tb + slot_of(rr)] = a4[q];
+                }
+            }
         }
         wave_lds_sync();
         float prev_last = INFINITY;
@@ -277,14 +287,7 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
                 if (r >= ln) xl = buf[r - ln - slo];
             }
             const float xh = cf_update(x, xl, r >= ln, vf, sp, Lj);
-            if (v) {
-                const int sl = slot_of(r);
-                if (tb >= 0) {
-                    d.tape_pos[tb + sl] = x;
-                    d.tape_agent[tb + sl] = d.ring_agent[base + sl];
-                }
-                d.ring_pos[base + sl] = xh;
-            }
+            if (v) d.ring_pos[base + slot_of(r)] = xh;
             nh += g.count(v && xh >= thr);
             nocc += g.count(v && xh <= sp);
 #pragma unroll
@@ -363,7 +366,7 @@ __device__ __forceinline__ int ring_role(const Dev &d, int G, int &b, int &nblk)
     return 2;
 }
 
-template <int GC>
+template <int GC, bool TAPE>
 __device__ __forceinline__ void link_role(Dev &d, int c, int b, int nblk, int t, int sample_b, int tape_k, float *lds)
 {
     const Group<GC> g;
@@ -375,25 +378,25 @@ __device__ __forceinline__ void link_role(Dev &d, int c, int b, int nblk, int t,
     const int s = item / d.lc_n[c];
     const int first = c == 0 ? 0 : (c == 1 ? d.lc_n[0] : d.lc_n[0] + d.lc_n[1]);
     const int seg = s * d.L + first + (item - s * d.lc_n[c]);
-    link_segment<GC>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
+    link_segment<GC, TAPE>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
 }
 
-template <int G>
+template <int G, bool TAPE>
 __device__ __forceinline__ void link_launch(Dev &d, int t, int sample_b, int tape_k)
 {
     __shared__ float lds[4 * kBigLds];
     int b, nblk;
     const int c = ring_role(d, G, b, nblk);
-    if (c == 0) link_role<ring_lanes(0, G)>(d, 0, b, nblk, t, sample_b, tape_k, lds);
-    else if (c == 1) link_role<ring_lanes(1, G)>(d, 1, b, nblk, t, sample_b, tape_k, lds);
-    else link_role<ring_lanes(2, G)>(d, 2, b, nblk, t, sample_b, tape_k, lds);
+    if (c == 0) link_role<ring_lanes(0, G), TAPE>(d, 0, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 1) link_role<ring_lanes(1, G), TAPE>(d, 1, b, nblk, t, sample_b, tape_k, lds);
+    else link_role<ring_lanes(2, G), TAPE>(d, 2, b, nblk, t, sample_b, tape_k, lds);
 }
 
-template <int G>
+template <int G, bool TAPE>
 __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int tape_k)
 {
     const unsigned long long t0 = stamp_begin(d);
-    link_launch<G>(d, t, sample_b, tape_k);
+    link_launch<G, TAPE>(d, t, sample_b, tape_k);
     stamp_end(d, t0);
 }
 
@@ -1565,14 +1568,20 @@ static void launch(K kernel, int blocks, hipStream_t st, A... args)
     hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, st, args...);
 }
 
-void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
+template <bool TAPE>
+static void launch_link_t(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
 {
     switch (d.g_link) {
-    case 8: launch(k_link<8>, link_blocks(d), st, d, t, sample_b, tape_k); break;
-    case 16: launch(k_link<16>, link_blocks(d), st, d, t, sample_b, tape_k); break;
-    case 32: launch(k_link<32>, link_blocks(d), st, d, t, sample_b, tape_k); break;
-    default: launch(k_link<64>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    case 8: launch(k_link<8, TAPE>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    case 16: launch(k_link<16, TAPE>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    case 32: launch(k_link<32, TAPE>, link_blocks(d), st, d, t, sample_b, tape_k); break;
+    default: launch(k_link<64, TAPE>, link_blocks(d), st, d, t, sample_b, tape_k); break;
     }
+}
+void launch_link(const Dev &d, int t, int sample_b, int tape_k, hipStream_t st)
+{
+    if (tape_k >= 0) launch_link_t<true>(d, t, sample_b, tape_k, st);
+    else launch_link_t<false>(d, t, sample_b, tape_k, st);
 }
 void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
 {

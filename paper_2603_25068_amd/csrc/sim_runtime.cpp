@@ -108,6 +108,9 @@ struct sim_t {
         int4 *ste = nullptr;   // node candidates' choices and outcomes (straight-through gradients)
     };
     std::vector<TapeSet> tapes;              // n_replay + 1 sets
+    // the recording forward writes window w's tape into set w % tapes.size(); tape_win[set] is the
+    // window a set holds from the forward (-1: none) and tape_steps[set] how many of its steps
+    std::vector<int> tape_win, tape_steps;
     // concurrent replays of the backward pass: each has its own copy of the mutable state and
     // its own stream, so windows are replayed side by side while the main stream sweeps
     int n_replay = 3;
@@ -399,6 +402,8 @@ void zero_state(sim_t *h)
     HIPCHK(hipMemsetAsync(d.err, 0, sim::ERR_N * 4, st));
     h->t = 0;
     h->rec_valid = h->record != 0;
+    h->tape_win.assign(h->tapes.size(), -1);
+    h->tape_steps.assign(h->tapes.size(), 0);
 }
 
 void upload_queues(sim_t *h)
@@ -1194,6 +1199,8 @@ int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_d
 {
     return guarded(h, [&] {
         if (!values) fail(SIM_EINVAL, "values is NULL");
+        // a rollout recorded under other parameters can no longer be replayed
+        if (h->t > 0) h->rec_valid = false;
         float *dst = nullptr;
         int64_t per = h->L;
         switch (which) {
@@ -1318,6 +1325,10 @@ int sim_rollout(sim_t *h, int32_t T)
 {
     return guarded(h, [&] {
         if (T < 0) fail(SIM_EINVAL, "T < 0");
+        // only the windows that end up as the last tapes.size() of this call are taped as the
+        // forward goes (taping costs a load and a store per agent and step)
+        const int64_t t_end = (int64_t)h->t + T;
+        const int64_t first_taped = t_end > 0 ? (t_end - 1) / h->ckpt_every - (int64_t)h->tapes.size() + 1 : 0;
         for (int k = 0; k < T; ++k) {
             if (h->record && h->rec_valid) {
                 if (h->t >= h->max_steps) h->rec_valid = false;
@@ -1330,7 +1341,31 @@ int sim_rollout(sim_t *h, int32_t T)
                     c.t = h->t;
                 }
             }
-            do_step(h, -1);
+            if (h->record && h->rec_valid && h->t / h->ckpt_every < first_taped) {
+                const int w = h->t / h->ckpt_every, set = w % (int)h->tapes.size();
+                if (h->tape_win[set] == w) h->tape_win[set] = -1;
+                do_step(h, -1);
+            } else if (h->record && h->rec_valid) {
+                // the window's tape, written as the forward goes: the last windows then need no replay
+                const int w = h->t / h->ckpt_every, kw = h->t % h->ckpt_every;
+                const int set = w % (int)h->tapes.size();
+                if (kw == 0) { h->tape_win[set] = w; h->tape_steps[set] = 0; }
+                const bool contiguous = h->tape_win[set] == w && h->tape_steps[set] == kw;
+                Dev dt = h->d;
+                const auto &ts = h->tapes[set];
+                dt.tape_pos = ts.pos; dt.tape_agent = ts.agent; dt.tape_head = ts.head; dt.tape_tail = ts.tail;
+                dt.tape_dst = ts.dst; dt.tape_dstg = nullptr; dt.tape_ste = nullptr;
+                step_on(h, dt, h->stream, h->t, contiguous ? kw : -1);
+                h->t += 1;
+                if (contiguous) {
+                    h->tape_steps[set] = kw + 1;
+                    if (kw + 1 == h->ckpt_every) sim::launch_tape_snapshot(dt, h->ckpt_every, h->stream);
+                } else {
+                    h->tape_win[set] = -1;
+                }
+            } else {
+                do_step(h, -1);
+            }
         }
         if (h->timing) h->resolve_timing();
         check_device_errors(h);
@@ -1404,7 +1439,6 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         // waits for the sweep that last read its tape set; a sweep waits for its window's replay.
         hipEvent_t *rp_done = h->bw_events.data(), *rv_done = h->bw_events.data() + nw;
         hipEvent_t start = h->bw_events[2 * (size_t)nw];
-        HIPCHK(hipEventRecord(start, st));
         auto use_tapes = [&](Dev &dv, int set) {
             const auto &ts = h->tapes[set];
             dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_head = ts.head; dv.tape_tail = ts.tail;
@@ -1412,7 +1446,21 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             dv.tape_dstg = want_m ? ts.dstg : nullptr;
             dv.tape_ste = want_ste ? ts.ste : nullptr;
         };
+        // windows whose whole tape the forward wrote (the last NT windows) are swept without a
+        // replay, unless the requested groups need tapes the forward does not write
+        auto fwd_taped = [&](int w) {
+            if (h->timing || want_m || want_ste || NT != (int)h->tapes.size()) return false;
+            const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
+            return h->tape_win[w % NT] == w && h->tape_steps[w % NT] == Ww;
+        };
+        if (fwd_taped(nw - 1) && T - (nw - 1) * h->ckpt_every < h->ckpt_every) {
+            Dev dl = h->d;   // the final partial window ends at the live state
+            use_tapes(dl, (nw - 1) % NT);
+            sim::launch_tape_snapshot(dl, T - (nw - 1) * h->ckpt_every, st);
+        }
+        HIPCHK(hipEventRecord(start, st));
         auto replay = [&](int w) {
+            if (fwd_taped(w)) return;
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
             const int slot = w % K;
             const hipStream_t rs = h->rp_stream[slot];
@@ -1433,7 +1481,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         for (int w = nw - 1; w >= std::max(0, nw - K); --w) replay(w);
         for (int w = nw - 1; w >= 0; --w) {
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
-            HIPCHK(hipStreamWaitEvent(st, rp_done[w], 0));
+            if (!fwd_taped(w)) HIPCHK(hipStreamWaitEvent(st, rp_done[w], 0));
             use_tapes(d, w % NT);
             if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
             for (int k = Ww - 1; k >= 0; --k) {
@@ -1444,7 +1492,9 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             if (w - K >= 0) replay(w - K);
             HIPCHK(hipGetLastError());
         }
-        // the main stream has waited for every replay (each sweep waits for its own)
+        // the main stream has waited for every replay (each sweep waits for its own); replays have
+        // reused the tape sets
+        h->tape_win.assign(h->tapes.size(), -1);
         h->d.gQ = nullptr; h->d.gT = nullptr; h->d.gx = nullptr;
         h->d.tape_dstg = nullptr; h->d.gm = nullptr;
         h->d.gbeta = h->d.gcost = h->d.galpha = h->d.gth = nullptr;
@@ -1638,6 +1688,7 @@ int sim_set_full_state(sim_t *h, const void *blob, size_t n)
         upload_queues(h);
         h->t = hd.t;
         h->rec_valid = h->record && hd.t == 0;
+        h->tape_win.assign(h->tapes.size(), -1);
         HIPCHK(hipStreamSynchronize(h->stream));
     });
 }
@@ -1840,6 +1891,7 @@ int sim_autotune(sim_t *h, int32_t probe_steps, const char *cache_path, int32_t 
 {
     return guarded(h, [&] {
         if (probe_steps < 1) fail(SIM_EINVAL, "probe_steps must be >= 1");
+        h->tape_win.assign(h->tapes.size(), -1);   // probes record into the tape sets
         const std::string key = shape_key(h), path = cache_path ? cache_path : "";
         std::array<int, 3> best = {h->g_link, h->g_node, h->g_rev};
         auto valid = [&](const std::array<int, 3> &v) {

@@ -480,6 +480,44 @@ def test_closed_links_hold_their_queues():
         _grad_close(go[k], gg[k][0], f"closed {k}")
 
 
+def test_forward_tape_gives_the_replayed_gradients():
+    """The recording forward writes the tape of its last windows, so the
+    backward sweeps them without a replay (the final one partial here).  A
+    second backward of the same rollout replays every window; a backward that
+    also asks for capacity multipliers replays every window with the extra
+    tape.  All three give bitwise the same gradients."""
+    w = W.random_small(7, nx=4, ny=4, n_agents=500, rates=True, steps=280)
+    s = _sim(w, record=True, ckpt_every=30).rollout()
+    cnt, _ = s.observables()
+    gQ = np.random.default_rng(7).normal(size=cnt.shape).astype(np.float32)
+    groups = ("free_speed", "jam_density", "rates")
+    g1 = s.backward(gQ=gQ, gT=[0.3], groups=groups)
+    g2 = s.backward(gQ=gQ, gT=[0.3], groups=groups)
+    g3 = s.backward(gQ=gQ, gT=[0.3], groups=groups + ("cap_mult",))
+    for k in groups:
+        assert np.array_equal(g1[k], g2[k]) and np.array_equal(g1[k], g3[k]), k
+    o = Oracle(w, log=True).run()
+    go = o.backward(gQ=gQ[0].astype(np.float64), gT=0.3)
+    for k in groups:
+        _grad_close(go[k], g1[k][0], k)
+
+
+def test_set_params_after_t0_ends_the_recording():
+    """Parameters changed in the middle of a recorded rollout: the backward
+    refuses (the replay would follow other parameters than the forward)."""
+    from paper_2603_25068_amd.sim import SimError
+    w = W.random_small(3, nx=3, ny=3, n_agents=100, rates=True, steps=120)
+    s = _sim(w, record=True)
+    s.step(50)
+    s.set_params("free_speed", w.net.free_speed)
+    s.step(10)
+    with pytest.raises(SimError):
+        s.backward(gT=[1.0])
+    s.reset()
+    s.step(60)
+    s.backward(gT=[1.0])
+
+
 def test_autotune_restores_state_and_caches(tmp_path):
     """The autotuner probes from the live state and puts it back: a rollout
     tuned half-way equals an untuned one (values and gradients), and a second
