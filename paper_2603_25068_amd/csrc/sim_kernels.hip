@@ -884,6 +884,7 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
 // init = 1: adj_ring = dL/dx(T) at the final state (no step).
 // ---------------------------------------------------------------------------
 constexpr int kRevBigLds = 1280;    // LDS words per wavefront (two arrays), split evenly among its lane groups
+constexpr int kRevUnroll = 4;       // staged ranks per lane and round of the reverse
 
 template <int G>
 __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
@@ -937,21 +938,45 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     for (int lo = 0; lo < n; lo += piece) {
         const int hi = min(n, lo + piece);
         const int slo = max(0, lo - ln), shi = min(n, hi + ln);
-        // taped positions of [slo, shi) and the adjoints of the x_hat of [lo, shi)
-        for (int r = slo + gl; r < shi; r += G) {
-            const int sl = slot_of(r);
-            xb[r - slo] = d.tape_pos[tb + sl];
-            if (r >= lo) {
-                float ap;
-                if (init) ap = d.gx ? d.gx[sN + d.tape_agent[tb + sl]] : 0.f;
-                else if (r < npass) {
-                    const int ds = d.tape_dst[dst0 + r];
-                    ap = ds < 0 ? exit_adj : d.adj_ring[ds];
-                    // admission graft of a head that left on a token (once per rank: r < hi)
-                    if (d.gm && ds >= 0 && r < hi) gm += (double)ap * (double)d.tape_dstg[dst0 + r];
-                }
-                else ap = d.adj_ring[base + sl];
-                pb[r - slo] = ap;
+        // taped positions of [slo, shi) and the adjoints of the x_hat of [lo, shi): kRevUnroll ranks
+        // per lane per round with their direct loads in flight together; the few heads that left
+        // (r < npass) then read their adjoint at the entry slot the tape names
+        for (int r = slo + gl; r < shi; r += kRevUnroll * G) {
+            float x4[kRevUnroll], a4[kRevUnroll];
+#pragma unroll
+            for (int q = 0; q < kRevUnroll; ++q) {
+                const int rr = r + q * G;
+                const bool in = rr < shi;
+                const int sl = in ? slot_of(rr) : 0;
+                x4[q] = in ? d.tape_pos[tb + sl] : 0.f;
+                a4[q] = (in && rr >= lo && !init && rr >= npass) ? d.adj_ring[base + sl] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < kRevUnroll; ++q) {
+                const int rr = r + q * G;
+                if (rr < shi) xb[rr - slo] = x4[q];
+                if (rr < shi && rr >= lo) pb[rr - slo] = a4[q];
+            }
+        }
+        // heads that left, and the final state's cotangents
+        for (int r = lo + gl; r < hi && (init || r < npass); r += G) {
+            float ap;
+            if (init) {
+                ap = d.gx ? d.gx[sN + d.tape_agent[tb + slot_of(r)]] : 0.f;
+            } else {
+                const int ds = d.tape_dst[dst0 + r];
+                ap = ds < 0 ? exit_adj : d.adj_ring[ds];
+                // admission graft of a head that left on a token
+                if (d.gm && ds >= 0) gm += (double)ap * (double)d.tape_dstg[dst0 + r];
+            }
+            pb[r - slo] = ap;
+        }
+        if (init) {   // the follower halo [hi, shi) of the final state
+            for (int r = hi + gl; r < shi; r += G) pb[r - slo] = d.gx ? d.gx[sN + d.tape_agent[tb + slot_of(r)]] : 0.f;
+        } else {      // heads that left in the follower halo (only when a piece ends inside them)
+            for (int r = hi + gl; r < min(shi, npass); r += G) {
+                const int ds = d.tape_dst[dst0 + r];
+                pb[r - slo] = ds < 0 ? exit_adj : d.adj_ring[ds];
             }
         }
         wave_lds_sync();
