@@ -146,21 +146,32 @@ struct Group {
 };
 
 
-// Counter increments of one work item: summed over its lane group, then one
-// atomic per non-zero counter into one of kCtrSlots slots (spread by item) so
-// that concurrent items rarely hit the same address.
+// Counter increments of one node: releases, and five small counts packed as
+// 8-bit fields of one word (each at most 2 per lane, so at most 128 per
+// group), summed over the lane group, then one atomic per non-zero counter
+// into one of kCtrSlots slots (spread by item) so that concurrent items
+// rarely hit the same address.
+enum { NF_DEPARTED = 0, NF_EXITED, NF_TRANSFERS, NF_TIES, NF_STUCK, NF_N };
+__device__ __forceinline__ uint64_t nf_one(int f) { return 1ull << (8 * f); }
+
 template <int G>
-__device__ __forceinline__ void add_counters(Dev &d, const Group<G> &g, int s, int item, int (&inc)[CTR_N])
+__device__ __forceinline__ void add_node_counters(Dev &d, const Group<G> &g, int s, int item, int released,
+                                                  uint64_t small)
 {
-#pragma unroll
-    for (int k = 0; k < CTR_N; ++k) inc[k] = g.sum(inc[k]);
+    released = g.sum(released);
+    small = g.sum(small);
     if (g.gl == 0) {
         unsigned long long *c = (unsigned long long *)&d.ctr[((int64_t)s * kCtrSlots + (item % kCtrSlots)) * CTR_N];
+        if (released) atomicAdd(c + CTR_RELEASED, (unsigned long long)released);
+        constexpr int ctr_of[NF_N] = {CTR_DEPARTED, CTR_EXITED, CTR_TRANSFERS, CTR_TIES, CTR_STUCK};
 #pragma unroll
-        for (int k = 0; k < CTR_N; ++k)
-            if (inc[k]) atomicAdd(c + k, (unsigned long long)inc[k]);
+        for (int f = 0; f < NF_N; ++f) {
+            const unsigned long long v = (small >> (8 * f)) & 0xffull;
+            if (v) atomicAdd(c + ctr_of[f], v);
+        }
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Link phase: per (scenario, link) segment, in place on the ring.
@@ -182,6 +193,7 @@ __device__ __forceinline__ void add_counters(Dev &d, const Group<G> &g, int s, i
 // go back to front, so a piece never reads ranks an earlier piece wrote.
 // ---------------------------------------------------------------------------
 constexpr int kBigLds = 1024;    // LDS floats per wavefront for big segments (link phase)
+constexpr int kLinkUnroll = 4;   // staged ranks per lane and round of the link phase
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -254,19 +266,19 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     for (int hi = n; hi > 0; hi -= piece) {
         const int lo = max(0, hi - piece);
         const int slo = max(0, lo - ln);
-        // stage ranks [slo, hi): four loads in flight per lane per round; a recording replay also
-        // copies the time-t position and agent of ranks [lo, hi) to the tape here, with those loads
-        for (int r = slo + gl; r < hi; r += 4 * G) {
-            float v4[4];
-            int a4[4];
+        // stage ranks [slo, hi): kLinkUnroll loads in flight per lane per round; a recording replay
+        // also copies the time-t position and agent of ranks [lo, hi) to the tape here, with those loads
+        for (int r = slo + gl; r < hi; r += kLinkUnroll * G) {
+            float v4[kLinkUnroll];
+            int a4[kLinkUnroll];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kLinkUnroll; ++q) {
                 const int rr = r + q * G;
                 v4[q] = rr < hi ? d.ring_pos[base + slot_of(rr)] : 0.f;
                 a4[q] = (TAPE && rr >= lo && rr < hi) ? d.ring_agent[base + slot_of(rr)] : 0;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kLinkUnroll; ++q) {
                 const int rr = r + q * G;
                 if (rr >= hi) continue;
                 buf[rr - slo] = v4[q];
@@ -437,9 +449,8 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const int ncin = (cnt >> 24) & 0xff;   // head lanes of the in-links (sum of their lane counts)
     const int nc = ncin + norg;
     const int64_t sL = (int64_t)s * d.L;
-    int inc[CTR_N];
-#pragma unroll
-    for (int k = 0; k < CTR_N; ++k) inc[k] = 0;
+    int released = 0;
+    uint64_t small = 0;   // packed counts (NF_* fields)
 
     // first-level loads issued together (padded tables need no offsets)
     const int om_raw = d.out_pad[(int64_t)v * d.max_out + min(gl, d.max_out - 1)];
@@ -535,14 +546,14 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
             }
         }
         if (newrel != rel) d.rel_ptr[so] = newrel;
-        inc[CTR_RELEASED] += newrel - rel;
+        released += newrel - rel;
         if (dp0 < newrel) { ag = fa; dst = fdst; didx = fdidx; }
     }
     const bool ste_rec = tape_k >= 0 && d.tape_ste != nullptr;   // straight-through tape (recording replay)
     const int64_t ste_i = ((int64_t)tape_k * d.S + s) * d.n_cand + (ste_rec ? d.cbase[v] : 0) + gl;
     if (g.count(ag >= 0) == 0) {   // nothing to move at this node this step
         if (ste_rec && gl < nc) d.tape_ste[ste_i] = make_int4(-1, 0, -1, -1);
-        add_counters<G>(d, g, s, item, inc);
+        add_node_counters<G>(d, g, s, item, released, 0);
         return;
     }
     const uint64_t seed = d.seed[s];
@@ -640,7 +651,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     int ch = CH_NONE;
     if (chooser) {
         ch = arg;
-        if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) inc[CTR_TIES] += 1;
+        if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) small += nf_one(NF_TIES);
     } else if (exiting) {
         ch = CH_EXIT;
     }
@@ -677,7 +688,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     }
     const int sl = ch >= 0 ? orc[argk].slots : 0;
     const int won = (ch >= 0) && rank < sl;
-    if (ch >= 0) inc[CTR_TIES] += close;
+    if (ch >= 0 && close) small += nf_one(NF_TIES);
 
     // ---- resolve: lane q < deg walks in-link q's heads in rank order ----
     int np = 0;
@@ -689,7 +700,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         if (gl < deg && !stop && r < nhq) {
             if (c2 == CH_EXIT) ++np;
             else if (c2 >= 0 && w2 && Bj >= 1.0) { Bj -= 1.0; ++np; consumed = true; }
-            else { stop = true; if (c2 == CH_STUCK) inc[CTR_STUCK] += 1; }
+            else { stop = true; if (c2 == CH_STUCK) small += nf_one(NF_STUCK); }
         }
     }
     if (gl < deg) {
@@ -776,17 +787,17 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
                 d.status[ga] = AG_ON;
                 d.dep_t[ga] = t;
                 d.dep_ptr[s * d.O + origin] = dp0 + 1;
-                inc[CTR_DEPARTED] += 1;
+                small += nf_one(NF_DEPARTED);
             } else {
-                inc[CTR_TRANSFERS] += 1;
+                small += nf_one(NF_TRANSFERS);
             }
         } else {
             d.status[ga] = AG_EXITED;
             d.exit_t[ga] = t;
-            inc[CTR_EXITED] += 1;
+            small += nf_one(NF_EXITED);
         }
     }
-    add_counters<G>(d, g, s, item, inc);
+    add_node_counters<G>(d, g, s, item, released, small);
 }
 
 // Node phase launch: nodes are split on the host into classes by the lane
