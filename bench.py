@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--profile-pass", action="store_true", help="one forward+adjoint pass only")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tape-windows", type=int, default=16,
+                    help="windows of replay tape kept on the device (the forward tapes the last ones)")
     ap.add_argument("--no-control", action="store_true", help="skip the batched-control leg")
     ap.add_argument("--schedule", default="", help="g_link,g_node,g_rev instead of the autotuner's choice")
     ap.add_argument("--fwd-adj-only", action="store_true",
@@ -306,7 +308,7 @@ def main():
     gen_s = time.perf_counter() - t_gen
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sim = Simulator(w, record=True, max_steps=T)
+    sim = Simulator(w, record=True, max_steps=T, tape_windows=args.tape_windows)
     fwd = Simulator(w, record=False)
     S, L, Nn, O = 1, w.net.n_links, w.net.n_nodes, w.net.n_origins
     nb = sim.n_count_bins
@@ -404,7 +406,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "agents": w.dem.n_agents, "links": L, "nodes": Nn, "origins": O,
-                   "sim_steps": T, "ckpt_every": w.cfg.ckpt_every, "pass": "forward+adjoint",
+                   "sim_steps": T, "ckpt_every": w.cfg.ckpt_every, "tape_windows": args.tape_windows,
+                   "pass": "forward+adjoint",
                    "vehicle_steps_per_pass": vs,
                    "forward_only_vehicle_steps_per_s": round(fwd_value, 1) if fwd_value else None,
                    "forward_only_ms": round(1000.0 * el_f / args.steps, 3) if el_f else None,

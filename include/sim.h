@@ -116,6 +116,11 @@ typedef struct {
     int32_t allow_uturn;      /* 1: a head may take the reverse of its link */
     int32_t record_for_backward; /* 1: sim_rollout keeps checkpoints for sim_backward */
     size_t mem_budget_bytes;  /* 0 = no limit; sim_create fails with SIM_ENOMEM beyond it */
+    int32_t tape_windows;     /* recording handles: windows of replay tape kept on the device.  The
+                                 recording forward writes the tape of its last tape_windows windows
+                                 as it goes; sim_backward replays only the windows before them (from
+                                 their checkpoints).  0: as many as fit in 32 GiB, between 4 and 16;
+                                 otherwise at least 4.  Never more than the recorded windows. */
 } sim_config;
 
 typedef struct sim_t sim_t;

@@ -107,13 +107,14 @@ struct sim_t {
         int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *dst = nullptr;
         int4 *ste = nullptr;   // node candidates' choices and outcomes (straight-through gradients)
     };
-    std::vector<TapeSet> tapes;              // n_replay + 1 sets
+    std::vector<TapeSet> tapes;              // n_tape_sets sets
     // the recording forward writes window w's tape into set w % tapes.size(); tape_win[set] is the
     // window a set holds from the forward (-1: none) and tape_steps[set] how many of its steps
     std::vector<int> tape_win, tape_steps;
     // concurrent replays of the backward pass: each has its own copy of the mutable state and
     // its own stream, so windows are replayed side by side while the main stream sweeps
     int n_replay = 3;
+    int n_tape_sets = 4;                     // tape sets (windows of tape kept on the device), >= n_replay + 1
     std::vector<Dev> rp_dev;
     std::vector<hipStream_t> rp_stream;
     std::vector<hipEvent_t> bw_events;       // replay-done and reverse-done events per window
@@ -875,7 +876,16 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
         h->W = h->ckpt_every;
         bytes += (size_t)n_ck * (SR * 16 + SL * 32 + SO * 16 + SN);
-        bytes += (size_t)(h->n_replay + 1) * (h->W + 1) * (SR * 8 + SL * 8 + SL * maxl * 8) + SR * 4 + SN * 4 + SL * 24;
+        // one tape set: positions and agents per slot, head/tail per segment, entry slot and graft factor
+        // per leaving head, and a straight-through record per node candidate, for W + 1 states
+        const size_t per_set = (size_t)(h->W + 1) *
+                               (SR * 8 + SL * 8 + SL * maxl * 8 + (size_t)h->S * std::max(h->n_cand, 1) * 16);
+        const int min_sets = h->n_replay + 1, windows = std::max(n_ck - 1, 1);
+        int sets = cfg->tape_windows > 0 ? std::max(min_sets, (int)cfg->tape_windows)
+                                         : (int)std::min<size_t>(16, ((size_t)32 << 30) / std::max<size_t>(per_set, 1));
+        sets = std::max(min_sets, std::min(sets, std::max(windows, min_sets)));
+        h->n_tape_sets = sets;
+        bytes += (size_t)sets * per_set + SR * 4 + SN * 4 + SL * 24 + SL * 8 * 4 + (size_t)h->S * Nn * 8;
         bytes += (size_t)h->n_replay * (SR * 16 + SL * (48 + maxl * 16) + SN * 21 + SO * 16 +
                                         (size_t)h->S * h->D * std::max(h->nb, 1) * 4);
     }
@@ -965,7 +975,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     if (h->record) {
         h->ckpts.resize(n_ck + 1);
         for (auto &c : h->ckpts) ckpt_alloc(h, c);
-        h->tapes.resize((size_t)h->n_replay + 1);
+        h->tapes.resize((size_t)h->n_tape_sets);
         for (auto &ts : h->tapes) {
             ts.pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
             ts.agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
@@ -1432,9 +1442,9 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         const int nw = (T + h->ckpt_every - 1) / h->ckpt_every;
         // in timing mode the windows run one after another (one replay slot, each replay after the
         // previous sweep), so that per-kernel times are not stretched by concurrent kernels
-        const int K = h->timing ? 1 : h->n_replay, NT = K + 1;
+        const int K = h->timing ? 1 : h->n_replay, NT = (int)h->tapes.size();
         // Window w is replayed from its checkpoint by slot w % K (its own copy of the mutable state,
-        // on its own stream) into tape set w % (K + 1), then swept in reverse on the main stream.
+        // on its own stream) into tape set w % NT, then swept in reverse on the main stream.
         // Up to K replays run at once beside the sweep; the live state is never touched.  A replay
         // waits for the sweep that last read its tape set; a sweep waits for its window's replay.
         hipEvent_t *rp_done = h->bw_events.data(), *rv_done = h->bw_events.data() + nw;
@@ -1449,7 +1459,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         // windows whose whole tape the forward wrote (the last NT windows) are swept without a
         // replay, unless the requested groups need tapes the forward does not write
         auto fwd_taped = [&](int w) {
-            if (h->timing || want_m || want_ste || NT != (int)h->tapes.size()) return false;
+            if (want_m || want_ste) return false;
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
             return h->tape_win[w % NT] == w && h->tape_steps[w % NT] == Ww;
         };
@@ -1459,12 +1469,14 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             sim::launch_tape_snapshot(dl, T - (nw - 1) * h->ckpt_every, st);
         }
         HIPCHK(hipEventRecord(start, st));
+        std::vector<char> slot_used((size_t)K, 0);
         auto replay = [&](int w) {
             if (fwd_taped(w)) return;
             const int t0 = w * h->ckpt_every, Ww = std::min(h->ckpt_every, T - t0);
             const int slot = w % K;
             const hipStream_t rs = h->rp_stream[slot];
-            if (w >= nw - K) HIPCHK(hipStreamWaitEvent(rs, start, 0));   // first use of the slot in this call
+            if (!slot_used[slot]) HIPCHK(hipStreamWaitEvent(rs, start, 0));   // first use of the slot in this call
+            slot_used[slot] = 1;
             if (w + NT <= nw - 1) HIPCHK(hipStreamWaitEvent(rs, rv_done[w + NT], 0));
             if (h->timing && w + 1 <= nw - 1) HIPCHK(hipStreamWaitEvent(rs, rv_done[w + 1], 0));
             Dev r = h->d;

@@ -51,7 +51,8 @@ class _Config(C.Structure):
                 ("dest_logit_coef", C.c_double), ("big_m", C.c_double), ("seed", C.c_uint64),
                 ("scenario_seed", C.c_void_p), ("n_scenarios", C.c_int32), ("ckpt_every", C.c_int32),
                 ("count_bin_steps", C.c_int32), ("n_count_bins", C.c_int32), ("max_steps", C.c_int32),
-                ("allow_uturn", C.c_int32), ("record_for_backward", C.c_int32), ("mem_budget_bytes", C.c_size_t)]
+                ("allow_uturn", C.c_int32), ("record_for_backward", C.c_int32), ("mem_budget_bytes", C.c_size_t),
+                ("tape_windows", C.c_int32)]
 
 
 _LIB = None
@@ -136,7 +137,8 @@ def _i32(a):
     return np.ascontiguousarray(a, np.int32)
 
 
-def _marshal(w, S: int, seeds, steps: int, ckpt_every, max_steps, record: bool, mem_budget_bytes: int):
+def _marshal(w, S: int, seeds, steps: int, ckpt_every, max_steps, record: bool, mem_budget_bytes: int,
+             tape_windows: int = 0):
     """The C structures of a workload (and the arrays they point into, which
     the caller keeps alive while the structures are in use)."""
     net, dem, cfg = w.net, w.dem, w.cfg
@@ -166,7 +168,7 @@ def _marshal(w, S: int, seeds, steps: int, ckpt_every, max_steps, record: bool, 
                 float(cfg.big_m), int(cfg.seed) & (2 ** 64 - 1), _p(K.get("seeds")), int(S),
                 int(ckpt_every or cfg.ckpt_every), cbs, n_count_bins,
                 int(max_steps if max_steps is not None else steps), int(cfg.allow_uturn), int(record),
-                int(mem_budget_bytes))
+                int(mem_budget_bytes), int(tape_windows))
     return n, d, c, K
 
 
@@ -179,7 +181,8 @@ class Simulator:
 
     def __init__(self, w, n_scenarios: int = 1, params: Optional[dict] = None, seeds: Optional[Sequence[int]] = None,
                  record: bool = False, max_steps: Optional[int] = None, steps: Optional[int] = None,
-                 device: int = 0, stream=None, mem_budget_bytes: int = 0, ckpt_every: Optional[int] = None):
+                 device: int = 0, stream=None, mem_budget_bytes: int = 0, ckpt_every: Optional[int] = None,
+                 tape_windows: int = 0):
         import torch
         self._L = lib()
         self.w = w
@@ -193,7 +196,7 @@ class Simulator:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
         n, d, c, self._keep = _marshal(w, self.S, seeds, self.steps, ckpt_every, max_steps, record,
-                                       mem_budget_bytes)
+                                       mem_budget_bytes, tape_windows)
         h = C.c_void_p()
         rc = self._L.sim_create(C.byref(n), C.byref(d), C.byref(c), device, C.c_void_p(stream.cuda_stream),
                                 C.byref(h))

@@ -502,6 +502,35 @@ def test_forward_tape_gives_the_replayed_gradients():
         _grad_close(go[k], g1[k][0], k)
 
 
+def test_tape_windows_do_not_change_gradients():
+    """Ten windows with 4, 5 or 7 tape sets: the last windows come from the
+    forward's tape and the rest are replayed from their checkpoints (three at
+    a time beside the sweep, or one at a time in timing mode).  Every mix
+    gives bitwise the same gradients, and they match the oracle's."""
+    w = W.random_small(11, nx=4, ny=4, n_agents=500, rates=True, steps=280)
+    groups = ("free_speed", "jam_density", "rates")
+    rng = np.random.default_rng(11)
+    ref = None
+    for tw, timing in ((4, False), (5, False), (7, False), (5, True)):
+        s = _sim(w, record=True, ckpt_every=28, tape_windows=tw)
+        if timing:
+            s.set_timing(True)
+        s.rollout()
+        cnt, _ = s.observables()
+        if ref is None:
+            gQ = rng.normal(size=cnt.shape).astype(np.float32)
+        g = s.backward(gQ=gQ, gT=[0.4], groups=groups)
+        if ref is None:
+            ref = g
+            o = Oracle(w, log=True).run()
+            go = o.backward(gQ=gQ[0].astype(np.float64), gT=0.4)
+            for k in groups:
+                _grad_close(go[k], g[k][0], k)
+        else:
+            for k in groups:
+                assert np.array_equal(ref[k], g[k]), (tw, timing, k)
+
+
 def test_set_params_after_t0_ends_the_recording():
     """Parameters changed in the middle of a recorded rollout: the backward
     refuses (the replay would follow other parameters than the forward)."""
