@@ -18,8 +18,10 @@ namespace sim {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxLanes = 8;     // lanes per link accepted by sim_create
-constexpr int kSmallRing = 128;  // ring classes by slots: <= kSmallRing, <= kMidRing, larger
+constexpr int kSmallRing = 128;  // ring classes by slots: <= kSmallRing, <= kMidRing, <= kLongRing, larger
 constexpr int kMidRing = 256;
+constexpr int kLongRing = 512;
+constexpr int kRingClasses = 4;
 constexpr int kMaxDetPerLink = 4;
 constexpr int kCtrSlots = 64;      // counters are spread over this many slots per scenario
 enum : int32_t { CH_STUCK = -1, CH_EXIT = -2, CH_NONE = -3 };
@@ -33,7 +35,7 @@ struct Dev {
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
     int32_t rate_bin_steps;          // steps per departure-rate bin (rate bins are whole numbers of steps)
     int32_t g_link, g_node, g_rev;   // lanes per small segment / node floor / small reverse segment (16, 32, 64)
-    int32_t lc_n[3];                 // links per ring class, contiguous ids: <= kSmallRing slots, <= kMidRing, larger
+    int32_t lc_n[kRingClasses];      // links per ring class, contiguous ids: <= kSmallRing slots, <= kMidRing, ...
     int32_t nd_begin[4], nd_n[4];    // node id ranges of the node kernel's 8-, 16-, 32- and 64-lane roles
     int64_t ring_total;
     double dt, theta, rate_bin_s;

@@ -184,10 +184,10 @@ __device__ __forceinline__ void add_node_counters(Dev &d, const Group<G> &g, int
 //   step's idle cap min(B, 1) is applied here, before the accrual), detector
 //   crossings, order check; records the heads (agent, destination) for the
 //   node phase.
-// Links are split by ring capacity into three contiguous id ranges (at most
-// kSmallRing slots, at most kMidRing, larger), served by G, max(G, 16) and
-// max(G, 32) lanes, so that a launch holds about as many waves as the chip
-// keeps resident.  Each lane group gets an equal share of the block's LDS.
+// Links are split by ring capacity into four contiguous id ranges (at most
+// kSmallRing slots, kMidRing, kLongRing, larger), served by G, max(G, 16),
+// max(G, 32) and 64 lanes, so that a launch holds about as many waves as the
+// chip keeps resident and the longest rings get the most lanes.  Each lane group gets an equal share of the block's LDS.
 // A segment is staged into LDS
 // (a piece of up to bufcap ranks plus the leader halo) with all loads in
 // flight at once, then updated from that snapshot: every input is a time-t
@@ -352,7 +352,7 @@ __device__ __forceinline__ void stamp_end(const Dev &d, unsigned long long t0)
 // block counts are multiples of 8, so every role keeps the XCD pattern.
 __host__ __device__ __forceinline__ constexpr int ring_lanes(int c, int G)
 {
-    return c == 0 ? G : (c == 1 ? (G > 16 ? G : 16) : (G > 32 ? G : 32));
+    return c == 0 ? G : (c == 1 ? (G > 16 ? G : 16) : (c == 2 ? (G > 32 ? G : 32) : 64));
 }
 __host__ __device__ __forceinline__ int ring_role_blocks(int items, int lanes, bool last)
 {
@@ -364,7 +364,8 @@ __host__ __device__ __forceinline__ int ring_blocks(const Dev &d, int G)
 {
     return ring_role_blocks(d.S * d.lc_n[0], ring_lanes(0, G), false) +
            ring_role_blocks(d.S * d.lc_n[1], ring_lanes(1, G), false) +
-           ring_role_blocks(d.S * d.lc_n[2], ring_lanes(2, G), true);
+           ring_role_blocks(d.S * d.lc_n[2], ring_lanes(2, G), false) +
+           ring_role_blocks(d.S * d.lc_n[3], ring_lanes(3, G), true);
 }
 // block b of the launch -> (class, block within the class, blocks of the class)
 __device__ __forceinline__ int ring_role(const Dev &d, int G, int &b, int &nblk)
@@ -376,8 +377,11 @@ __device__ __forceinline__ int ring_role(const Dev &d, int G, int &b, int &nblk)
     const int b1 = ring_role_blocks(d.S * d.lc_n[1], ring_lanes(1, G), false);
     if (b < b1) { nblk = b1; return 1; }
     b -= b1;
-    nblk = (int)gridDim.x - b0 - b1;
-    return 2;
+    const int b2 = ring_role_blocks(d.S * d.lc_n[2], ring_lanes(2, G), false);
+    if (b < b2) { nblk = b2; return 2; }
+    b -= b2;
+    nblk = (int)gridDim.x - b0 - b1 - b2;
+    return 3;
 }
 
 template <int GC, bool TAPE>
@@ -390,7 +394,8 @@ __device__ __forceinline__ void link_role(Dev &d, int c, int b, int nblk, int t,
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / GC;
     if (item >= n) return;
     const int s = item / d.lc_n[c];
-    const int first = c == 0 ? 0 : (c == 1 ? d.lc_n[0] : d.lc_n[0] + d.lc_n[1]);
+    int first = 0;
+    for (int k = 0; k < c; ++k) first += d.lc_n[k];
     const int seg = s * d.L + first + (item - s * d.lc_n[c]);
     link_segment<GC, TAPE>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
 }
@@ -403,7 +408,8 @@ __device__ __forceinline__ void link_launch(Dev &d, int t, int sample_b, int tap
     const int c = ring_role(d, G, b, nblk);
     if (c == 0) link_role<ring_lanes(0, G), TAPE>(d, 0, b, nblk, t, sample_b, tape_k, lds);
     else if (c == 1) link_role<ring_lanes(1, G), TAPE>(d, 1, b, nblk, t, sample_b, tape_k, lds);
-    else link_role<ring_lanes(2, G), TAPE>(d, 2, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 2) link_role<ring_lanes(2, G), TAPE>(d, 2, b, nblk, t, sample_b, tape_k, lds);
+    else link_role<ring_lanes(3, G), TAPE>(d, 3, b, nblk, t, sample_b, tape_k, lds);
 }
 
 template <int G, bool TAPE>
@@ -1065,7 +1071,8 @@ __device__ __forceinline__ void reverse_role(Dev &d, int c, int b, int nblk, int
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / GC;
     if (item >= n) return;
     const int s = item / d.lc_n[c];
-    const int first = c == 0 ? 0 : (c == 1 ? d.lc_n[0] : d.lc_n[0] + d.lc_n[1]);
+    int first = 0;
+    for (int k = 0; k < c; ++k) first += d.lc_n[k];
     const int seg = s * d.L + first + (item - s * d.lc_n[c]);
     reverse_segment<GC>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
 }
@@ -1078,7 +1085,8 @@ __device__ __forceinline__ void reverse_launch(Dev &d, int t, int tape_k, int in
     const int c = ring_role(d, G, b, nblk);
     if (c == 0) reverse_role<ring_lanes(0, G)>(d, 0, b, nblk, t, tape_k, init, lds);
     else if (c == 1) reverse_role<ring_lanes(1, G)>(d, 1, b, nblk, t, tape_k, init, lds);
-    else reverse_role<ring_lanes(2, G)>(d, 2, b, nblk, t, tape_k, init, lds);
+    else if (c == 2) reverse_role<ring_lanes(2, G)>(d, 2, b, nblk, t, tape_k, init, lds);
+    else reverse_role<ring_lanes(3, G)>(d, 3, b, nblk, t, tape_k, init, lds);
 }
 
 template <int G>

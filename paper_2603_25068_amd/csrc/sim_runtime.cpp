@@ -75,7 +75,7 @@ struct sim_t {
     double dt = 1.0, rate_bin_s = 0.0;
     int32_t platoon = 1, ckpt_every = 60, max_steps = 0, record = 0;
     int32_t g_link = 16, g_node = 64, g_rev = 16;   // lanes per work item
-    int32_t n_ring_cls[3] = {0, 0, 0};   // internal links by ring class (<= kSmallRing, <= kMidRing, larger)
+    int32_t n_ring_cls[sim::kRingClasses] = {0, 0, 0, 0};   // internal links by ring class
     int32_t nd_off[5] = {0, 0, 0, 0, 0};  // internal nodes by lane-group class (8, 16, 32, 64 lanes), contiguous
     std::vector<int32_t> tail, head, lanes, origin_node, det_link, agent_origin, agent_dest;
     std::vector<float> length, free_speed, jam_density, capacity, beta, alpha, cost, det_pos, ready, rates;
@@ -446,7 +446,7 @@ int node_class(int need) { return need <= 8 ? 0 : (need <= 16 ? 1 : (need <= 32 
 
 // Internal numbering.  Nodes: reverse Cuthill-McKee for locality, then grouped by lane-group class
 // (stable), so each class of the node kernel is a contiguous id range.  Links: by ring class (at most
-// kSmallRing slots, at most kMidRing, larger), then by new tail node and original id, so each class of
+// kSmallRing slots, kMidRing, kLongRing, larger), then by new tail node and original id, so each class of
 // the link and reverse kernels is a contiguous id range and a node's out-links lie together.
 void renumber(sim_t *h)
 {
@@ -499,10 +499,10 @@ void renumber(sim_t *h)
     h->ninv.assign(Nn, 0);
     for (int k = 0; k < Nn; ++k) h->ninv[order[k]] = k;
     std::vector<char> cls(L);
-    for (int c = 0; c < 3; ++c) h->n_ring_cls[c] = 0;
+    for (int c = 0; c < sim::kRingClasses; ++c) h->n_ring_cls[c] = 0;
     for (int j = 0; j < L; ++j) {
         const double slots = ring_slots(h->length[j], h->lanes[j], h->jam_density[j], h->platoon);
-        cls[j] = slots <= sim::kSmallRing ? 0 : (slots <= sim::kMidRing ? 1 : 2);
+        cls[j] = slots <= sim::kSmallRing ? 0 : (slots <= sim::kMidRing ? 1 : (slots <= sim::kLongRing ? 2 : 3));
         h->n_ring_cls[(int)cls[j]]++;
     }
     h->lperm.resize(L);
@@ -539,7 +539,7 @@ std::vector<float> links_in(const sim_t *h, const float *v)
 void build_classes(sim_t *h)
 {
     Dev &d = h->d;
-    for (int c = 0; c < 3; ++c) d.lc_n[c] = h->n_ring_cls[c];
+    for (int c = 0; c < sim::kRingClasses; ++c) d.lc_n[c] = h->n_ring_cls[c];
     // node roles of 8, 16, 32 and 64 lanes; the schedule's floor moves smaller classes up
     const int r1 = h->g_node <= 8 ? h->nd_off[1] : 0;
     const int r2 = h->g_node <= 16 ? h->nd_off[2] : 0;
