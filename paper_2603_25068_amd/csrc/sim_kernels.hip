@@ -931,29 +931,11 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     if (d.gQ && d.cbs > 0 && t > 0 && t % d.cbs == 0 && t / d.cbs <= d.nb) sb = t / d.cbs - 1;
     const int d0 = d.det_off[j], nd = d.det_off[j + 1] - d0;
     const float sc = 5.0f / Lj;
-    float gC[kMaxDetPerLink], dpos[kMaxDetPerLink];
-#pragma unroll
-    for (int k = 0; k < kMaxDetPerLink; ++k) {
-        gC[k] = 0.f;
-        dpos[k] = 0.f;
-        if (sb >= 0 && k < nd) {
-            const int det = d.det_list[d0 + k];
-            const int64_t qi = ((int64_t)s * d.D + det) * d.nb;
-            gC[k] = d.gQ[qi + sb] - (sb + 1 < d.nb ? d.gQ[qi + sb + 1] : 0.f);
-            dpos[k] = d.det_pos[det];
-        }
-    }
     const int P = bufcap / 2;
     float *xb = buf, *pb = buf + P;
     const int piece = P - 2 * kMaxLanes;
     const int64_t dst0 = ((int64_t)tape_k * SL + seg) * d.maxl;
     double gu = 0.0, gk = 0.0, gm = 0.0;
-    double gu0 = 0.0, gk0 = 0.0, gm0 = 0.0;   // accumulators of this segment, read with the first loads
-    if (gl == 0 && !init) {
-        gu0 = d.gu[seg];
-        gk0 = d.gk[seg];
-        if (d.gm) gm0 = d.gm[seg];
-    }
     for (int lo = 0; lo < n; lo += piece) {
         const int hi = min(n, lo + piece);
         const int slo = max(0, lo - ln), shi = min(n, hi + ln);
@@ -1027,13 +1009,16 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
             } else {
                 anew = ap;
             }
-            if (sb >= 0) {
+            if (sb >= 0) {   // a sampling step (rare): the detector values are read here, not held
 #pragma unroll
                 for (int k = 0; k < kMaxDetPerLink; ++k) {
                     if (k >= nd) break;
-                    const float z = sc * (x - dpos[k]);
+                    const int det = d.det_list[d0 + k];
+                    const int64_t qi = ((int64_t)s * d.D + det) * d.nb;
+                    const float gC = d.gQ[qi + sb] - (sb + 1 < d.nb ? d.gQ[qi + sb + 1] : 0.f);
+                    const float z = sc * (x - d.det_pos[det]);
                     const float sg = 1.0f / (1.0f + expf(-z));
-                    anew += gC[k] * sc * sg * (1.0f - sg);
+                    anew += gC * sc * sg * (1.0f - sg);
                 }
             }
             d.adj_ring[base + slot_of(r)] = anew;
@@ -1053,10 +1038,12 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     gu = g.sum(gu);
     gk = g.sum(gk);
     if (d.gm) gm = g.sum(gm);
+    // one non-returning atomic per accumulator: this group is the segment's only writer in the
+    // launch, so the sum is the plain accumulator + contribution, without a read held in registers
     if (gl == 0 && !init) {
-        d.gu[seg] = gu0 + gu;
-        d.gk[seg] = gk0 + gk;
-        if (d.gm) d.gm[seg] = gm0 + gm;
+        unsafeAtomicAdd(&d.gu[seg], gu);
+        unsafeAtomicAdd(&d.gk[seg], gk);
+        if (d.gm) unsafeAtomicAdd(&d.gm[seg], gm);
     }
 }
 
