@@ -246,11 +246,12 @@ int sim_gumbel_fast(sim_t *h, int32_t n, const uint32_t *words, float *out);
 int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
                 const int32_t *seq, int32_t *perm, int32_t *seg_off);
 
-/* Launch schedule: lanes per work item of the link-phase and reverse
- * kernels for rings of at most 128 slots (8, 16, 32 or 64; larger rings run
- * on a whole wavefront), and the floor of the node-phase lane group (8, 16,
- * 32 or 64: each node runs on the smallest group, not below the floor, that
- * holds its merge candidates and out-links).  Results do not depend on it. */
+/* Launch schedule: lanes G per work item of the link-phase and reverse
+ * kernels for rings of at most 128 slots (8, 16, 32 or 64; rings of at most
+ * 256 slots run on max(G, 16) lanes, at most 512 on max(G, 32), larger on a
+ * whole wavefront), and the floor of the node-phase lane group (8, 16, 32 or
+ * 64: each node runs on the smallest group, not below the floor, that holds
+ * its merge candidates and out-links).  Results do not depend on it. */
 int sim_set_schedule(sim_t *h, int g_link, int g_node, int g_rev);
 int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
 
