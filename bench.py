@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def byte_model(kind: str, S: int, L: int, Nn: int, O: int, T: int, vs: int, moves: int, launches: int) -> float:
+def byte_model(kind: str, S: int, L: int, Nn: int, O: int, T: int, vs: int, moves: int, launches: int,
+               R: int = None, vs_r: int = None, moves_r: int = None) -> float:
     """Algorithmic (compulsory) bytes per launch of each kernel kind, from the
     structure-of-arrays layout; each array counted once per launch.
       link: per segment 72 B (ring counters, link constants, bucket r/w,
@@ -41,12 +42,16 @@ def byte_model(kind: str, S: int, L: int, Nn: int, O: int, T: int, vs: int, move
             per head candidate 16 B, per mover 12 B, per origin 40 B.
       reverse: per segment 40 B, per agent 24 B (tape position and agent id,
             adjoint read + write, departure step).
-    `vs` = vehicle-steps of the forward, `moves` = transfers + exits + departures."""
+    `vs` = vehicle-steps of the forward, `moves` = transfers + exits + departures; R steps
+    are replayed (the first R of the horizon) with `vs_r` vehicle-steps and `moves_r` moves
+    (default: every step replayed once).  Every step is taped once, by the forward or by its
+    replay."""
+    if R is None:
+        R, vs_r, moves_r = T, vs, moves
     if kind == "link":
-        per_step = 72.0 * S * L
-        total = 2 * T * per_step + 2 * 8.0 * vs + 2 * 140.0 * moves + 8.0 * vs + 8.0 * S * L * T
+        total = (T + R) * 72.0 * S * L + 8.0 * (vs + vs_r) + 140.0 * (moves + moves_r) + 8.0 * vs + 8.0 * S * L * T
     elif kind == "node":
-        total = 2 * T * (24.0 * S * Nn + 64.0 * S * L + 40.0 * S * O) + 2 * (16.0 + 12.0) * moves
+        total = (T + R) * (24.0 * S * Nn + 64.0 * S * L + 40.0 * S * O) + (16.0 + 12.0) * (moves + moves_r)
     elif kind == "reverse":
         total = T * 40.0 * S * L + 24.0 * vs
     else:
@@ -371,7 +376,14 @@ def main():
     dom = max(kinds, key=lambda k: kinds[k][0])
     ms_tot, launches = kinds[dom]
     avg_ms = ms_tot / launches
-    bytes_launch = byte_model(dom, S, L, Nn, O, T, vs, moves, launches)
+    # the replayed steps of the pass (the windows before the taped ones), measured on a forward run
+    R = max(0, tm.get("node", (0.0, T))[1] - T)
+    fwd.reset()
+    fwd.step(R)
+    vs_r = int(fwd.vehicle_steps()[0])
+    cr = fwd.state()["counters"][0]
+    moves_r = cr["transfers"] + cr["exited"] + cr["departed"]
+    bytes_launch = byte_model(dom, S, L, Nn, O, T, vs, moves, launches, R, vs_r, moves_r)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None, "kernel": f"k_{dom}",
@@ -379,11 +391,13 @@ def main():
                 "kernel_ms": {k: [round(v[0], 3), v[1]] for k, v in tm.items()}}
 
     roofline["traffic"] = measured_traffic(f"k_{dom}", w.name)
-    # whole-pass figure with the per-unit model of the hot path: 92 B per agent-step on the network
-    # for forward + adjoint (28 B forward, 40 B replay with its tape, 24 B reverse), 68 B per head
-    # that moves and 48 B per link or origin and step in each forward sweep (forward and replay)
-    pass_bytes = 92.0 * vs + 2 * (68.0 * moves + 48.0 * (L + O) * T)
-    roofline["pass"] = {"model": "92 B/agent-step + 2 x (68 B/move + 48 B/(link|origin)-step)",
+    # whole-pass figure with the per-unit model of the hot path: per agent-step on the network 28 B
+    # forward, 12 B tape (written once, by the forward or by the replay), 24 B reverse, and 28 B for
+    # each replayed agent-step; 68 B per head that moves and 48 B per link or origin and step in each
+    # forward sweep (the forward and the replayed steps)
+    pass_bytes = 64.0 * vs + 28.0 * vs_r + 68.0 * (moves + moves_r) + 48.0 * (L + O) * (T + R)
+    roofline["pass"] = {"model": "64 B/agent-step + 28 B/replayed agent-step + 68 B/move + 48 B/(link|origin)-step, "
+                                 "forward and %d replayed steps" % R,
                         "bytes": int(pass_bytes), "achieved": round(pass_bytes / (ms_per_step * 1e-3) / 1e9, 2),
                         "frac": round(pass_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)}
 
