@@ -59,13 +59,25 @@ def byte_model(kind: str, S: int, L: int, Nn: int, O: int, T: int, vs: int, move
     return total / max(launches, 1)
 
 
-def kernel_source_digest() -> str:
-    """Digest of the kernel sources; a counter summary names the digest it was taken on."""
+def _code_only(src: str) -> str:
+    """C++ source without comments, trailing blanks and empty lines (what a counter depends on)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
+def kernel_source_digest(read=None) -> str:
+    """Digest of the kernel sources' code (comments ignored); a counter summary names the digest
+    it was taken on.  `read(name)` returns a source's text (default: the working tree's)."""
     import hashlib
+    if read is None:
+        def read(name):
+            with open(os.path.join(ROOT, "paper_2603_25068_amd", "csrc", name)) as fh:
+                return fh.read()
     h = hashlib.sha256()
     for f in ("sim_kernels.hip", "sim_internal.h"):
-        with open(os.path.join(ROOT, "paper_2603_25068_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        h.update(_code_only(read(f)).encode())
     return h.hexdigest()[:16]
 
 

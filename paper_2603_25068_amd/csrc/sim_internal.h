@@ -34,7 +34,7 @@ struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
     int32_t rate_bin_steps;          // steps per departure-rate bin (rate bins are whole numbers of steps)
-    int32_t g_link, g_node, g_rev;   // lanes per small segment / node floor / small reverse segment (16, 32, 64)
+    int32_t g_link, g_node, g_rev;   // lanes per small segment / node floor / small reverse segment (8-64)
     int32_t lc_n[kRingClasses];      // links per ring class, contiguous ids: <= kSmallRing slots, <= kMidRing, ...
     int32_t nd_begin[4], nd_n[4];    // node id ranges of the node kernel's 8-, 16-, 32- and 64-lane roles
     int64_t ring_total;

@@ -117,7 +117,7 @@ constexpr int kChoiceChunk = 16;   // out-links whose route entries and noise ar
 
 // ---------------------------------------------------------------------------
 // Lane groups: a work item (segment or node) is served by G consecutive
-// lanes of a wavefront (G = 16, 32 or 64), 256/G items per workgroup.  All
+// lanes of a wavefront (G = 8, 16, 32 or 64), 256/G items per workgroup.  All
 // cross-lane traffic stays inside the group (width-G shuffles, masked
 // ballots); loops that contain shuffles have group-uniform trip counts.
 // ---------------------------------------------------------------------------

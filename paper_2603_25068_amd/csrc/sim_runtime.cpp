@@ -100,8 +100,8 @@ struct sim_t {
     // mutable parameter buffers
     float *p_u = nullptr, *p_kappa = nullptr, *p_beta = nullptr, *p_alpha = nullptr, *p_cost = nullptr,
           *p_rates = nullptr, *p_capm = nullptr, *capacity_dev = nullptr;
-    // two tape sets: the reverse sweep of one window reads one while the replay of the window
-    // before it writes the other, on a second stream
+    // tape sets: the reverse sweep of one window reads one while replays of earlier windows write
+    // others, on their own streams; the recording forward fills the sets of the last windows
     struct TapeSet {
         float *pos = nullptr, *dstg = nullptr;
         int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *dst = nullptr;
