@@ -531,6 +531,28 @@ def test_tape_windows_do_not_change_gradients():
                 assert np.array_equal(ref[k], g[k]), (tw, timing, k)
 
 
+def test_straight_through_gradients_do_not_depend_on_recording_layout():
+    """The straight-through groups replay every window (their tape is written
+    only by replays): checkpoint interval and tape windows change nothing,
+    bit for bit, in any group."""
+    w = W.random_small(5, nx=4, ny=4, n_agents=500, rates=True, steps=240)
+    groups = ("free_speed", "jam_density", "rates", "beta", "cost", "alpha", "theta")
+    rng = np.random.default_rng(5)
+    ref, gQ = None, None
+    for ckpt, tw in ((24, 4), (40, 6), (17, 0)):
+        s = _sim(w, record=True, ckpt_every=ckpt, tape_windows=tw).rollout()
+        if gQ is None:
+            cnt, _ = s.observables()
+            gQ = rng.normal(size=cnt.shape).astype(np.float32)
+        g = s.backward(gQ=gQ, gT=[0.2], groups=groups)
+        if ref is None:
+            ref = g
+            assert np.abs(g["alpha"]).max() > 0 and np.abs(g["theta"]).max() > 0
+        else:
+            for k in groups:
+                assert np.array_equal(ref[k], g[k]), (ckpt, tw, k)
+
+
 def test_set_params_after_t0_ends_the_recording():
     """Parameters changed in the middle of a recorded rollout: the backward
     refuses (the replay would follow other parameters than the forward)."""
