@@ -480,26 +480,32 @@ def test_closed_links_hold_their_queues():
         _grad_close(go[k], gg[k][0], f"closed {k}")
 
 
-def test_forward_tape_gives_the_replayed_gradients():
+@pytest.mark.parametrize("S", [1, 2])
+def test_forward_tape_gives_the_replayed_gradients(S):
     """The recording forward writes the tape of its last windows, so the
     backward sweeps them without a replay (the final one partial here).  A
     second backward of the same rollout replays every window; a backward that
     also asks for capacity multipliers replays every window with the extra
-    tape.  All three give bitwise the same gradients."""
+    tape.  All three give bitwise the same gradients, for one scenario and for
+    two scenarios with their own seeds in one handle."""
     w = W.random_small(7, nx=4, ny=4, n_agents=500, rates=True, steps=280)
-    s = _sim(w, record=True, ckpt_every=30).rollout()
+    seeds = [70 + k for k in range(S)]
+    s = _sim(w, n_scenarios=S, seeds=seeds, record=True, ckpt_every=30, tape_windows=4).rollout()
     cnt, _ = s.observables()
     gQ = np.random.default_rng(7).normal(size=cnt.shape).astype(np.float32)
+    gT = [0.3, -0.1][:S]
     groups = ("free_speed", "jam_density", "rates")
-    g1 = s.backward(gQ=gQ, gT=[0.3], groups=groups)
-    g2 = s.backward(gQ=gQ, gT=[0.3], groups=groups)
-    g3 = s.backward(gQ=gQ, gT=[0.3], groups=groups + ("cap_mult",))
+    g1 = s.backward(gQ=gQ, gT=gT, groups=groups)
+    g2 = s.backward(gQ=gQ, gT=gT, groups=groups)
+    g3 = s.backward(gQ=gQ, gT=gT, groups=groups + ("cap_mult",))
     for k in groups:
         assert np.array_equal(g1[k], g2[k]) and np.array_equal(g1[k], g3[k]), k
-    o = Oracle(w, log=True).run()
-    go = o.backward(gQ=gQ[0].astype(np.float64), gT=0.3)
-    for k in groups:
-        _grad_close(go[k], g1[k][0], k)
+    for sc in range(S):
+        o = Oracle(w, log=True, seed=seeds[sc]).run()
+        _compare_state(o, s, scen=sc, ctx=f"scenario {sc}")
+        go = o.backward(gQ=gQ[sc].astype(np.float64), gT=gT[sc])
+        for k in groups:
+            _grad_close(go[k], g1[k][sc], f"{k} scenario {sc}")
 
 
 def test_tape_windows_do_not_change_gradients():
