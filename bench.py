@@ -284,7 +284,7 @@ def profile_pass(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed forward+adjoint passes")
+    ap.add_argument("--steps", type=int, default=10, help="timed forward+adjoint passes")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="metro", choices=["metro", "grid", "small"])
     ap.add_argument("--sim-steps", type=int, default=None, help="override simulated steps per pass")
