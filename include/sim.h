@@ -45,15 +45,15 @@ enum {
 /* Parameter groups (sim_set_params / sim_backward).  Per link: [S x n_links];
  * rates: [S x n_origins x n_rate_bins]. */
 enum sim_param {
-    SIM_P_U = 0,         /* free-flow speed u (m/s), Methods eq. newell_model */
-    SIM_P_KAPPA = 1,     /* jam density kappa per lane (veh/m), same */
-    SIM_P_BETA = 2,      /* route-choice weight beta, SI-B link utility */
-    SIM_P_ALPHA = 3,     /* merge priority alpha, SI-B merge choice */
-    SIM_P_COST = 4,      /* link cost c, SI-B link utility */
-    SIM_P_RATES = 5,     /* departure rate per (origin, time bin), veh/s */
-    SIM_P_CAP_MULT = 6,  /* outflow capacity multiplier per link */
-    SIM_P_THETA = 7,     /* destination-time coefficient theta of the link utility (gradient only: [S],
-                            one value per scenario; the value itself is sim_config.dest_logit_coef) */
+    SIM_P_U = 0,          /* free-flow speed u (m/s), Methods eq. newell_model */
+    SIM_P_KAPPA = 1,      /* jam density kappa per lane (veh/m), same */
+    SIM_P_BETA = 2,       /* route-choice weight beta, SI-B link utility */
+    SIM_P_ALPHA = 3,      /* merge priority alpha, SI-B merge choice */
+    SIM_P_COST = 4,       /* link cost c, SI-B link utility */
+    SIM_P_THETA_DEST = 5, /* destination-time coefficient theta of the link utility (gradient only: [S],
+                             one value per scenario; the value itself is sim_config.dest_logit_coef) */
+    SIM_P_RATES = 6,      /* departure rate per (origin, time bin), veh/s */
+    SIM_P_CAP_MULT = 7,   /* outflow capacity multiplier per link */
     SIM_P_COUNT = 8
 };
 
@@ -175,7 +175,7 @@ int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device);
  * dL_dttt [S] double, dL_dpos [S x n_agents] float (final positions of
  * agents on the network).  grads[k] (for each bit k set in param_mask,
  * every group below SIM_P_COUNT) receives dL/d(group k), overwritten, float,
- * same layout as sim_set_params (SIM_P_THETA: [S]).  Rates reach the loss
+ * same layout as sim_set_params (SIM_P_THETA_DEST: [S]).  Rates reach the loss
  * through departure-time grafting and capacity multipliers through
  * admission-time grafting: a vehicle released, or let through a link's
  * outflow token bucket, carries the time at which its release count or

@@ -1407,7 +1407,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             fail(SIM_ESTATE, "sim_backward needs a recorded rollout from t = 0 (at most max_steps)");
         if (param_mask >> SIM_P_COUNT) fail(SIM_EINVAL, "unknown gradient group in param_mask");
         const bool want_m = (param_mask & (1u << SIM_P_CAP_MULT)) != 0;
-        const uint32_t ste_mask = (1u << SIM_P_BETA) | (1u << SIM_P_COST) | (1u << SIM_P_ALPHA) | (1u << SIM_P_THETA);
+        const uint32_t ste_mask = (1u << SIM_P_BETA) | (1u << SIM_P_COST) | (1u << SIM_P_ALPHA) | (1u << SIM_P_THETA_DEST);
         const bool want_ste = (param_mask & ste_mask) != 0;
         if (want_ste && !(h->d.tau > 0.0)) fail(SIM_EINVAL, "straight-through gradients need gumbel_tau > 0");
         h->d.tape_dstg = want_m ? h->tape_dstg_buf : nullptr;
@@ -1530,9 +1530,9 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             sim::launch_gather_links(pg.second, h->linv_dev, h->grad_tmp, h->S, h->L, st);
             HIPCHK(hipMemcpyAsync(grads[pg.first], h->grad_tmp, SL * 4, kout, st));
         }
-        if (param_mask & (1u << SIM_P_THETA)) {
+        if (param_mask & (1u << SIM_P_THETA_DEST)) {
             sim::launch_theta_sum(d, h->grad_tmp, st);
-            HIPCHK(hipMemcpyAsync(grads[SIM_P_THETA], h->grad_tmp, (size_t)h->S * 4, kout, st));
+            HIPCHK(hipMemcpyAsync(grads[SIM_P_THETA_DEST], h->grad_tmp, (size_t)h->S * 4, kout, st));
         }
         if (param_mask & (1u << SIM_P_RATES)) {
             const size_t nr = (size_t)h->S * h->O * h->B;

@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsim.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PARAMS = {"free_speed": 0, "jam_density": 1, "beta": 2, "alpha": 3, "cost": 4, "rates": 5, "cap_mult": 6,
-          "theta": 7}   # theta: gradient only (its value is the config's dest_logit_coef)
+PARAMS = {"free_speed": 0, "jam_density": 1, "beta": 2, "alpha": 3, "cost": 4, "theta": 5, "rates": 6,
+          "cap_mult": 7}   # theta: gradient only (its value is the config's dest_logit_coef)
 N_GROUPS = 8
 PARAM_NAMES = {v: k for k, v in PARAMS.items()}
 COUNTER_NAMES = ("released", "departed", "on_net", "exited", "transfers", "ties", "stuck", "order_viol")

@@ -440,6 +440,27 @@ def merge_toy(alpha=(1.0, 1.0), length: float = 100.0, speed: float = 10.0, seed
     return Workload("merge_toy", net, dem, cfg)
 
 
+def route_merge_toy(seed: int = 0, alpha=(1.0, 1.0), tau: float = 0.5) -> Workload:
+    """A route choice whose chosen link is contested.  Links 0: 0->2 and
+    1: 1->2 (one lane, 100 m) end at node 2, whose out-links 2: 2->3 and
+    3: 2->4 lead on to node 5 through 4: 3->5 and 5: 4->5.  Agent 0 is placed
+    at the end of link 0 and bound for node 5, so it chooses between links 2
+    and 3 (distinct beta, cost and times to node 5); agent 1 is placed at the
+    end of link 1 and bound for node 3, which only link 2 reaches.  When agent
+    0 picks link 2, the two heads compete for its single entry slot."""
+    net = Network(
+        n_nodes=6, tail=_i32([0, 1, 2, 2, 3, 4]), head=_i32([2, 2, 3, 4, 5, 5]), lanes=_i32([1] * 6),
+        length=_f32([100.0, 100.0, 120.0, 90.0, 200.0, 260.0]),
+        free_speed=_f32([10.0, 10.0, 10.0, 12.0, 10.0, 13.0]),
+        jam_density=_f32([JAM_DENSITY_PER_LANE] * 6), capacity=_f32([10.0] * 6),
+        beta=_f32([0.0, 0.0, 1.2, 0.7, 0.0, 0.0]), alpha=_f32(list(alpha) + [1.0] * 4),
+        cost=_f32([1.0, 1.0, 1.5, 0.8, 1.0, 1.0]),
+        origin_node=_i32([0]), detector_link=_i32([2]), detector_pos=_f32([60.0]))
+    dem = Demand(agent_origin=_i32([0, 0]), agent_dest=_i32([5, 3]), ready_time=_f32([1e9, 1e9]))
+    cfg = Config(dt=1.0, steps=1, count_bin_steps=1, ckpt_every=60, seed=seed, gumbel_tau=tau)
+    return Workload("route_merge_toy", net, dem, cfg)
+
+
 def hub(n_spokes: int = 8, lanes: int = 8, long_len: float = 1500.0, short_len: float = 60.0,
         n_agents: int = 8000, steps: int = 600, capacity: float = 0.05, seed: int = 3) -> Workload:
     """The kernels' largest cases in one network.  A hub node 0 with n_spokes

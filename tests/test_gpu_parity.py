@@ -334,6 +334,26 @@ def test_merge_priority_gradient_closed_form_gpu(alpha, seed):
     assert np.all(g["beta"] == 0.0) and np.all(g["cost"] == 0.0) and np.all(g["theta"] == 0.0)
 
 
+@pytest.mark.parametrize("seed,alpha", [(3, (1.0, 1.0)), (5, (1.0, 1.0)), (10, (1.3, 0.6)), (19, (0.8, 1.1))])
+def test_route_choice_straight_through_closed_form_gpu(seed, alpha):
+    """The GPU's beta, cost, theta and alpha gradients through a contested
+    route choice equal the hand derivation from SI-B's estimators (the
+    oracle's own pin), so the kernel's relaxed route weight is checked
+    independently of the oracle."""
+    from closed_forms import route_merge_closed_form
+    w = W.route_merge_toy(seed=seed, alpha=alpha)
+    s = _sim(w, record=True, max_steps=1)
+    s.place([0, 1], [0, 1], [100.0, 100.0])
+    s.step(1)
+    adj = np.float32([0.7, -1.3])
+    expect, win = route_merge_closed_form(w, seed, adj.astype(np.float64))
+    st = s.state()
+    assert st["link"][0][win] == 2 and st["link"][0][1 - win] == 1 - win
+    g = s.backward(gx=adj[None], groups=("alpha", "beta", "cost", "theta"))
+    for k in ("beta", "cost", "alpha", "theta"):
+        np.testing.assert_allclose(g[k][0], expect[k], rtol=1e-5, atol=1e-6 * np.abs(expect[k]).max(), err_msg=k)
+
+
 def test_rollout_autograd_function_matches_backward():
     """The torch.autograd wrapper returns exactly what a direct backward call
     on the same recorded rollout returns, for every group it was given."""

@@ -11,9 +11,10 @@ import numpy as np
 import pytest
 
 import oracle
+from closed_forms import route_merge_closed_form
 from oracle import ST_EXITED, ST_ON, ST_QUEUED, ST_WAIT, Oracle
 from paper_2603_25068_amd import workloads as W
-from tests import dense_paper
+from tests import dense_form
 
 
 # ---------------------------------------------------------------------------
@@ -404,35 +405,37 @@ def _dense_case(seed):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
-def test_sparse_equals_dense_paper_form(seed):
+def test_sparse_equals_dense_form(seed):
+    """The oracle's sparse per-agent step equals the dense agent-by-link form
+    of SI-A/SI-B (tests/dense_form.py) step by step: same links, same
+    positions to 1e-9."""
     w, agents, links, pos = _dense_case(seed)
     net = w.net
     n_ag, Lk = len(agents), net.n_links
     o = Oracle(w, variant="f64", seed=seed)
     o.place(agents, links, pos)
-    M = 99999.0
-    X = np.full((n_ag, Lk), -M)
-    X[np.arange(n_ag), links] = pos.astype(np.float64)
-    A = (net.head[:, None] == net.tail[None, :]).astype(float)
-    outs = {v: [j for j in range(Lk) if net.tail[j] == v] for v in range(net.n_nodes)}
+    P = np.full((n_ag, Lk), np.nan)
+    P[np.arange(n_ag), links] = pos.astype(np.float64)
+    # the route-choice draw of a candidate link is word c of the agent's counter, c = the link's
+    # place among its tail node's out-links (caller order)
     cidx = np.zeros(Lk, int)
-    for v, js in outs.items():
-        for c, j in enumerate(js):
+    for v in range(net.n_nodes):
+        for c, j in enumerate(np.flatnonzero(net.tail == v)):
             cidx[j] = c
     u = net.free_speed.astype(np.float64)
     kap = net.jam_density.astype(np.float64)
     Ln = net.length.astype(np.float64)
     for t in range(w.cfg.steps):
-        Xf = dense_paper.car_following(X, u, kap, Ln, 1.0, 1.0, M)
-        G = np.array([[oracle.gumbel(seed, int(agents[i]), t, 0, int(cidx[m])) for m in range(Lk)]
-                      for i in range(n_ag)])
-        Gm = np.array([[oracle.gumbel(seed, int(agents[i]), t, 1, 0) for i in range(n_ag)] for m in range(Lk)])
-        X = dense_paper.node_model(Xf, A, net.alpha.astype(float), net.beta.astype(float),
-                                   net.cost.astype(float), kap, Ln, 1.0, M, G, Gm)
+        Xh = dense_form.newell_dense(P, u, kap, Ln, 1.0, 1.0)
+        g_route = np.array([[oracle.gumbel(seed, int(agents[i]), t, 0, int(cidx[m])) for m in range(Lk)]
+                            for i in range(n_ag)])
+        g_merge = np.array([oracle.gumbel(seed, int(agents[i]), t, 1, 0) for i in range(n_ag)])
+        P = dense_form.node_dense(Xh, net.tail, net.head, net.alpha.astype(float), net.beta.astype(float),
+                                  net.cost.astype(float), kap, Ln, 1.0, g_route, g_merge)
         o.step()
         st = o.state()
-        dl = np.argmax(X > -1.0, axis=1)
-        dx = X[np.arange(n_ag), dl]
+        dl = np.array([np.flatnonzero(~np.isnan(P[i]))[0] for i in range(n_ag)])
+        dx = P[np.arange(n_ag), dl]
         assert np.array_equal(st["link"][agents], dl), f"step {t}"
         np.testing.assert_allclose(st["pos"][agents], dx, rtol=0, atol=1e-9)
 
@@ -709,6 +712,28 @@ def test_merge_priority_gradient_closed_form(alpha, seed):
     assert g["alpha"][win] == pytest.approx(expect, rel=1e-9)
     assert g["alpha"][lose] == pytest.approx(-expect, rel=1e-9)
     assert np.all(g["beta"] == 0.0) and np.all(g["cost"] == 0.0)
+
+
+@pytest.mark.parametrize("seed,alpha", [(3, (1.0, 1.0)), (5, (1.0, 1.0)), (10, (1.3, 0.6)), (19, (0.8, 1.1))])
+def test_route_choice_straight_through_closed_form(seed, alpha):
+    """The route-choice part of the straight-through estimator (SI-B eqs.
+    softmax, gumbel, straigththrough) against the hand derivation above: the
+    oracle's beta, cost, theta and alpha gradients equal it to 1e-9, so a
+    dropped noise term, temperature or utility term in the relaxed route
+    weight would show here (the chosen link is contested, so Gamma != 0)."""
+    w = W.route_merge_toy(seed=seed, alpha=alpha)
+    o = Oracle(w, variant="f64", log=True)
+    o.place([0, 1], [0, 1], [100.0, 100.0])
+    o.run(1)
+    st = o.state()
+    adj = np.array([0.7, -1.3])
+    expect, win = route_merge_closed_form(w, seed, adj)
+    assert st["link"][win] == 2 and st["pos"][win] == 0.0
+    assert st["link"][1 - win] == 1 - win and st["pos"][1 - win] == 100.0
+    g = o.backward(gx=adj)
+    for k in ("beta", "cost", "alpha", "theta"):
+        assert np.abs(expect[k]).max() > 0, k
+        np.testing.assert_allclose(g[k], expect[k], rtol=1e-9, atol=1e-12 * np.abs(expect[k]).max(), err_msg=k)
 
 
 def test_hub_workload_reaches_the_kernel_limits():
