@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 ST_WAIT, ST_QUEUED, ST_ON, ST_EXITED = 0, 1, 2, 3
+TIE_CHOICE, TIE_MERGE, TIE_ARRIVE, TIE_VACANT, TIE_DETECT = 0, 1, 2, 3, 4
 COUNTER_NAMES = ("released", "departed", "on_net", "exited", "transfers", "ties", "stuck", "order_viol")
 
 
@@ -94,6 +95,11 @@ def _lib(variant: str):
     L.orc_gumbel.restype = dbl
     L.orc_uniform.argtypes = [C.c_uint64, i32, i32, i32, i32]
     L.orc_uniform.restype = dbl
+    L.orc_tie_count.argtypes = [vp]
+    L.orc_tie_count.restype = i64
+    L.orc_tie_log.argtypes = [vp, vp]
+    L.orc_tie_stats.argtypes = [vp, vp, vp, vp]
+    L.orc_adopt_ties.argtypes = [vp, vp, i64]
     _LIBS[variant] = L
     return L
 
@@ -126,7 +132,8 @@ class Oracle:
     and rates (per origin x bin), and `seed` the Philox key."""
 
     def __init__(self, w, params: Optional[dict] = None, seed: Optional[int] = None,
-                 variant: str = "f32", log: bool = False, steps: Optional[int] = None):
+                 variant: str = "f32", log: bool = False, steps: Optional[int] = None,
+                 adopt: Optional[np.ndarray] = None):
         self.w = w
         self._L = _lib(variant)
         net, dem, cfg = w.net, w.dem, w.cfg
@@ -181,6 +188,9 @@ class Oracle:
         self._h = self._L.orc_create(C.byref(ins))
         if log:
             self._L.orc_set_logging(self._h, 1)
+        if adopt is not None:
+            a = np.ascontiguousarray(adopt, np.int32).reshape(-1, 5)
+            self._L.orc_adopt_ties(self._h, _ptr(a), len(a))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -241,6 +251,22 @@ class Oracle:
         ttt = C.c_double(0.0)
         self._L.orc_get_counts(self._h, _ptr(out), C.byref(ttt))
         return out, float(ttt.value)
+
+    def tie_log(self) -> np.ndarray:
+        """Near-tie events so far, [n x 5] int32 rows (t, class, id, aux, decision); classes
+        TIE_CHOICE, TIE_MERGE, TIE_ARRIVE, TIE_VACANT, TIE_DETECT."""
+        n = int(self._L.orc_tie_count(self._h))
+        out = np.zeros((n, 5), np.int32)
+        if n:
+            self._L.orc_tie_log(self._h, _ptr(out))
+        return out
+
+    def tie_stats(self) -> dict:
+        """Decisions taken from the adopted log, near ties it did not hold, and adopted
+        decisions that differ from this run's own."""
+        a, u, f = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        self._L.orc_tie_stats(self._h, C.byref(a), C.byref(u), C.byref(f))
+        return {"adopted": int(a.value), "unmatched": int(u.value), "flipped": int(f.value)}
 
     def dist_table(self):
         nd = self._L.orc_n_dest(self._h)

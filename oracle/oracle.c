@@ -212,6 +212,11 @@ typedef struct orc {
     pos_t *xhat;
     double *mkey, *bacc;
     /* frozen surrogate base values */
+    /* near-tie log: (t, class, id, aux, decision) per event; see orc_tie_log */
+    pos_t *tietol;      /* per link: margin below which a position threshold is a near tie */
+    VEC(int32_t) ties;
+    const int32_t *adopt; int64_t adopt_n;   /* another run's log, sorted, whose decisions are taken */
+    int64_t n_adopted, n_unmatched, n_flipped;
     int have_base;
     double *base_x1;    /* per cf record: x' (before cap) in the base surrogate */
     double *base_xhat;  /* per cf record */
@@ -360,6 +365,8 @@ orc_t *orc_create(const orc_inputs *in)
         o->spacing[j] = (pos_t)in->platoon / (pos_t)o->kappa[j];
         o->thr[j] = (pos_t)o->length[j] - (pos_t)0.01;
     }
+    o->tietol = malloc(sizeof(pos_t) * (size_t)(L + 1));
+    for (int32_t j = 0; j < L; ++j) o->tietol[j] = (pos_t)(o->length[j] * 1e-5f);
 
     /* CSR adjacency, link order within each node */
     o->out_off = calloc((size_t)Nn + 1, 4); o->in_off = calloc((size_t)Nn + 1, 4);
@@ -449,7 +456,7 @@ void orc_destroy(orc_t *o)
         o->bucket_off, o->bucket, o->rank, o->leader_of, o->branch, o->capped, o->choice, o->won,
         o->head_cnt, o->slots, o->cfidx, o->xhat, o->mkey, o->bacc, o->cf.p, o->mv.p, o->smp.p, o->steps.p, o->capf.p,
         o->chs.p, o->chl.p, o->chr.p, o->chg.p, o->mgs.p, o->mgc.p, o->mgmv.p, o->mgg.p, o->chidx, o->base_pi, o->base_pim,
-        o->base_x1, o->base_xhat, o->base_psi, o->base_sig };
+        o->base_x1, o->base_xhat, o->base_psi, o->base_sig, o->tietol, o->ties.p, (void *)o->adopt };
     for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
     free(o);
 }
@@ -503,6 +510,75 @@ static double rate_overlap(double b0, double b1, double t0, double t1)
     return hi > lo ? hi - lo : 0.0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Near ties.  Decisions taken on values that lie closer together than the  */
+/* rounding of another precision could move them are logged as             */
+/* (t, class, id, aux, decision):                                           */
+/*   TIE_CHOICE  route choice whose best and second score differ by less    */
+/*               than 1e-12 (1 + |best|): id agent, aux chosen link;        */
+/*   TIE_MERGE   merge keys of one target link adjacent in key order that   */
+/*               differ by less than 1e-12 (1 + |key|): id the agent ranked */
+/*               first of the pair, aux the target link;                    */
+/*   TIE_ARRIVE  |x_hat - (L - 0.01)| < 1e-5 L for an agent not at the cap  */
+/*               L: id agent, aux link, decision arrived;                   */
+/*   TIE_VACANT  |x_hat - dn/kappa| < 1e-5 L: id agent, aux link, decision  */
+/*               occupies an entry slot;                                    */
+/*   TIE_DETECT  at a sampling step, |x - o| < 1e-5 L for an agent on the   */
+/*               detector's link below L - 0.01: id detector, aux agent,    */
+/*               decision counted.                                          */
+/* With another run's log attached (orc_adopt_ties), a position threshold   */
+/* whose own margin is below half the tolerance takes the decision that log */
+/* holds for the same (t, class, id, aux); none found counts as unmatched.  */
+/* ------------------------------------------------------------------------ */
+enum { TIE_CHOICE = 0, TIE_MERGE = 1, TIE_ARRIVE = 2, TIE_VACANT = 3, TIE_DETECT = 4 };
+
+static int cmp_tie(const void *a, const void *b)
+{
+    const int32_t *x = a, *y = b;
+    for (int k = 0; k < 4; ++k) if (x[k] != y[k]) return x[k] < y[k] ? -1 : 1;
+    return 0;
+}
+
+static void tie_push(orc_t *o, int32_t cls, int32_t id, int32_t aux, int32_t dec)
+{
+    VPUSH(o->ties, o->t); VPUSH(o->ties, cls); VPUSH(o->ties, id); VPUSH(o->ties, aux); VPUSH(o->ties, dec);
+}
+
+/* decision `own` of a position threshold at margin m (tolerance tol) */
+static int tie_threshold(orc_t *o, int32_t cls, int32_t id, int32_t aux, int own, pos_t m, pos_t tol)
+{
+    pos_t am = m < 0 ? -m : m;
+    if (!(am < tol)) return own;
+    int dec = own;
+    if (o->adopt_n > 0 && am < tol / 2) {
+        int32_t key[4] = { o->t, cls, id, aux };
+        const int32_t *f = bsearch(key, o->adopt, (size_t)o->adopt_n, 5 * sizeof(int32_t), cmp_tie);
+        if (f) { dec = f[4]; o->n_adopted++; o->n_flipped += dec != own; }
+        else o->n_unmatched++;
+    }
+    tie_push(o, cls, id, aux, dec);
+    return dec;
+}
+
+int64_t orc_tie_count(const orc_t *o) { return o->ties.n / 5; }
+void orc_tie_log(const orc_t *o, int32_t *out) { if (o->ties.n) memcpy(out, o->ties.p, 4 * (size_t)o->ties.n); }
+void orc_tie_stats(const orc_t *o, int64_t *adopted, int64_t *unmatched, int64_t *flipped)
+{
+    *adopted = o->n_adopted;
+    *unmatched = o->n_unmatched;
+    *flipped = o->n_flipped;
+}
+/* Take the decisions of another run's near-tie log (n records of 5 int32). */
+void orc_adopt_ties(orc_t *o, const int32_t *log, int64_t n)
+{
+    free((void *)o->adopt);
+    int32_t *c = malloc(sizeof(int32_t) * 5 * (size_t)(n > 0 ? n : 1));
+    if (n > 0) memcpy(c, log, sizeof(int32_t) * 5 * (size_t)n);
+    qsort(c, (size_t)n, 5 * sizeof(int32_t), cmp_tie);
+    o->adopt = c;
+    o->adopt_n = n;
+}
+
 /* Route choice of one agent standing at node v, coming from link `from`
  * (-1 for an origin queue).  Returns the chosen link, or CH_STUCK. */
 static int32_t choose(orc_t *o, int32_t a, int32_t v, int32_t from)
@@ -525,7 +601,10 @@ static int32_t choose(orc_t *o, int32_t a, int32_t v, int32_t from)
         else if (s > second) second = s;
         if (o->log_on) { VPUSH(o->chl, m); VPUSH(o->chr, tff + dm); VPUSH(o->chg, g); cr.n++; }
     }
-    if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) o->ctr[5]++;
+    if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) {
+        o->ctr[5]++;
+        tie_push(o, TIE_CHOICE, a, arg, arg);
+    }
     if (o->log_on) { cr.chosen = arg; o->chidx[a] = o->chs.n; VPUSH(o->chs, cr); }
     return arg;
 }
@@ -624,8 +703,14 @@ int orc_step(orc_t *o)
                 int32_t p = o->bucket[b0 + r - 1];
                 if (o->xhat[p] < o->xhat[a]) o->ctr[7]++;
             }
-            if (o->xhat[a] >= o->thr[j] && h == r) h++;
-            if (o->xhat[a] <= o->spacing[j]) occ++;
+            int capped_now = o->xhat[a] == (pos_t)o->length[j];   /* exact at the cap: no tie */
+            int arrived = o->xhat[a] >= o->thr[j];
+            if (!capped_now)
+                arrived = tie_threshold(o, TIE_ARRIVE, a, j, arrived, o->xhat[a] - o->thr[j], o->tietol[j]);
+            int occupies = tie_threshold(o, TIE_VACANT, a, j, o->xhat[a] <= o->spacing[j],
+                                         o->xhat[a] - o->spacing[j], o->tietol[j]);
+            if (arrived && h == r) h++;
+            if (occupies) occ++;
         }
         o->head_cnt[j] = h;
         o->slots[j] = o->lanes[j] - occ > 0 ? o->lanes[j] - occ : 0;   /* free entry slots */
@@ -686,7 +771,10 @@ int orc_step(orc_t *o)
             }
             qsort(cand, (size_t)nc, sizeof(mcand), cmp_mcand);
             for (int32_t c = 0; c + 1 < nc; ++c)
-                if (cand[c].key - cand[c + 1].key < 1e-12 * (1.0 + fabs(cand[c].key))) o->ctr[5]++;
+                if (cand[c].key - cand[c + 1].key < 1e-12 * (1.0 + fabs(cand[c].key))) {
+                    o->ctr[5]++;
+                    tie_push(o, TIE_MERGE, cand[c].agent, m, 1);
+                }
             int32_t kwin = nc < o->slots[m] ? nc : o->slots[m];
             if (o->log_on && kwin > 0) {
                 mg_rec g = { m, nc, kwin, o->mgc.n };
@@ -801,7 +889,11 @@ int orc_step(orc_t *o)
                 int64_t c = o->E[j];
                 for (int32_t q = o->bucket_off[j]; q < o->bucket_off[j + 1]; ++q) {
                     int32_t i = o->bucket[q];
-                    if (o->pos[i] >= (pos_t)o->det_pos[d]) c++;
+                    int counted = o->pos[i] >= (pos_t)o->det_pos[d];
+                    if (o->pos[i] < o->thr[j])
+                        counted = tie_threshold(o, TIE_DETECT, d, i, counted, o->pos[i] - (pos_t)o->det_pos[d],
+                                                o->tietol[j]);
+                    if (counted) c++;
                     if (o->log_on) { smp_rec sm = { d, i, (double)o->pos[i] }; VPUSH(o->smp, sm); }
                 }
                 o->counts[(int64_t)d * in->n_count_bins + kb] = (double)(c - o->cprev[d]);

@@ -457,6 +457,85 @@ def test_position_precision_does_not_move_decisions(mk):
     assert np.array_equal(ca, cb) and ta == tb
 
 
+# A constructed near tie: on a 386.56 m link at 13.805375 m/s the float sum
+# of 28 steps reaches L - 0.01 while the exact (double) sum falls short of it
+# by 7e-6 m, so the two precisions let the vehicle leave one step apart.  The
+# float run logs the event (its margin is below 1e-5 L); the double run that
+# adopts the float run's log takes the float decision and then follows it.
+_FLIP_L, _FLIP_U, _FLIP_K = 386.5605773925781, 13.805375099182129, 28
+
+
+def _exit_step(o, T=200):
+    for t in range(T):
+        o.step()
+        if o.state()["status"][0] == ST_EXITED:
+            return t
+    return None
+
+
+def test_near_tie_is_logged_and_adopted_across_precisions():
+    x32 = np.float32(0)
+    for _ in range(_FLIP_K):
+        x32 = np.float32(x32 + np.float32(_FLIP_U))
+    thr32 = np.float32(np.float32(_FLIP_L) - np.float32(0.01))
+    x64 = _FLIP_K * float(np.float32(_FLIP_U))
+    thr64 = float(np.float32(_FLIP_L)) - 0.01
+    assert x32 >= thr32 and x64 < thr64          # the two precisions decide differently
+    w = W.line(n_links=1, length=_FLIP_L, speed=_FLIP_U, steps=200)
+    a = Oracle(w, variant="f32")
+    b = Oracle(w, variant="f64")
+    ea, eb = _exit_step(a), _exit_step(b)
+    assert ea == _FLIP_K and eb == _FLIP_K + 1    # it enters at 0 in step 0, then moves u per step
+    log = a.tie_log()
+    assert len(log) == 1 and list(log[0]) == [_FLIP_K, oracle.TIE_ARRIVE, 0, 0, 1]
+    c = Oracle(w, variant="f64", adopt=log)
+    assert _exit_step(c) == _FLIP_K
+    assert c.tie_stats() == {"adopted": 1, "unmatched": 0, "flipped": 1}
+
+
+def _precision_agreement(w, T, every):
+    """Float-position run logs its near ties; the double-position run adopts
+    them.  Integer state, counts and travel time must then agree exactly, and
+    positions within 1e-4 of the link length (they differ by rounding only)."""
+    a = Oracle(w, variant="f32")
+    b = Oracle(w, variant="f64")
+    ref = Oracle(w, variant="f32")
+    ref.run(T)
+    b = Oracle(w, variant="f64", adopt=ref.tie_log())
+    L = np.asarray(w.net.length, np.float64)
+    worst = 0.0
+    for k in range(0, T, every):
+        n = min(every, T - k)
+        a.step(n)
+        b.step(n)
+        sa, sb = a.state(), b.state()
+        for key in ("status", "link", "seq"):
+            assert np.array_equal(sa[key], sb[key]), f"{key} differs after step {k + n}"
+        on = sa["status"] == ST_ON
+        if on.any():
+            rel = np.abs(sa["pos"][on] - sb["pos"][on]) / L[sa["link"][on]]
+            worst = max(worst, float(rel.max()))
+    assert worst <= 1e-4
+    ca, ta = a.counts()
+    cb, tb = b.counts()
+    assert np.array_equal(ca, cb) and ta == tb
+    assert a.counters() == b.counters()
+    st = b.tie_stats()
+    assert st["unmatched"] == 0
+    return st, len(ref.tie_log())
+
+
+def test_precision_agreement_grid_full_horizon():
+    """32x32 lattice, 50k-agent pool, all 1,800 steps."""
+    _precision_agreement(W.grid_rates(), 1800, 100)
+
+
+def test_precision_agreement_metro_first_window():
+    """1M-agent metro network, first 300 steps (near ties do occur here)."""
+    st, n = _precision_agreement(W.metro(), 300, 100)
+    assert n > 0 and st["adopted"] > 0
+
+
 # ---------------------------------------------------------------------------
 # Adjoint == exact derivative of the frozen surrogate (central differences in
 # FP64), and closed-form gradients
