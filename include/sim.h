@@ -246,6 +246,24 @@ int sim_gumbel_fast(sim_t *h, int32_t n, const uint32_t *words, float *out);
 int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
                 const int32_t *seq, int32_t *perm, int32_t *seg_off);
 
+/* Allocation-free variant of sim_segsort, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, order and results as sim_segsort;
+ * it calls no allocating routine.  Its per-segment counters live in one fixed
+ * device array of the library per GPU (8 MiB, held until the process ends),
+ * so n_segments may be at most SIM_SEGSORT_NOALLOC_MAX_SEGMENTS (SIM_EINVAL
+ * beyond); segments hold at most 2048 keys, as in sim_segsort.  The array is
+ * cleared at the start of every call.  status: NULL -> the call waits for the
+ * handle's stream and returns SIM_EUNSUPPORTED if a segment is too long;
+ * otherwise a device int32 that receives 0, or 1 for that overflow, in
+ * stream order, and the call returns without waiting.  All calls on one GPU
+ * share the array: calls that may overlap on one GPU (other streams or
+ * handles not ordered with this one) race and must be serialised by the
+ * caller. */
+#define SIM_SEGSORT_NOALLOC_MAX_SEGMENTS (1 << 20)
+int sim_segsort_noalloc(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
+                        const int32_t *seq, int32_t *perm, int32_t *seg_off, int32_t *status);
+
 /* Launch schedule: lanes G per work item of the link-phase and reverse
  * kernels for rings of at most 128 slots (8, 16, 32 or 64; rings of at most
  * 256 slots run on max(G, 16) lanes, at most 512 on max(G, 32), larger on a

@@ -149,6 +149,16 @@ void launch_philox(int n, const uint32_t *ctr, const uint32_t *key, uint32_t *ou
 void launch_gumbel_fast(int n, const uint32_t *w, float *out, hipStream_t st);
 int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
                    int32_t *perm, int32_t *seg_off, int32_t *scratch, hipStream_t st);
+// allocation-free variant: counters in a fixed per-device array (at most
+// kNoAllocMaxSegments segments); status: device flag written in stream order
+// (nothing waited for), or NULL to wait and return 1 on a segment overflow.
+// Returns -2 for too many segments, -1 on a HIP failure or a device whose
+// array address was not taken (segsort_scratch_init, with it current).
+constexpr int kNoAllocMaxSegments = 1 << 20;
+constexpr int kMaxDevices = 64;
+int segsort_scratch_init(int device);
+int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
+                           int32_t *perm, int32_t *seg_off, int32_t *status, hipStream_t st);
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing,
                    hipStream_t st);

@@ -13,6 +13,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace sim {
 
 // ---------------------------------------------------------------------------
@@ -1536,19 +1538,86 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_lds_sort(const int32_t *of
     for (int i = tid; i < n; i += kSortThreads) perm[b + i] = (int32_t)k0[i];
 }
 
-int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq, int32_t *perm,
-                   int32_t *seg_off, int32_t *scratch, hipStream_t st)
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
-    int32_t *cnt = scratch, *cursor = scratch + (n_seg + 1), *err = scratch + 2 * (n_seg + 1);
-    if (hipMemsetAsync(scratch, 0, ((size_t)2 * (n_seg + 1) + 1) * 4, st) != hipSuccess) return -1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// The sort proper on caller-provided scratch: cnt and cursor [n_seg + 1],
+// err [1].  The scratch is cleared with a fill kernel (no memset node), and
+// nothing here waits for the device.
+static int enqueue_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
+                           int32_t *perm, int32_t *seg_off, int32_t *cnt, int32_t *cursor, int32_t *err,
+                           hipStream_t st)
+{
+    const int64_t nc = (int64_t)n_seg + 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, cnt, nc, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, (int64_t)1, 0);
     if (n > 0) hipLaunchKernelGGL(k_seg_hist, dim3((n + 255) / 256), dim3(256), 0, st, n, seg, cnt);
     hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, n_seg, cnt, seg_off, cursor);
     if (n > 0) hipLaunchKernelGGL(k_seg_scatter, dim3((n + 255) / 256), dim3(256), 0, st, n, seg, cursor, perm);
     hipLaunchKernelGGL(k_seg_lds_sort, dim3(n_seg), dim3(kSortThreads), 0, st, seg_off, pos, seq, perm, err);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+static int read_sort_flag(const int32_t *err, hipStream_t st)
+{
     int32_t e = 0;
     if (hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
     if (hipStreamSynchronize(st) != hipSuccess) return -1;
     return e ? 1 : 0;
+}
+
+int launch_segsort(int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq, int32_t *perm,
+                   int32_t *seg_off, int32_t *scratch, hipStream_t st)
+{
+    int32_t *cnt = scratch, *cursor = scratch + (n_seg + 1), *err = scratch + 2 * (n_seg + 1);
+    if (enqueue_segsort(n, n_seg, seg, pos, seq, perm, seg_off, cnt, cursor, err, st) != 0) return -1;
+    return read_sort_flag(err, st);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free segmented sort: its counters live in one fixed device
+// array per GPU instead of a per-call allocation.  The array's name is only
+// a host-side stand-in; its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current (segsort_scratch_init,
+// called when a handle is created) and used for every launch and copy.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) int32_t scratch[2 * (kNoAllocMaxSegments + 1) + 64];
+
+namespace {
+std::mutex g_scratch_mu;
+int32_t *g_scratch_ptr[kMaxDevices] = {};
+}
+
+int segsort_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return -1;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return 0;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) return -1;
+    int32_t *p = nullptr;
+    if (hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    g_scratch_ptr[device] = p;
+    return 0;
+}
+
+int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
+                           int32_t *perm, int32_t *seg_off, int32_t *status, hipStream_t st)
+{
+    if (n_seg < 1 || n_seg > kNoAllocMaxSegments) return -2;
+    int32_t *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device >= 0 && device < kMaxDevices) base = g_scratch_ptr[device];
+    }
+    if (!base) return -1;
+    int32_t *cnt = base, *cursor = base + (n_seg + 1), *flag = base + 2 * (kNoAllocMaxSegments + 1);
+    int32_t *err = status ? status : flag;
+    if (enqueue_segsort(n, n_seg, seg, pos, seq, perm, seg_off, cnt, cursor, err, st) != 0) return -1;
+    return status ? 0 : read_sort_flag(err, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -1161,6 +1161,9 @@ int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *
         HIPCHK(hipGetDeviceCount(&ndev));
         if (hip_device < 0 || hip_device >= ndev) fail(SIM_EINVAL, "bad device index");
         HIPCHK(hipSetDevice(hip_device));
+        // device address of the allocation-free sort's fixed scratch array, once per device
+        if (hip_device < sim::kMaxDevices && sim::segsort_scratch_init(hip_device) != 0)
+            fail(SIM_EDEVICE, "hipGetSymbolAddress of the sort scratch array failed");
         prepare_host(h, net, dem, cfg);
         allocate_device(h, cfg);
         *out = h;
@@ -1800,6 +1803,21 @@ int sim_segsort(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, con
         HIPCHK(hipStreamSynchronize(h->stream));
         (void)hipFree(scratch);
         if (rc != 0) fail(SIM_EUNSUPPORTED, "a segment exceeds the LDS sort capacity");
+    });
+}
+
+int sim_segsort_noalloc(sim_t *h, int32_t n, int32_t n_segments, const int32_t *seg, const float *pos,
+                        const int32_t *seq, int32_t *perm, int32_t *seg_off, int32_t *status)
+{
+    return guarded(h, [&] {
+        if (n < 0 || n_segments < 1) fail(SIM_EINVAL, "bad sizes");
+        if (n_segments > SIM_SEGSORT_NOALLOC_MAX_SEGMENTS)
+            fail(SIM_EINVAL, "n_segments above SIM_SEGSORT_NOALLOC_MAX_SEGMENTS");
+        if (n > 0 && (!seg || !pos || !seq || !perm || !seg_off)) fail(SIM_EINVAL, "null array");
+        const int rc = sim::launch_segsort_noalloc(h->device, n, n_segments, seg, pos, seq, perm, seg_off, status,
+                                                   h->stream);
+        if (rc < 0) fail(SIM_EDEVICE, "sort launch failed, or no scratch array address for this device");
+        if (rc > 0) fail(SIM_EUNSUPPORTED, "a segment exceeds the LDS sort capacity");
     });
 }
 

@@ -89,6 +89,7 @@ def lib():
         "sim_philox": ([vp, i32, vp, vp, vp], C.c_int),
         "sim_gumbel_fast": ([vp, i32, vp, vp], C.c_int),
         "sim_segsort": ([vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+        "sim_segsort_noalloc": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], C.c_int),
         "sim_set_schedule": ([vp, C.c_int, C.c_int, C.c_int], C.c_int),
         "sim_get_schedule": ([vp, vp, vp, vp], C.c_int),
         "sim_set_timing": ([vp, C.c_int], C.c_int),
@@ -119,7 +120,7 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_gumbel_fast", "sim_segsort",
-            "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
+            "sim_segsort_noalloc", "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
             "sim_set_full_state",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
             "srv_stats", "srv_destroy"]
@@ -367,6 +368,16 @@ class Simulator:
                                       C.c_void_p(seq.data_ptr()), C.c_void_p(perm.data_ptr()),
                                       C.c_void_p(off.data_ptr())))
         return perm, off
+
+    def segsort_noalloc(self, seg, pos, seq, n_segments: int, perm, seg_off, status=None):
+        """Allocation-free sort into caller tensors perm [n] and seg_off [n_segments + 1] (int32, on the
+        handle's device); status: optional int32 device tensor [1] that receives the overflow flag
+        without waiting (sim_segsort_noalloc)."""
+        n = seg.numel()
+        st = None if status is None else C.c_void_p(status.data_ptr())
+        self._chk(self._L.sim_segsort_noalloc(self._h, n, n_segments, C.c_void_p(seg.data_ptr()),
+                                              C.c_void_p(pos.data_ptr()), C.c_void_p(seq.data_ptr()),
+                                              C.c_void_p(perm.data_ptr()), C.c_void_p(seg_off.data_ptr()), st))
 
     def set_schedule(self, g_link: int, g_node: int, g_rev: int):
         self._chk(self._L.sim_set_schedule(self._h, g_link, g_node, g_rev))
