@@ -233,8 +233,9 @@ int sim_philox(sim_t *h, int32_t n, const uint32_t *ctr, const uint32_t *key, ui
  * route-choice and merge decisions on, evaluated on the device: for each of n
  * host words w, g = -log(-log U) with U = ((w >> 8) + 1/2) 2^-24 (the same U
  * as the double-precision draw).  out [n] host floats.  A decision is
- * taken on these values only when it wins by more than twice their largest
- * error; otherwise it is recomputed in double precision.  SIM_EINVAL for
+ * taken on these values only when it wins by a margin of 1e-4, five times
+ * the largest error of a difference of two of them (2e-5); otherwise it is
+ * recomputed in double precision.  SIM_EINVAL for
  * n < 0 or NULL arrays. */
 int sim_gumbel_fast(sim_t *h, int32_t n, const uint32_t *words, float *out);
 

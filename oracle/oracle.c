@@ -26,7 +26,7 @@
  *
  * Readings where the paper is silent (each is also listed in the design
  * notes of the repository):
- *  - order inside a step: phi = g(f(x)) (Results, "composition of f and g");
+ *  - order inside a step: phi = g(f(x)): the link model f, then the node model g (Results);
  *  - lanes: the leader of rank r is rank r - lanes; jam spacing dn/kappa per
  *    lane; a link has lanes - #(x <= dn/kappa) free entry slots (the paper's
  *    vacancy mask X_min > dn/kappa is the one-lane case);
