@@ -70,7 +70,9 @@ enum { SIM_WAIT = 0, SIM_QUEUED = 1, SIM_ON = 2, SIM_EXITED = 3 };
 /* Road network.  Host pointers; copied by sim_create.
  * tail/head: node ids in [0, n_nodes); lanes in [1, 8]; length, free_speed,
  * jam_density > 0; capacity >= 0 (veh/s/lane); beta/alpha/cost may be NULL
- * (defaults 0, 1, 1), cost > 0.  Origins are nodes with a FIFO departure
+ * (defaults 0, 1, 1), cost > 0.  An agent stands for sim_config.platoon
+ * vehicles, so a link passes at most capacity * lanes / platoon agents per
+ * second.  Origins are nodes with a FIFO departure
  * queue (the paper's virtual inflow links).  Detectors count crossings of
  * position detector_pos (0 < pos <= length - 0.01) on detector_link (SI-D). */
 typedef struct {
@@ -89,7 +91,8 @@ typedef struct {
  * agent_origin: index into origin_node; agent_dest: node id, reachable
  * from the origin.  Either ready_time (fixed departure times, seconds) or
  * rates [n_origins x n_rate_bins] (departure-rate mode; rate_bin_s must be a
- * whole number of steps).  In rate mode agents of an origin are released in
+ * whole number of steps; rates count agents, i.e. platoons, per second).  In
+ * rate mode agents of an origin are released in
  * agent-index order when the integrated rate crosses their queue index + 1. */
 typedef struct {
     int32_t n_agents;

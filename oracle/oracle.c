@@ -344,6 +344,9 @@ orc_t *orc_create(const orc_inputs *in)
     o->rspeed = dupa(in->route_speed ? in->route_speed : in->free_speed, 4 * (size_t)L);
     o->kappa = dupa(in->jam_density, 4 * (size_t)L);
     o->cap = dupa(in->capacity, 4 * (size_t)L);
+    /* an agent is a platoon of dn vehicles (Methods, Newell's model): a link
+     * passes capacity * lanes / dn agents per second */
+    for (int32_t j = 0; j < L; ++j) o->cap[j] = o->cap[j] / (float)in->platoon;
     o->beta = dupa(in->beta, 4 * (size_t)L);
     o->alpha = dupa(in->alpha, 4 * (size_t)L);
     o->cost = dupa(in->cost, 4 * (size_t)L);

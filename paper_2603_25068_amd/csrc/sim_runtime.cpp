@@ -739,6 +739,8 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     h->dt = cfg->dt;
     h->platoon = cfg->platoon;
     if (!(cfg->dt > 0) || cfg->platoon < 1) fail(SIM_EINVAL, "dt > 0 and platoon >= 1 required");
+    // an agent stands for `platoon` vehicles: the outflow bucket counts agents, capacity * lanes / platoon per second
+    for (float &q : h->capacity) q = q / (float)h->platoon;
     if (!h->fixed_mode) {
         const double k = h->rate_bin_s / h->dt;
         if (std::fabs(k - std::round(k)) > 1e-9) fail(SIM_EINVAL, "rate bins must be a whole number of steps");

@@ -546,6 +546,31 @@ def line(n_links: int = 3, length: float = 200.0, speed: float = 13.9, lanes: in
     return Workload(f"line{n_links}", net, dem, cfg)
 
 
+def with_platoon(w: Workload, dn: int, tau: float = 1.0) -> Workload:
+    """The same network, agent pool and horizon with platoons of dn vehicles
+    per agent and the step the paper ties to it, dt = tau * dn (Methods,
+    Newell's model; SI-E): steps, sampling and checkpoint intervals shrink by
+    dn, departure rates given in vehicles/s become agents/s (divided by dn).
+    Capacities stay in vehicles/s/lane (the library divides by dn)."""
+    from copy import deepcopy
+    v = deepcopy(w)
+    dt = float(tau) * dn
+    for name, val in (("steps", w.cfg.steps), ("count_bin_steps", w.cfg.count_bin_steps)):
+        if val % dn:
+            raise ValueError(f"{name} = {val} is not a multiple of the platoon size {dn}")
+    v.cfg.platoon = int(dn)
+    v.cfg.dt = dt
+    v.cfg.steps = w.cfg.steps // dn
+    v.cfg.count_bin_steps = w.cfg.count_bin_steps // dn
+    v.cfg.ckpt_every = max(1, w.cfg.ckpt_every // dn)
+    if v.dem.rates is not None:
+        if abs(v.dem.rate_bin_s / dt - round(v.dem.rate_bin_s / dt)) > 1e-9:
+            raise ValueError("rate bins must be a whole number of platoon steps")
+        v.dem.rates = _f32(v.dem.rates / np.float32(dn))
+    v.name = f"{w.name}_dn{dn}"
+    return v
+
+
 def random_small(seed: int, nx: int = 3, ny: int = 3, n_agents: int = 60, rates: bool = False,
                  steps: int = 240, lanes_max: int = 2) -> Workload:
     """Small random lattice with random lengths/lanes/speeds/params, used for
