@@ -216,6 +216,25 @@ int sim_get_stats(sim_t *h, int64_t *vehicle_steps);
 int sim_get_full_state(sim_t *h, void *blob, size_t cap, size_t *n);
 int sim_set_full_state(sim_t *h, const void *blob, size_t n);
 
+/* Near-tie log of the forward steps since the last sim_reset (or
+ * sim_set_full_state): decisions whose margin lies within rounding distance
+ * of the other outcome, where an implementation with another rounding of the
+ * same arithmetic (the double-precision Gumbel transform goes through the
+ * platform's log) could decide otherwise.  Records are int32[6] (scenario,
+ * step t, class, agent, link, decision), sorted; links in the caller's
+ * numbering.  Classes: SIM_TIE_CHOICE, a route choice whose best and second
+ * score differ by less than 1e-12 (1 + |best|): link = decision = the chosen
+ * link (SI-B eq. gumbel); SIM_TIE_MERGE, a merge candidate whose key exceeds
+ * another candidate's for the same target by less than 1e-12 (1 + |key|):
+ * agent = the candidate ranked first, link = the target, decision 1.
+ * Replays of the backward pass and autotuner probes append nothing.  *n
+ * receives the number of records logged; min(*n, cap, SIM_TIE_LOG_MAX) are
+ * copied to buf (host, may be NULL when cap = 0).  The device keeps the first
+ * SIM_TIE_LOG_MAX records only. */
+enum { SIM_TIE_CHOICE = 0, SIM_TIE_MERGE = 1 };
+#define SIM_TIE_LOG_MAX (1 << 16)
+int sim_get_tie_log(sim_t *h, int32_t *buf, int64_t cap, int64_t *n);
+
 /* Per (scenario, link) state, host arrays [S x n_links] (any may be NULL):
  * token bucket B, cumulative outflow E, next entry sequence number. */
 int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq);

@@ -100,6 +100,12 @@ def _lib(variant: str):
     L.orc_tie_log.argtypes = [vp, vp]
     L.orc_tie_stats.argtypes = [vp, vp, vp, vp]
     L.orc_adopt_ties.argtypes = [vp, vp, i64]
+    L.orc_set_tie_tolerance.argtypes = [vp, C.c_double]
+    L.orc_state_size.argtypes = [vp]
+    L.orc_state_size.restype = i64
+    L.orc_export_state.argtypes = [vp, vp]
+    L.orc_import_state.argtypes = [vp, vp, i64]
+    L.orc_import_state.restype = C.c_int
     _LIBS[variant] = L
     return L
 
@@ -133,7 +139,7 @@ class Oracle:
 
     def __init__(self, w, params: Optional[dict] = None, seed: Optional[int] = None,
                  variant: str = "f32", log: bool = False, steps: Optional[int] = None,
-                 adopt: Optional[np.ndarray] = None):
+                 adopt: Optional[np.ndarray] = None, tie_tolerance: Optional[float] = None):
         self.w = w
         self._L = _lib(variant)
         net, dem, cfg = w.net, w.dem, w.cfg
@@ -188,9 +194,18 @@ class Oracle:
         self._h = self._L.orc_create(C.byref(ins))
         if log:
             self._L.orc_set_logging(self._h, 1)
+        if tie_tolerance is not None:
+            self._L.orc_set_tie_tolerance(self._h, float(tie_tolerance))
         if adopt is not None:
             a = np.ascontiguousarray(adopt, np.int32).reshape(-1, 5)
             self._L.orc_adopt_ties(self._h, _ptr(a), len(a))
+
+    @staticmethod
+    def tie_log_from_library(records: np.ndarray, scenario: int = 0) -> np.ndarray:
+        """A library near-tie log (rows scenario, step, class, agent, link, decision) as this
+        oracle's adoptable log (rows step, class, id, aux, decision) for one scenario."""
+        r = np.asarray(records, np.int32).reshape(-1, 6)
+        return np.ascontiguousarray(r[r[:, 0] == scenario][:, 1:])
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -260,6 +275,20 @@ class Oracle:
         if n:
             self._L.orc_tie_log(self._h, _ptr(out))
         return out
+
+    def export_state(self) -> bytes:
+        """The whole forward state as this oracle's own blob (orc_export_state)."""
+        n = int(self._L.orc_state_size(self._h))
+        buf = C.create_string_buffer(n)
+        self._L.orc_export_state(self._h, buf)
+        return buf.raw
+
+    def import_state(self, blob: bytes):
+        """Continue from another oracle's exported state (same inputs and placed agents)."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        if self._L.orc_import_state(self._h, buf, len(blob)) != 0:
+            raise ValueError("state blob does not match this oracle's inputs")
+        return self
 
     def tie_stats(self) -> dict:
         """Decisions taken from the adopted log, near ties it did not hold, and adopted

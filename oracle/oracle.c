@@ -217,6 +217,8 @@ typedef struct orc {
     VEC(int32_t) ties;
     const int32_t *adopt; int64_t adopt_n;   /* another run's log, sorted, whose decisions are taken */
     int64_t n_adopted, n_unmatched, n_flipped;
+    double tie_rel;     /* relative margin of a route-choice or merge near tie (1e-12) */
+    int restored;       /* state imported at t > 0: no log of the past, no reverse sweep */
     int have_base;
     double *base_x1;    /* per cf record: x' (before cap) in the base surrogate */
     double *base_xhat;  /* per cf record */
@@ -368,6 +370,7 @@ orc_t *orc_create(const orc_inputs *in)
         o->spacing[j] = (pos_t)in->platoon / (pos_t)o->kappa[j];
         o->thr[j] = (pos_t)o->length[j] - (pos_t)0.01;
     }
+    o->tie_rel = 1e-12;
     o->tietol = malloc(sizeof(pos_t) * (size_t)(L + 1));
     for (int32_t j = 0; j < L; ++j) o->tietol[j] = (pos_t)(o->length[j] * 1e-5f);
 
@@ -531,7 +534,12 @@ static double rate_overlap(double b0, double b1, double t0, double t1)
 /*               decision counted.                                          */
 /* With another run's log attached (orc_adopt_ties), a position threshold   */
 /* whose own margin is below half the tolerance takes the decision that log */
-/* holds for the same (t, class, id, aux); none found counts as unmatched.  */
+/* holds for the same (t, class, id, aux); a near-tie route choice takes   */
+/* the link that log chose for the same (t, agent) if it is a candidate;   */
+/* a near-tie merge pair is swapped when that log ranked its second agent  */
+/* first.  None found counts as unmatched.  Such a log may come from a run */
+/* with other rounding of the same step (double positions, or a Gumbel    */
+/* transform through another log implementation).                          */
 /* ------------------------------------------------------------------------ */
 enum { TIE_CHOICE = 0, TIE_MERGE = 1, TIE_ARRIVE = 2, TIE_VACANT = 3, TIE_DETECT = 4 };
 
@@ -563,6 +571,28 @@ static int tie_threshold(orc_t *o, int32_t cls, int32_t id, int32_t aux, int own
     return dec;
 }
 
+/* the adopted log's record for (t, class, id), any aux, or NULL */
+static int cmp_tie3(const void *a, const void *b)
+{
+    const int32_t *x = a, *y = b;
+    for (int k = 0; k < 3; ++k) if (x[k] != y[k]) return x[k] < y[k] ? -1 : 1;
+    return 0;
+}
+
+static const int32_t *adopted3(const orc_t *o, int32_t cls, int32_t id)
+{
+    if (o->adopt_n <= 0) return NULL;
+    int32_t key[3] = { o->t, cls, id };
+    return bsearch(key, o->adopt, (size_t)o->adopt_n, 5 * sizeof(int32_t), cmp_tie3);
+}
+
+static const int32_t *adopted4(const orc_t *o, int32_t cls, int32_t id, int32_t aux)
+{
+    if (o->adopt_n <= 0) return NULL;
+    int32_t key[4] = { o->t, cls, id, aux };
+    return bsearch(key, o->adopt, (size_t)o->adopt_n, 5 * sizeof(int32_t), cmp_tie);
+}
+
 int64_t orc_tie_count(const orc_t *o) { return o->ties.n / 5; }
 void orc_tie_log(const orc_t *o, int32_t *out) { if (o->ties.n) memcpy(out, o->ties.p, 4 * (size_t)o->ties.n); }
 void orc_tie_stats(const orc_t *o, int64_t *adopted, int64_t *unmatched, int64_t *flipped)
@@ -571,6 +601,10 @@ void orc_tie_stats(const orc_t *o, int64_t *adopted, int64_t *unmatched, int64_t
     *unmatched = o->n_unmatched;
     *flipped = o->n_flipped;
 }
+/* Relative margin below which a route choice or merge pair counts as a near
+ * tie (default 1e-12).  Tests widen it to exercise adoption on ordinary
+ * decisions. */
+void orc_set_tie_tolerance(orc_t *o, double rel) { o->tie_rel = rel; }
 /* Take the decisions of another run's near-tie log (n records of 5 int32). */
 void orc_adopt_ties(orc_t *o, const int32_t *log, int64_t n)
 {
@@ -604,8 +638,27 @@ static int32_t choose(orc_t *o, int32_t a, int32_t v, int32_t from)
         else if (s > second) second = s;
         if (o->log_on) { VPUSH(o->chl, m); VPUSH(o->chr, tff + dm); VPUSH(o->chg, g); cr.n++; }
     }
-    if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) {
+    if (arg >= 0 && second > -INFINITY && best - second < o->tie_rel * (1.0 + fabs(best))) {
         o->ctr[5]++;
+        /* another run's decision at this near tie, if it is a candidate here */
+        const int32_t *f = adopted3(o, TIE_CHOICE, a);
+        if (f) {
+            int ok = 0;
+            for (int32_t k = o->out_off[v]; k < o->out_off[v + 1]; ++k) {
+                int32_t m = o->out_lnk[k];
+                if (m != f[4] || !(dist[o->head[m]] < INFINITY)) continue;
+                if (!o->in.allow_uturn && from >= 0 && o->head[m] == o->tail[from]) continue;
+                ok = 1;
+            }
+            if (ok) {
+                o->n_adopted++;
+                if (f[4] != arg) { o->n_flipped++; arg = f[4]; }
+            } else {
+                o->n_unmatched++;
+            }
+        } else if (o->adopt_n > 0) {
+            o->n_unmatched++;
+        }
         tie_push(o, TIE_CHOICE, a, arg, arg);
     }
     if (o->log_on) { cr.chosen = arg; o->chidx[a] = o->chs.n; VPUSH(o->chs, cr); }
@@ -774,8 +827,21 @@ int orc_step(orc_t *o)
             }
             qsort(cand, (size_t)nc, sizeof(mcand), cmp_mcand);
             for (int32_t c = 0; c + 1 < nc; ++c)
-                if (cand[c].key - cand[c + 1].key < 1e-12 * (1.0 + fabs(cand[c].key))) {
+                if (cand[c].key - cand[c + 1].key < o->tie_rel * (1.0 + fabs(cand[c].key))) {
                     o->ctr[5]++;
+                    /* another run that ranked the second of the pair first: take its order */
+                    if (o->adopt_n > 0) {
+                        int second_first = adopted4(o, TIE_MERGE, cand[c + 1].agent, m) != NULL;
+                        int first_first = adopted4(o, TIE_MERGE, cand[c].agent, m) != NULL;
+                        if (second_first && !first_first) {
+                            mcand tmp = cand[c]; cand[c] = cand[c + 1]; cand[c + 1] = tmp;
+                            o->n_adopted++; o->n_flipped++;
+                        } else if (first_first) {
+                            o->n_adopted++;
+                        } else {
+                            o->n_unmatched++;
+                        }
+                    }
                     tie_push(o, TIE_MERGE, cand[c].agent, m, 1);
                 }
             int32_t kwin = nc < o->slots[m] ? nc : o->slots[m];
@@ -965,6 +1031,63 @@ void orc_get_origin_state(const orc_t *o, double *D, int32_t *rel, int32_t *dep)
     }
 }
 int32_t orc_time(const orc_t *o) { return o->t; }
+
+/* ------------------------------------------------------------------------ */
+/* State hand-off (the paper's nowcast starts from a state X(T); Methods,   */
+/* "Optimization", and the nowcasting results): the whole forward state as  */
+/* one flat blob, and its import into an oracle created from the same       */
+/* inputs (and the same placed agents).  The blob holds, in order: t, N, L, */
+/* O, detectors, bins (int32); per agent status, link, seq, release step,   */
+/* release-time bin (int32), position (pos_t), release time (double); per   */
+/* origin release and departure pointers (int32), accumulator (double); per */
+/* link next sequence (int32), B, dB (double), E (int64); per detector the  */
+/* last sample (int64) and its counts (double), travel time (double) and    */
+/* the eight counters (int64).  An imported oracle keeps no decision log of */
+/* the past, so it cannot run the reverse sweep (orc_backward fails).       */
+/* ------------------------------------------------------------------------ */
+typedef struct { char *p; size_t n; int wr; } blob_t;
+static void bput(blob_t *b, void *x, size_t n)
+{
+    if (b->p) { if (b->wr) memcpy(b->p + b->n, x, n); else memcpy(x, b->p + b->n, n); }
+    b->n += n;
+}
+static size_t state_io(orc_t *o, char *p, int wr)
+{
+    const orc_inputs *in = &o->in;
+    int32_t N = in->n_agents, L = in->n_links, O = in->n_origins, Dd = in->n_detectors, nb = in->n_count_bins;
+    blob_t b = { p, 0, wr };
+    int32_t hdr[6] = { o->t, N, L, O, Dd, nb };
+    bput(&b, hdr, sizeof hdr);
+    if (p && !wr) o->t = hdr[0];
+    bput(&b, o->status, 4 * (size_t)N); bput(&b, o->link, 4 * (size_t)N); bput(&b, o->seq, 4 * (size_t)N);
+    bput(&b, o->rel_t, 4 * (size_t)N); bput(&b, o->tstar_bin, 4 * (size_t)N);
+    bput(&b, o->pos, sizeof(pos_t) * (size_t)N); bput(&b, o->tstar, 8 * (size_t)N);
+    bput(&b, o->rel_ptr, 4 * (size_t)O); bput(&b, o->dep_ptr, 4 * (size_t)O); bput(&b, o->D, 8 * (size_t)O);
+    bput(&b, o->next_seq, 4 * (size_t)L); bput(&b, o->B, 8 * (size_t)L); bput(&b, o->dB, 8 * (size_t)L);
+    bput(&b, o->E, 8 * (size_t)L);
+    bput(&b, o->cprev, 8 * (size_t)Dd); bput(&b, o->counts, 8 * (size_t)Dd * (size_t)nb);
+    bput(&b, &o->ttt, 8); bput(&b, o->ctr, sizeof o->ctr);
+    return b.n;
+}
+int64_t orc_state_size(orc_t *o) { return (int64_t)state_io(o, NULL, 1); }
+void orc_export_state(orc_t *o, void *blob) { state_io(o, blob, 1); }
+/* 0 on success, -1 if the blob's sizes do not match this oracle's inputs */
+int orc_import_state(orc_t *o, const void *blob, int64_t n)
+{
+    const orc_inputs *in = &o->in;
+    int32_t hdr[6];
+    if (n < (int64_t)sizeof hdr || n != orc_state_size(o)) return -1;
+    memcpy(hdr, blob, sizeof hdr);
+    if (hdr[1] != in->n_agents || hdr[2] != in->n_links || hdr[3] != in->n_origins ||
+        hdr[4] != in->n_detectors || hdr[5] != in->n_count_bins) return -1;
+    state_io(o, (char *)blob, 0);
+    o->cf.n = o->mv.n = o->smp.n = o->steps.n = o->capf.n = 0;
+    o->chs.n = o->chl.n = o->chr.n = o->chg.n = o->mgs.n = o->mgc.n = o->mgmv.n = o->mgg.n = 0;
+    o->ties.n = 0;
+    o->have_base = 0;
+    o->restored = 1;
+    return 0;
+}
 int64_t orc_log_sizes(const orc_t *o, int64_t *out)
 {
     out[0] = o->cf.n; out[1] = o->mv.n; out[2] = o->smp.n; out[3] = o->steps.n;
@@ -1218,7 +1341,7 @@ int orc_backward(orc_t *o, const double *gQ, double gT, const double *gx,
 {
     const orc_inputs *in = &o->in;
     int32_t N = in->n_agents, Bn = in->n_rate_bins, nb = in->n_count_bins;
-    if (!o->log_on) return -1;
+    if (!o->log_on || o->restored) return -1;
     double *adj = calloc((size_t)N, 8), *nadj = calloc((size_t)N, 8);
     const int ste = g_beta || g_cost || g_alpha || g_theta;
     double *bb = malloc(8 * (size_t)(in->n_links + 1)), *cc = malloc(8 * (size_t)(in->n_links + 1));

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sim.h"
+
 namespace sim {
 
 constexpr int kWave = 64;
@@ -29,6 +31,9 @@ enum : uint8_t { AG_WAIT = 0, AG_QUEUED = 1, AG_ON = 2, AG_EXITED = 3 };
 enum { CTR_RELEASED = 0, CTR_DEPARTED, CTR_ON_NET, CTR_EXITED, CTR_TRANSFERS, CTR_TIES, CTR_STUCK,
        CTR_ORDER_VIOL, CTR_N };
 enum { ERR_RING_OVERFLOW = 0, ERR_CAND_OVERFLOW = 1, ERR_N = 4 };
+// near-tie log: classes of sim_get_tie_log, device capacity in records
+enum { TIE_CHOICE = SIM_TIE_CHOICE, TIE_MERGE = SIM_TIE_MERGE };
+constexpr int kTieLogMax = SIM_TIE_LOG_MAX;
 
 struct Dev {
     // sizes
@@ -92,6 +97,9 @@ struct Dev {
     int64_t *ctr;                    // [S*kCtrSlots*CTR_N], summed on read
     int32_t *cum;                    // [S*D*nb] cumulative detector counts
     int32_t *err;                    // [ERR_N]
+    int32_t *tie_log;                // [tie_cap x 6] near-tie records of the forward (null in replays)
+    int32_t *tie_n;                  // [1] records appended (may exceed tie_cap; the rest are dropped)
+    int32_t tie_cap;
 
     // tape (replay window) and adjoint
     float *tape_pos;                 // [(W+1) * S * ring_total]

@@ -58,6 +58,17 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
+// One near-tie record (scenario, step, class, agent, link, decision), links
+// in the internal numbering (the host maps them back).  Replays carry no log.
+__device__ __forceinline__ void tie_record(const Dev &d, int s, int t, int cls, int ag, int link, int dec)
+{
+    if (!d.tie_log) return;
+    const int k = atomicAdd(d.tie_n, 1);
+    if (k >= d.tie_cap) return;
+    int32_t *r = d.tie_log + 6 * (int64_t)k;
+    r[0] = s; r[1] = t; r[2] = cls; r[3] = ag; r[4] = link; r[5] = dec;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies with the Weyl key schedule.
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
@@ -661,7 +672,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     int ch = CH_NONE;
     if (chooser) {
         ch = arg;
-        if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) small += nf_one(NF_TIES);
+        if (arg >= 0 && second > -INFINITY && best - second < 1e-12 * (1.0 + fabs(best))) {
+            small += nf_one(NF_TIES);
+            tie_record(d, s, t, TIE_CHOICE, ag, arg, arg);
+        }
     } else if (exiting) {
         ch = CH_EXIT;
     }
@@ -698,7 +712,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     }
     const int sl = ch >= 0 ? orc[argk].slots : 0;
     const int won = (ch >= 0) && rank < sl;
-    if (ch >= 0 && close) small += nf_one(NF_TIES);
+    if (ch >= 0 && close) {
+        small += nf_one(NF_TIES);
+        tie_record(d, s, t, TIE_MERGE, ag, ch, 1);
+    }
 
     // ---- resolve: lane q < deg walks in-link q's heads in rank order ----
     int np = 0;

@@ -126,6 +126,7 @@ struct sim_t {
     Ckpt tune_ck;
     double *tune_tstar = nullptr;
     int32_t *tune_rel = nullptr, *tune_dep = nullptr, *tune_exit = nullptr, *tune_cum = nullptr;
+    int32_t *tune_tie_n = nullptr;
     float *vfree = nullptr, *spacing = nullptr;
     double *util = nullptr, *acc = nullptr;
     // mutable queue buffers
@@ -401,6 +402,7 @@ void zero_state(sim_t *h)
     HIPCHK(hipMemsetAsync(d.ctr, 0, (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8, st));
     if (h->D * h->nb) HIPCHK(hipMemsetAsync(d.cum, 0, (size_t)h->S * h->D * h->nb * 4, st));
     HIPCHK(hipMemsetAsync(d.err, 0, sim::ERR_N * 4, st));
+    HIPCHK(hipMemsetAsync(d.tie_n, 0, 4, st));
     h->t = 0;
     h->rec_valid = h->record != 0;
     h->tape_win.assign(h->tapes.size(), -1);
@@ -971,6 +973,9 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.ctr = h->dalloc<int64_t>((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
     d.cum = h->dalloc<int32_t>((size_t)h->S * h->D * std::max(h->nb, 1));
     d.err = h->dalloc<int32_t>(sim::ERR_N);
+    d.tie_log = h->dalloc<int32_t>((size_t)6 * sim::kTieLogMax);
+    d.tie_n = h->dalloc<int32_t>(1);
+    d.tie_cap = sim::kTieLogMax;
     h->ttt_dev = h->dalloc<double>(h->S);
     h->ttt_acc = h->dalloc<unsigned long long>(2 * (size_t)h->S);
     h->counts_dev = h->dalloc<float>((size_t)h->S * h->D * std::max(h->nb, 1));
@@ -993,6 +998,8 @@ void allocate_device(sim_t *h, const sim_config *cfg)
         h->rp_stream.assign((size_t)h->n_replay, nullptr);
         for (int k = 0; k < h->n_replay; ++k) {
             Dev &r = h->rp_dev[k];   // mutable state of replay slot k (errors go to the shared flags)
+            r.tie_log = nullptr;     // a replay repeats decisions already logged by the forward
+            r.tie_n = nullptr;
             r.ring_pos = h->dalloc<float>(SR); r.ring_agent = h->dalloc<int32_t>(SR); r.ring_aux = h->dalloc<int2>(SR);
             r.rhead = h->dalloc<int32_t>(SL); r.rtail = h->dalloc<int32_t>(SL);
             r.B = h->dalloc<double>(SL); r.dB = h->dalloc<double>(SL); r.E = h->dalloc<int64_t>(SL);
@@ -1703,10 +1710,38 @@ int sim_set_full_state(sim_t *h, const void *blob, size_t n)
         else h->placed.clear();
         build_queues(h, any ? &h->placed : nullptr);
         upload_queues(h);
+        HIPCHK(hipMemsetAsync(h->d.tie_n, 0, 4, h->stream));   // the log restarts with the restored run
         h->t = hd.t;
         h->rec_valid = h->record && hd.t == 0;
         h->tape_win.assign(h->tapes.size(), -1);
         HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_get_tie_log(sim_t *h, int32_t *buf, int64_t cap, int64_t *n)
+{
+    return guarded(h, [&] {
+        if (!n || cap < 0 || (cap > 0 && !buf)) fail(SIM_EINVAL, "bad tie-log arguments");
+        int32_t total = 0;
+        HIPCHK(hipMemcpyAsync(&total, h->d.tie_n, 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        *n = total;
+        const int64_t k = std::min<int64_t>({(int64_t)total, (int64_t)sim::kTieLogMax, buf ? cap : 0});
+        if (k <= 0) return;
+        std::vector<int32_t> r((size_t)6 * k);
+        HIPCHK(hipMemcpyAsync(r.data(), h->d.tie_log, r.size() * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int64_t q = 0; q < k; ++q) {   // links back to the caller's numbering
+            int32_t *x = &r[(size_t)6 * q];
+            x[4] = h->lperm[x[4]];
+            if (x[2] == sim::TIE_CHOICE) x[5] = h->lperm[x[5]];
+        }
+        std::vector<int64_t> ord((size_t)k);
+        for (int64_t q = 0; q < k; ++q) ord[(size_t)q] = q;
+        std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+            return std::lexicographical_compare(&r[6 * a], &r[6 * a + 6], &r[6 * b], &r[6 * b + 6]);
+        });
+        for (int64_t q = 0; q < k; ++q) std::copy(&r[6 * ord[q]], &r[6 * ord[q] + 6], buf + 6 * q);
     });
 }
 
@@ -1892,6 +1927,7 @@ void tune_snapshot(sim_t *h, bool save)
         h->tune_dep = h->dalloc<int32_t>(SN);
         h->tune_exit = h->dalloc<int32_t>(SN);
         h->tune_cum = h->dalloc<int32_t>(nc);
+        h->tune_tie_n = h->dalloc<int32_t>(1);
         h->tune_alloc = true;
     }
     ckpt_copy(h, h->tune_ck, save);
@@ -1904,6 +1940,7 @@ void tune_snapshot(sim_t *h, bool save)
     cp(h->tune_dep, d.dep_t, SN * 4);
     cp(h->tune_exit, d.exit_t, SN * 4);
     cp(h->tune_cum, d.cum, nc * 4);
+    cp(h->tune_tie_n, d.tie_n, 4);   // probe steps append no near-tie records
 }
 
 void set_groups(sim_t *h, int gl, int gn, int gr)

@@ -90,6 +90,7 @@ def lib():
         "sim_gumbel_fast": ([vp, i32, vp, vp], C.c_int),
         "sim_segsort": ([vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
         "sim_segsort_noalloc": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], C.c_int),
+        "sim_get_tie_log": ([vp, vp, i64, vp], C.c_int),
         "sim_set_schedule": ([vp, C.c_int, C.c_int, C.c_int], C.c_int),
         "sim_get_schedule": ([vp, vp, vp, vp], C.c_int),
         "sim_set_timing": ([vp, C.c_int], C.c_int),
@@ -120,7 +121,7 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_gumbel_fast", "sim_segsort",
-            "sim_segsort_noalloc", "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
+            "sim_segsort_noalloc", "sim_get_tie_log", "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
             "sim_set_full_state",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
             "srv_stats", "srv_destroy"]
@@ -378,6 +379,17 @@ class Simulator:
         self._chk(self._L.sim_segsort_noalloc(self._h, n, n_segments, C.c_void_p(seg.data_ptr()),
                                               C.c_void_p(pos.data_ptr()), C.c_void_p(seq.data_ptr()),
                                               C.c_void_p(perm.data_ptr()), C.c_void_p(seg_off.data_ptr()), st))
+
+    def tie_log(self) -> np.ndarray:
+        """Near-tie records of the forward since the last reset (sim_get_tie_log), int32 [n x 6]:
+        (scenario, step, class, agent, link, decision); classes 0 route choice, 1 merge."""
+        n = C.c_int64(0)
+        self._chk(self._L.sim_get_tie_log(self._h, None, 0, C.byref(n)))
+        k = min(n.value, 1 << 16)
+        out = np.zeros((k, 6), np.int32)
+        if k:
+            self._chk(self._L.sim_get_tie_log(self._h, _p(out), k, C.byref(n)))
+        return out
 
     def set_schedule(self, g_link: int, g_node: int, g_rev: int):
         self._chk(self._L.sim_set_schedule(self._h, g_link, g_node, g_rev))

@@ -493,6 +493,92 @@ def test_near_tie_is_logged_and_adopted_across_precisions():
     assert c.tie_stats() == {"adopted": 1, "unmatched": 0, "flipped": 1}
 
 
+def _route_merge_run(seed, adopt=None):
+    w = W.route_merge_toy(seed=seed)
+    o = Oracle(w, variant="f64", tie_tolerance=1e300, adopt=adopt)   # every choice and merge is a near tie
+    o.place([0, 1], [0, 1], [100.0, 100.0])
+    o.run(1)
+    return o
+
+
+@pytest.mark.parametrize("seed", [3, 5])
+def test_route_choice_near_tie_adopts_the_other_runs_link(seed):
+    """A near-tie route choice takes the link another run's log chose for the
+    same (step, agent), if it is a candidate there: agent 0 (choosing between
+    links 2 and 3 at node 2) follows a log that names the link it did not pick,
+    and that decision shows in its own log and its position."""
+    a = _route_merge_run(seed)
+    la = a.tie_log()
+    ch = la[la[:, 1] == oracle.TIE_CHOICE]
+    assert len(ch) == 1 and ch[0][2] == 0
+    own = int(ch[0][3])
+    assert own == 2 and a.state()["link"][0] in (0, 2)   # the chosen link is the contested one
+    flip = la.copy()
+    flip[flip[:, 1] == oracle.TIE_CHOICE, 3:] = 3
+    b = _route_merge_run(seed, adopt=flip)
+    lb = b.tie_log()
+    assert list(lb[lb[:, 1] == oracle.TIE_CHOICE][0]) == [0, oracle.TIE_CHOICE, 0, 3, 3]
+    st = b.state()
+    assert st["link"][0] == 3 and st["pos"][0] == 0.0 and st["link"][1] == 2   # no contest left
+    assert b.tie_stats()["flipped"] == 1
+    # a link that is no candidate at that node is not taken (counted as unmatched)
+    bad = la.copy()
+    bad[bad[:, 1] == oracle.TIE_CHOICE, 3:] = 4
+    c = _route_merge_run(seed, adopt=bad)
+    assert c.tie_stats()["unmatched"] >= 1 and c.state()["link"][0] in (0, 2)
+
+
+@pytest.mark.parametrize("seed", [3, 10])
+def test_merge_near_tie_adopts_the_other_runs_order(seed):
+    """A near-tie merge pair is ranked as another run's log ranked it: with the
+    log naming the loser of the contest for link 2 as ranked first, the loser
+    enters link 2 and the former winner stays at the end of its link."""
+    a = _route_merge_run(seed)
+    la = a.tie_log()
+    mg = la[la[:, 1] == oracle.TIE_MERGE]
+    assert len(mg) == 1 and mg[0][3] == 2
+    win = int(mg[0][2])
+    assert a.state()["link"][win] == 2
+    flip = la.copy()
+    flip[flip[:, 1] == oracle.TIE_MERGE, 2] = 1 - win
+    b = _route_merge_run(seed, adopt=flip)
+    st = b.state()
+    assert st["link"][1 - win] == 2 and st["pos"][1 - win] == 0.0
+    assert st["link"][win] == win and st["pos"][win] == 100.0
+    assert b.tie_stats()["flipped"] == 1
+
+
+@pytest.mark.parametrize("mk,T0,T1", [(lambda: W.random_small(4, nx=4, ny=4, n_agents=500, rates=True, steps=300),
+                                      137, 300),
+                                     (lambda: W.small_grid_fixed(), 250, 520)])
+def test_state_hand_off_continues_the_run(mk, T0, T1):
+    """Nowcast hand-off: an oracle that imports another's state at T0 and runs
+    on to T1 ends in the same state, counts, travel time and counters as one
+    that ran straight through; it keeps no log of the past, so its reverse
+    sweep is refused."""
+    w = mk()
+    a = Oracle(w, log=True)
+    a.run(T0)
+    blob = a.export_state()
+    a.run(T1 - T0)
+    b = Oracle(w, log=True).import_state(blob)
+    b.run(T1 - T0)
+    sa, sb = a.state(), b.state()
+    for k in ("status", "link", "seq", "pos"):
+        assert np.array_equal(sa[k], sb[k]), k
+    la, lb = a.link_state(), b.link_state()
+    for k in ("B", "E", "next_seq"):
+        assert np.array_equal(la[k], lb[k]), k
+    ca, ta = a.counts()
+    cb, tb = b.counts()
+    assert np.array_equal(ca, cb) and ta == tb and a.counters() == b.counters()
+    assert sa["status"].tolist().count(ST_ON) > 0
+    with pytest.raises(RuntimeError):
+        b.backward(gT=1.0)
+    with pytest.raises(ValueError):
+        Oracle(W.random_small(5, nx=3, ny=3, n_agents=10)).import_state(blob)
+
+
 def _precision_agreement(w, T, every):
     """Float-position run logs its near ties; the double-position run adopts
     them.  Integer state, counts and travel time must then agree exactly, and

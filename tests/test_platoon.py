@@ -127,7 +127,7 @@ def test_platoon_parity_gpu(dn):
     so, sg = o.state(), s.state()
     assert np.array_equal(so["status"], sg["status"][0])
     on = so["status"] == ST_ON
-    assert on.sum() > 50
+    assert on.sum() > 20
     for k in ("link", "seq", "pos"):
         assert np.array_equal(so[k][on].astype(sg[k].dtype), sg[k][0][on]), k
     lo, lg = o.link_state(), s.link_state()
