@@ -150,6 +150,10 @@ const char *sim_last_error(const sim_t *h);
  * parameters, so sim_backward needs a new one from t = 0 (SIM_ESTATE). */
 int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_device);
 
+/* Current values of one parameter group, same layout and numbering as
+ * sim_set_params: values [S x n], host or device (on_device). */
+int sim_get_params(sim_t *h, int which, float *values, int64_t n, int on_device);
+
 /* Back to t = 0: empty network, all agents waiting, counters, buckets and
  * observables cleared.  Parameters are kept. */
 int sim_reset(sim_t *h);
@@ -193,6 +197,61 @@ int sim_get_observables(sim_t *h, float *counts, double *ttt, int on_device);
  * SIM_EINVAL. */
 int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const float *dL_dpos,
                  uint32_t param_mask, float *const *grads, int on_device);
+
+/* ------------------------------------------------------------------------
+ * Gradient-based calibration and control (Methods, "Optimization"): each
+ * iteration runs the forward rollout from t = 0, evaluates the loss on the
+ * detector counts, runs the adjoint, and updates the chosen parameter groups
+ * with AdamW (Loshchilov and Hutter: decoupled weight decay; the paper uses
+ * learning rate 0.1, weight decay 1e-5 and otherwise default
+ * hyperparameters).  The loop stops when the loss has not improved for
+ * `patience` iterations (the paper: 20) or after max_iters, and leaves the
+ * handle on the parameters of the lowest loss seen.  Every step runs on the
+ * device; the host reads one loss value per iteration.
+ *
+ * Losses: SIM_LOSS_COUNTS_MSE, mean over detectors and count bins of the
+ * squared difference to `observed` [det x bins] (calibration, Methods
+ * "Optimization"; the paper averages squared count errors over observed
+ * links); SIM_LOSS_CUMULATIVE, (sum over the bins of detector
+ * target_detector - target)^2 (control: the paper steers the cumulative
+ * count of one target link to half its uncontrolled value through the link
+ * costs; Results, "Gradient-guided traffic control").
+ *
+ * After each update a group is clipped to [lower[k], upper[k]] (k = its
+ * sim_param; NULL arrays take wide defaults: u [0.5, 60], kappa [1e-3, the
+ * jam density the rings were sized for], beta and alpha unbounded, cost
+ * [0.01, 1e4], rates and capacity multipliers [0, 1e4]); kappa never exceeds
+ * the value sim_create sized the link rings for.  Requirements: a recording
+ * handle (record_for_backward) with one scenario, steps <= max_steps;
+ * SIM_P_THETA_DEST cannot be optimised.  loss_history [max_iters] (host, may
+ * be NULL) receives the loss of every iteration.
+ * ------------------------------------------------------------------------ */
+enum { SIM_LOSS_COUNTS_MSE = 0, SIM_LOSS_CUMULATIVE = 1 };
+typedef struct {
+    uint32_t groups;          /* bit k set: optimise sim_param k */
+    int32_t steps;            /* rollout length of every iteration */
+    int32_t max_iters;        /* at most this many loss evaluations */
+    int32_t patience;         /* stop after this many iterations without a lower loss */
+    double lr, weight_decay, beta1, beta2, eps;   /* AdamW */
+    int32_t loss;             /* SIM_LOSS_COUNTS_MSE or SIM_LOSS_CUMULATIVE */
+    int32_t target_detector;  /* SIM_LOSS_CUMULATIVE */
+    double target;            /* SIM_LOSS_CUMULATIVE */
+    const float *lower, *upper;   /* [SIM_P_COUNT] box per group, or NULL */
+    int32_t normalized;       /* 1: AdamW works on x = (p - lower) / (upper - lower) of each optimised group
+                                 (finite boxes required), so one learning rate moves groups of very
+                                 different scales by the same fraction of their range; 0: on p */
+    float *const *first_grad; /* NULL, or per sim_param k a host buffer [n_k] (NULL entries skipped)
+                                 that receives dLoss/d(group k) at the starting parameters
+                                 (written when max_iters >= 2) */
+} sim_opt_config;
+typedef struct {
+    int32_t iterations;       /* loss evaluations made */
+    int32_t best_iter;        /* iteration of the lowest loss (0 = the starting parameters) */
+    double first_loss, best_loss;
+    double seconds;           /* wall time of the loop */
+} sim_opt_result;
+int sim_optimize(sim_t *h, const sim_opt_config *oc, const float *observed, double *loss_history,
+                 sim_opt_result *res);
 
 /* Agent state, host arrays [S x n_agents] (any may be NULL): status
  * (SIM_WAIT..SIM_EXITED), link (-1 when not on a link), pos, seq (entry

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsim.so")
-SOURCES = ["sim_kernels.hip", "sim_runtime.cpp", "sim_serve.cpp"]
+SOURCES = ["sim_kernels.hip", "sim_runtime.cpp", "sim_serve.cpp", "sim_optimize.cpp"]
 ARCH = os.environ.get("SIM_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",

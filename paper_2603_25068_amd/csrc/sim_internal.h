@@ -174,5 +174,22 @@ void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long
 void launch_counts(const Dev &d, float *out, hipStream_t st);
 void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st);
 void launch_gather_links(const double *src, const int32_t *linv, float *dst, int S, int L, hipStream_t st);
+void launch_count_loss(int n, int nb, const float *q, const float *y, int kind, int det, double target,
+                       double *loss, float *gq, hipStream_t st);
+void launch_adamw(int64_t n, float *p, const float *g, float *m, float *v, int t, double lr, double b1, double b2,
+                  double eps, double wd, double x0, double sc, double lo, double hi, const float *hi_vec,
+                  hipStream_t st);
+
+// handle facts for the optimisation loop (sim_optimize.cpp)
+hipStream_t stream_of(const sim_t *h);
+int device_of(const sim_t *h);
+int detectors_of(const sim_t *h);
+int count_bins_of(const sim_t *h);
+int max_steps_of(const sim_t *h);
+bool is_recording(const sim_t *h);
+bool rate_mode(const sim_t *h);
+int64_t group_size(const sim_t *h, int which);     // values per scenario of a parameter group (-1: none)
+void kappa_ceiling(const sim_t *h, float *out);     // [L], caller order: the jam density the rings were sized for
+int set_error(sim_t *h, int code, const std::string &msg);
 
 }  // namespace sim

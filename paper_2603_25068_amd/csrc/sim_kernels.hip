@@ -1638,8 +1638,90 @@ int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, con
 }
 
 // ---------------------------------------------------------------------------
+// Optimisation loop (calibration and control, Methods "Optimization"): the
+// count loss with its cotangent, and the AdamW update of one parameter group.
+// ---------------------------------------------------------------------------
+
+// One workgroup.  kind 0: mean over the n = det x nb counts of (q - y)^2,
+// cotangent 2 (q - y) / n.  kind 1: (sum over the bins of detector det of q
+// - target)^2, cotangent 2 (sum - target) on those bins, 0 elsewhere.  Fixed
+// reduction order, so the loss is reproducible.
+__global__ __launch_bounds__(1024) void k_count_loss(int n, int nb, const float *q, const float *y, int kind,
+                                                      int det, double target, double *loss, float *gq)
+{
+    __shared__ double part[1024];
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    if (kind == 0) {
+        for (int i = tid; i < n; i += 1024) {
+            const double e = (double)q[i] - (double)y[i];
+            acc += e * e;
+            gq[i] = (float)(2.0 * e / (double)n);
+        }
+    } else {
+        for (int i = tid; i < n; i += 1024) gq[i] = 0.0f;
+        if (tid < nb) acc = (double)q[(int64_t)det * nb + tid];
+    }
+    part[tid] = acc;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (tid < o) part[tid] += part[tid + o];
+        __syncthreads();
+    }
+    if (kind == 0) {
+        if (tid == 0) *loss = n > 0 ? part[0] / (double)n : 0.0;
+    } else {
+        const double e = part[0] - target;
+        if (tid == 0) *loss = e * e;
+        if (tid < nb) gq[(int64_t)det * nb + tid] = (float)(2.0 * e);
+    }
+}
+
+// AdamW (Loshchilov and Hutter, decoupled weight decay) on float parameters
+// in the coordinates x = (p - x0) / sc (x0 = 0, sc = 1: the parameters
+// themselves), update t >= 1 with the gradient gx = g sc:
+// m <- b1 m + (1 - b1) gx, v <- b2 v + (1 - b2) gx^2,
+// x <- x - lr (m / (1 - b1^t) / (sqrt(v / (1 - b2^t)) + eps) + wd x),
+// p = x0 + sc x, then the box [lo, min(hi, hi_vec[i])].  Arithmetic in double.
+__global__ void k_adamw(int64_t n, float *p, const float *g, float *m, float *v, int t, double lr, double b1,
+                        double b2, double eps, double wd, double x0, double sc, double lo, double hi,
+                        const float *hi_vec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double gi = (double)g[i] * sc;
+    const double mi = b1 * (double)m[i] + (1.0 - b1) * gi;
+    const double vi = b2 * (double)v[i] + (1.0 - b2) * gi * gi;
+    m[i] = (float)mi;
+    v[i] = (float)vi;
+    const double mh = mi / (1.0 - pow(b1, (double)t));
+    const double vh = vi / (1.0 - pow(b2, (double)t));
+    double x = ((double)p[i] - x0) / sc;
+    x = x - lr * (mh / (sqrt(vh) + eps) + wd * x);
+    double y = x0 + sc * x;
+    double top = hi;
+    if (hi_vec) top = fmin(top, (double)hi_vec[i]);
+    y = fmin(fmax(y, lo), top);
+    p[i] = (float)y;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+void launch_count_loss(int n, int nb, const float *q, const float *y, int kind, int det, double target,
+                       double *loss, float *gq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_loss, dim3(1), dim3(1024), 0, st, n, nb, q, y, kind, det, target, loss, gq);
+}
+
+void launch_adamw(int64_t n, float *p, const float *g, float *m, float *v, int t, double lr, double b1, double b2,
+                  double eps, double wd, double x0, double sc, double lo, double hi, const float *hi_vec,
+                  hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_adamw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, g, m, v, t, lr, b1, b2,
+                       eps, wd, x0, sc, lo, hi, hi_vec);
+}
 static inline int blocks_for(int64_t waves) { return (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock); }
 
 // one wavefront per launch record (offset, waves): first start and last end over its waves

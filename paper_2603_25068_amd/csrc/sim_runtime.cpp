@@ -1142,6 +1142,28 @@ int device_errors(sim_t *h, std::string *err)
     }
 }
 
+hipStream_t stream_of(const sim_t *h) { return h->stream; }
+int device_of(const sim_t *h) { return h->device; }
+int detectors_of(const sim_t *h) { return h->D; }
+int count_bins_of(const sim_t *h) { return h->nb; }
+int max_steps_of(const sim_t *h) { return h->max_steps; }
+bool is_recording(const sim_t *h) { return h->record != 0; }
+bool rate_mode(const sim_t *h) { return !h->fixed_mode; }
+int64_t group_size(const sim_t *h, int which)
+{
+    switch (which) {
+    case SIM_P_U: case SIM_P_KAPPA: case SIM_P_BETA: case SIM_P_ALPHA: case SIM_P_COST: case SIM_P_CAP_MULT:
+        return h->L;
+    case SIM_P_RATES: return h->fixed_mode ? -1 : (int64_t)h->O * h->B;
+    case SIM_P_THETA_DEST: return 1;
+    default: return -1;
+    }
+}
+void kappa_ceiling(const sim_t *h, float *out)
+{
+    for (int j = 0; j < h->L; ++j) out[j] = h->jam_density[h->linv[j]];
+}
+int set_error(sim_t *h, int code, const std::string &msg) { return record_error(h, code, msg); }
 int counts_size(const sim_t *h) { return h->S * h->D * h->nb; }
 int scenarios_of(const sim_t *h) { return h->S; }
 void destroy_handle(sim_t *h) { delete h; }
@@ -1257,6 +1279,38 @@ int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_d
         }
         HIPCHK(hipMemcpyAsync(dst, host.data(), n * 4, hipMemcpyHostToDevice, h->stream));
         derive(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+int sim_get_params(sim_t *h, int which, float *values, int64_t n, int on_device)
+{
+    return guarded(h, [&] {
+        if (!values) fail(SIM_EINVAL, "values is NULL");
+        const float *src = nullptr;
+        int64_t per = h->L;
+        switch (which) {
+        case SIM_P_U: src = h->p_u; break;
+        case SIM_P_KAPPA: src = h->p_kappa; break;
+        case SIM_P_BETA: src = h->p_beta; break;
+        case SIM_P_ALPHA: src = h->p_alpha; break;
+        case SIM_P_COST: src = h->p_cost; break;
+        case SIM_P_CAP_MULT: src = h->p_capm; break;
+        case SIM_P_RATES:
+            if (h->fixed_mode) fail(SIM_EINVAL, "rates need departure-rate mode");
+            src = h->p_rates; per = (int64_t)h->O * h->B; break;
+        default: fail(SIM_EINVAL, "unknown parameter group");
+        }
+        if (n != per * h->S) fail(SIM_EINVAL, "expected " + std::to_string(per * h->S) + " values");
+        std::vector<float> host((size_t)n), out((size_t)n);
+        HIPCHK(hipMemcpyAsync(host.data(), src, n * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (which == SIM_P_RATES) out = host;
+        else
+            for (int s = 0; s < h->S; ++s)
+                for (int k = 0; k < h->L; ++k) out[(size_t)s * h->L + h->lperm[k]] = host[(size_t)s * h->L + k];
+        HIPCHK(hipMemcpyAsync(values, out.data(), n * 4, on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost,
+                              h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
     });
 }

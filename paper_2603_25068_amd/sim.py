@@ -46,6 +46,21 @@ class _Demand(C.Structure):
                 ("rates", C.c_void_p)]
 
 
+class _OptConfig(C.Structure):
+    _fields_ = [("groups", C.c_uint32), ("steps", C.c_int32), ("max_iters", C.c_int32), ("patience", C.c_int32),
+                ("lr", C.c_double), ("weight_decay", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("loss", C.c_int32), ("target_detector", C.c_int32), ("target", C.c_double),
+                ("lower", C.c_void_p), ("upper", C.c_void_p), ("normalized", C.c_int32), ("first_grad", C.c_void_p)]
+
+
+class _OptResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("best_iter", C.c_int32), ("first_loss", C.c_double),
+                ("best_loss", C.c_double), ("seconds", C.c_double)]
+
+
+SIM_LOSS_COUNTS_MSE, SIM_LOSS_CUMULATIVE = 0, 1
+
+
 class _Config(C.Structure):
     _fields_ = [("dt", C.c_double), ("platoon", C.c_int32), ("gumbel_tau", C.c_double),
                 ("dest_logit_coef", C.c_double), ("big_m", C.c_double), ("seed", C.c_uint64),
@@ -91,6 +106,8 @@ def lib():
         "sim_segsort": ([vp, i32, i32, vp, vp, vp, vp, vp], C.c_int),
         "sim_segsort_noalloc": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], C.c_int),
         "sim_get_tie_log": ([vp, vp, i64, vp], C.c_int),
+        "sim_get_params": ([vp, C.c_int, vp, i64, C.c_int], C.c_int),
+        "sim_optimize": ([vp, vp, vp, vp, vp], C.c_int),
         "sim_set_schedule": ([vp, C.c_int, C.c_int, C.c_int], C.c_int),
         "sim_get_schedule": ([vp, vp, vp, vp], C.c_int),
         "sim_set_timing": ([vp, C.c_int], C.c_int),
@@ -121,7 +138,7 @@ def exported_symbols() -> list:
     return ["sim_create", "sim_destroy", "sim_last_error", "sim_set_params", "sim_reset", "sim_place",
             "sim_step", "sim_rollout", "sim_get_observables", "sim_backward", "sim_get_state",
             "sim_get_link_state", "sim_get_stats", "sim_get_dist", "sim_time", "sim_philox", "sim_gumbel_fast", "sim_segsort",
-            "sim_segsort_noalloc", "sim_get_tie_log", "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
+            "sim_segsort_noalloc", "sim_get_tie_log", "sim_get_params", "sim_optimize", "sim_set_schedule", "sim_get_schedule", "sim_set_timing", "sim_get_timing", "sim_footprint", "sim_autotune", "sim_get_full_state",
             "sim_set_full_state",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_result", "srv_error", "srv_cancel",
             "srv_stats", "srv_destroy"]
@@ -247,6 +264,57 @@ class Simulator:
             v = np.tile(v, self.S)
         v = np.ascontiguousarray(v)
         self._chk(self._L.sim_set_params(self._h, PARAMS[group], _p(v), v.size, 0))
+
+    def get_params(self, group: str) -> np.ndarray:
+        """Current values of a parameter group, [S x n] (sim_get_params)."""
+        out = np.zeros((self.S, self.n_per(group)), np.float32)
+        self._chk(self._L.sim_get_params(self._h, PARAMS[group], _p(out), out.size, 0))
+        return out
+
+    def optimize(self, groups, steps: Optional[int] = None, observed=None, loss: str = "counts",
+                 target_detector: int = 0, target: float = 0.0, lr: float = 0.1, weight_decay: float = 1e-5,
+                 betas=(0.9, 0.999), eps: float = 1e-8, max_iters: int = 200, patience: int = 20,
+                 bounds: Optional[dict] = None, normalized: bool = False) -> dict:
+        """Gradient-based calibration ("counts": mean squared count error against `observed`
+        [det x bins]) or control ("cumulative": squared error of detector `target_detector`'s
+        whole-horizon count against `target`) with AdamW, early stopping after `patience`
+        iterations without improvement; the handle keeps the best parameters (sim_optimize).
+        `bounds` maps group names to (lower, upper); `normalized` runs AdamW on each group's position in
+        its box.  The result holds the gradient at the starting parameters ("first_grad")."""
+        mask = 0
+        for g in groups:
+            mask |= 1 << PARAMS[g]
+        lo = np.full(N_GROUPS, -np.inf, np.float32)
+        hi = np.full(N_GROUPS, np.inf, np.float32)
+        have = bool(bounds)
+        defaults = {"free_speed": (0.5, 60.0), "jam_density": (1e-3, np.inf), "cost": (0.01, 1e4),
+                    "rates": (0.0, 1e4), "cap_mult": (0.0, 1e4)}
+        for g, (a, b) in defaults.items():
+            lo[PARAMS[g]], hi[PARAMS[g]] = a, b
+        for g, (a, b) in (bounds or {}).items():
+            lo[PARAMS[g]], hi[PARAMS[g]] = a, b
+        obs = None
+        if loss == "counts":
+            if observed is None:
+                raise ValueError("calibration needs observed counts")
+            obs = _f32(np.asarray(observed, np.float32).reshape(self.w.net.n_detectors, self.n_count_bins))
+        elif loss != "cumulative":
+            raise ValueError(loss)
+        g0 = {g: np.zeros(self.n_per(g), np.float32) for g in groups}
+        g0_arr = (C.c_void_p * N_GROUPS)()
+        for g, a in g0.items():
+            g0_arr[PARAMS[g]] = a.ctypes.data
+        cfg = _OptConfig(mask, int(self.steps if steps is None else steps), int(max_iters), int(patience),
+                         float(lr), float(weight_decay), float(betas[0]), float(betas[1]), float(eps),
+                         SIM_LOSS_COUNTS_MSE if loss == "counts" else SIM_LOSS_CUMULATIVE, int(target_detector),
+                         float(target), _p(lo) if have else None, _p(hi) if have else None, int(bool(normalized)),
+                         C.cast(g0_arr, C.c_void_p))
+        hist = np.full(int(max_iters), np.nan)
+        res = _OptResult()
+        self._chk(self._L.sim_optimize(self._h, C.byref(cfg), _p(obs), _p(hist), C.byref(res)))
+        return {"iterations": res.iterations, "best_iter": res.best_iter, "first_loss": res.first_loss,
+                "best_loss": res.best_loss, "seconds": res.seconds, "history": hist[:res.iterations],
+                "first_grad": g0}
 
     def reset(self):
         self._chk(self._L.sim_reset(self._h))

@@ -357,6 +357,74 @@ def metro(n_nodes: int = 12_000, n_roads: int = 17_500, n_agents: int = 1_000_00
                     extra={"theta_true": _f32(theta_true), "zone_node": _i32(zone_node)})
 
 
+# Ranges the paper samples its ground-truth per-link parameters from (Methods, "Experimental setting").
+PAPER_RANGES = {"free_speed": (13.9, 22.2), "jam_density": (0.18, 0.22), "beta": (0.0, 5.0), "alpha": (0.01, 5.0)}
+
+
+def sioux_like(seed: int = 7, n_agents: int = 20_000, steps: int = 1800, n_inter: int = 24, n_roads: int = 38,
+               side_m: float = 8000.0) -> Workload:
+    """A stand-in of the paper's per-link calibration network (Methods,
+    "Experimental setting": a TNTP network of 24 intersections whose nodes
+    each keep either a virtual inflow or a virtual outflow link, 48 nodes and
+    100 links in all, 20,000 vehicles spread evenly over the inflow links).
+    Here: 24 uniform points on an 8 km square, the Delaunay MST plus the
+    shortest remaining edges up to 38 two-way roads (76 links, length = the
+    distance), and one 200 m virtual link per intersection, half of them
+    inflow (an origin queue at its outer node) and half outflow (a
+    destination); agents spread evenly over the origins, all ready at t = 0,
+    each bound to a uniformly drawn destination; ground-truth u, kappa, beta,
+    alpha per link drawn uniformly from the paper's ranges, cost 1; a midpoint
+    detector on every link, 5-min counts."""
+    k = seed
+    rng_net = np.random.default_rng(10 * k + 1)
+    rng_dem = np.random.default_rng(10 * k + 2)
+    rng_true = np.random.default_rng(10 * k + 3)
+    xy, roads = metro_roads(n_inter, n_roads, rng_net)
+    tail, head = _links_from_roads(roads)
+    length = np.linalg.norm(xy[tail] - xy[head], axis=1) * side_m
+    kind = rng_net.permutation(np.arange(n_inter) % 2)          # 0: inflow, 1: outflow
+    virt = np.arange(n_inter) + n_inter                           # outer node of each intersection
+    vt = np.where(kind == 0, virt, np.arange(n_inter))
+    vh = np.where(kind == 0, np.arange(n_inter), virt)
+    tail = np.concatenate([tail, vt])
+    head = np.concatenate([head, vh])
+    length = np.concatenate([np.maximum(length, 50.0), np.full(n_inter, 200.0)])
+    L = len(tail)
+    lanes = np.concatenate([rng_net.integers(1, 3, len(roads)).repeat(2), np.full(n_inter, 2)])
+    truth = {g: rng_true.uniform(lo, hi, L) for g, (lo, hi) in PAPER_RANGES.items()}
+    origins = virt[kind == 0]
+    dests = virt[kind == 1]
+    net = Network(
+        n_nodes=2 * n_inter, tail=_i32(tail), head=_i32(head), lanes=_i32(lanes), length=_f32(length),
+        free_speed=_f32(truth["free_speed"]), jam_density=_f32(truth["jam_density"]),
+        capacity=_f32(np.full(L, CAPACITY_PER_LANE)), beta=_f32(truth["beta"]), alpha=_f32(truth["alpha"]),
+        cost=_f32(np.ones(L)), origin_node=_i32(origins), detector_link=_i32(np.arange(L)),
+        detector_pos=_f32(_f32(length) * np.float32(0.5)), node_xy=None)
+    O = len(origins)
+    o = np.arange(n_agents) % O
+    dest = dests[rng_dem.integers(0, len(dests), n_agents)]
+    dem = Demand(agent_origin=_i32(o), agent_dest=_i32(dest), ready_time=_f32(np.zeros(n_agents)))
+    cfg = Config(dt=1.0, gumbel_tau=0.5, dest_logit_coef=0.1, seed=k, steps=steps, count_bin_steps=300,
+                 ckpt_every=60, allow_uturn=1)
+    return Workload(f"sioux_like_{L}links_{n_agents // 1000}k", net, dem, cfg,
+                    extra={"truth": {g: _f32(v) for g, v in truth.items()}})
+
+
+def calibration_start(w: Workload) -> Workload:
+    """The same workload with every calibrated per-link parameter at the middle of the paper's range
+    (the paper starts its calibration there) and the jam density of the network at the top of its
+    range, so that link rings are sized for any value the calibration may reach; the starting
+    values are in extra["start"]."""
+    from copy import deepcopy
+    v = deepcopy(w)
+    v.extra["start"] = {g: _f32(np.full(w.net.n_links, 0.5 * (lo + hi))) for g, (lo, hi) in PAPER_RANGES.items()}
+    v.net.jam_density = _f32(np.full(w.net.n_links, PAPER_RANGES["jam_density"][1]))
+    for g in ("free_speed", "beta", "alpha"):
+        setattr(v.net, g, v.extra["start"][g].copy())
+    v.name = w.name + "_start"
+    return v
+
+
 def control_multipliers(n_links: int, n_controlled: int, n_scenarios: int, seed0: int = 500):
     """Capacity multipliers in [0.5, 1] on n_controlled links sampled
     uniformly; one independent draw per candidate scenario; 1 elsewhere."""
