@@ -359,7 +359,11 @@ int sim_get_schedule(sim_t *h, int *g_link, int *g_node, int *g_rev);
  * the last call with reset = 1, while timing is enabled (sim_set_timing).
  * Kinds 0 link phase, 1 node phase, 2 reverse: each launch's execution
  * interval, first wave start to last wave end, which the kernels record
- * themselves; kind 3 tape/checkpoint copies: HIP events around the copy.
+ * themselves; kind 3 tape/checkpoint copies: HIP events around the copy;
+ * kinds 4, 5, 6: the link, node and reverse launches again, timed with HIP
+ * events recorded on the launch's stream right before and after it (each
+ * interval also holds the dispatch of the launch after the preceding work on
+ * the stream ended).  n_kinds <= 7.
  * While timing is enabled the backward pass runs its windows one after
  * another instead of overlapping replays with the reverse sweep, so each
  * kernel's time is its own.  Within one sim_rollout or sim_backward call at

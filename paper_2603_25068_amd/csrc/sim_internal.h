@@ -132,7 +132,11 @@ namespace sim {
 sim_t *host_prepare(const sim_network *net, const sim_demand *dem, const sim_config *cfg, int device, int *code,
                     std::string *err);
 size_t footprint_of(const sim_t *h);
-int device_attach(sim_t *h, hipStream_t stream, std::string *err);
+// allocate and upload a prepared handle's device state on `stream`, carving it from
+// [arena, arena + arena_bytes) when arena is not null (hipMalloc for what does not fit)
+int device_attach(sim_t *h, hipStream_t stream, void *arena, size_t arena_bytes, std::string *err);
+void release_handle(sim_t *h);
+int64_t arena_fallbacks(const sim_t *h);
 int rollout_enqueue(sim_t *h, int T, std::string *err);
 int results_enqueue(sim_t *h, float *counts, double *ttt, int64_t *vsteps, std::string *err);
 int device_errors(sim_t *h, std::string *err);

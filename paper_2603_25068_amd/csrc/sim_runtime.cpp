@@ -28,6 +28,7 @@ using sim::Dev;
 namespace {
 
 thread_local std::string g_create_error;
+constexpr int kTimingKinds = 7;   // link, node, reverse (self-timed), copies, link, node, reverse (HIP events)
 
 struct HipError {
     std::string msg;
@@ -97,6 +98,11 @@ struct sim_t {
 
     Dev d{};
     std::vector<void *> allocs;
+    // serving: device memory carved from a range of the server's pool (bump allocation, never
+    // freed one by one); allocations that do not fit fall back to hipMalloc
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_off = 0;
+    int64_t arena_fallbacks = 0;
     // mutable parameter buffers
     float *p_u = nullptr, *p_kappa = nullptr, *p_beta = nullptr, *p_alpha = nullptr, *p_cost = nullptr,
           *p_rates = nullptr, *p_capm = nullptr, *capacity_dev = nullptr;
@@ -165,12 +171,20 @@ struct sim_t {
     struct Ev { hipEvent_t a, b; int kind; };
     std::vector<Ev> evs;
     std::vector<hipEvent_t> ev_pool;
-    double ms_acc[4] = {0, 0, 0, 0};
-    int64_t n_acc[4] = {0, 0, 0, 0};
+    double ms_acc[kTimingKinds] = {};
+    int64_t n_acc[kTimingKinds] = {};
 
     template <class T>
     T *dalloc(size_t n) {
         if (n == 0) n = 1;
+        if (arena) {
+            const size_t off = (arena_off + 255) & ~(size_t)255;
+            if (off + n * sizeof(T) <= arena_cap) {
+                arena_off = off + n * sizeof(T);
+                return reinterpret_cast<T *>(arena + off);
+            }
+            ++arena_fallbacks;
+        }
         void *p = nullptr;
         if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
             (void)hipGetLastError();
@@ -627,8 +641,13 @@ void step_on(sim_t *h, const Dev &dv, hipStream_t on, int t, int tape_k)
 {
     int sb = -1;
     if (h->cbs > 0 && (t + 1) % h->cbs == 0 && (t + 1) / h->cbs <= h->nb) sb = (t + 1) / h->cbs - 1;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    h->time_begin(4, &ea, on);
     sim::launch_link(h->stamped(dv, 0, sim::link_blocks(dv)), t, sb, tape_k, on);
+    h->time_end(4, ea, on);
+    h->time_begin(5, &eb, on);
     sim::launch_node(h->stamped(dv, 1, sim::node_blocks(dv)), t, tape_k, on);
+    h->time_end(5, eb, on);
     HIPCHK(hipGetLastError());
 }
 
@@ -873,8 +892,19 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     // ---------------- memory budget ----------------
     const size_t SL = (size_t)h->S * L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
     const size_t SR = (size_t)h->S * h->ring_total;
-    size_t bytes = SR * 16 + SL * (8 * 4 + 4 * 4 + maxl * 16 + 24) + SN * (1 + 8 + 12 + 8) + SO * 16 +
-                   h->route.size() * 8 + (size_t)Nn * 8 + (size_t)h->S * h->D * h->nb * 8;
+    // an upper bound of what allocate_device takes: every array below, each rounded up to 256 bytes
+    // (the serving pool carves a request's state with that alignment)
+    const size_t nQ = (size_t)h->S * h->D * std::max(h->nb, 1);
+    size_t bytes = SR * 16                                   // ring positions, agents, (destination, row)
+                   + SL * (24 + 8 + 16 + 32 + maxl * 16)     // parameters, derived, state, head records
+                   + SN * (1 + 8 + 12) + SO * 16             // per agent and per origin state
+                   + (size_t)h->S * h->O * std::max(h->B, 1) * 4
+                   + (size_t)L * 56 + (size_t)Nn * 32        // link constants, node offsets and words
+                   + (h->in_pad.size() + h->in_loff.size() + h->out_pad.size()) * 4 + h->cand.size() * 8 +
+                   (size_t)Nn * h->max_org * 8 + (size_t)h->N * 44 + h->route.size() * 8 +
+                   (size_t)h->D * 12 + (size_t)h->S * 8 +
+                   (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8 + nQ * 8 + (size_t)6 * sim::kTieLogMax * 4 +
+                   (size_t)h->S * 24 + 128 * 256;
     int n_ck = 0;
     if (h->record) {
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
@@ -1069,10 +1099,13 @@ sim_t *host_prepare(const sim_network *net, const sim_demand *dem, const sim_con
 
 size_t footprint_of(const sim_t *h) { return h->footprint; }
 
-int device_attach(sim_t *h, hipStream_t stream, std::string *err)
+int device_attach(sim_t *h, hipStream_t stream, void *arena, size_t arena_bytes, std::string *err)
 {
     try {
         h->stream = stream;
+        h->arena = static_cast<char *>(arena);
+        h->arena_cap = arena ? arena_bytes : 0;
+        h->arena_off = 0;
         HIPCHK(hipSetDevice(h->device));
         sim_config c{};
         c.dest_logit_coef = h->theta_cfg;
@@ -1167,6 +1200,14 @@ int set_error(sim_t *h, int code, const std::string &msg) { return record_error(
 int counts_size(const sim_t *h) { return h->S * h->D * h->nb; }
 int scenarios_of(const sim_t *h) { return h->S; }
 void destroy_handle(sim_t *h) { delete h; }
+// the handle's stream has no work left (its last event completed): free host state without waiting
+void release_handle(sim_t *h)
+{
+    if (!h) return;
+    h->stream = nullptr;
+    delete h;
+}
+int64_t arena_fallbacks(const sim_t *h) { return h->arena_fallbacks; }
 
 }  // namespace sim
 
@@ -1564,7 +1605,10 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
             if (w == nw - 1) sim::launch_reverse(d, T, Ww, 1, st);
             for (int k = Ww - 1; k >= 0; --k) {
                 if (want_ste) sim::launch_ste(d, t0 + k, k, st);   // reads dL/dx(t+1) before the reverse replaces it
+                hipEvent_t er = nullptr;
+                h->time_begin(6, &er, st);
                 sim::launch_reverse(h->stamped(d, 2, sim::reverse_blocks(d)), t0 + k, k, 0, st);
+                h->time_end(6, er, st);
             }
             HIPCHK(hipEventRecord(rv_done[w], st));
             if (w - K >= 0) replay(w - K);
@@ -2141,11 +2185,11 @@ int sim_get_timing(sim_t *h, double *ms, int64_t *launches, int n_kinds, int res
 {
     return guarded(h, [&] {
         h->resolve_timing();
-        for (int k = 0; k < n_kinds && k < 4; ++k) {
+        for (int k = 0; k < n_kinds && k < kTimingKinds; ++k) {
             if (ms) ms[k] = h->ms_acc[k];
             if (launches) launches[k] = h->n_acc[k];
         }
-        if (reset) for (int k = 0; k < 4; ++k) { h->ms_acc[k] = 0; h->n_acc[k] = 0; }
+        if (reset) for (int k = 0; k < kTimingKinds; ++k) { h->ms_acc[k] = 0; h->n_acc[k] = 0; }
     });
 }
 

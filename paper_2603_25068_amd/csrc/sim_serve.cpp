@@ -8,8 +8,17 @@
 // gives each admitted request its own device state and HIP stream, and
 // advances all running requests chunk by chunk, so their kernels overlap on
 // the device.  A finished request's observables are copied to pinned host
-// memory, its device state is freed and its slot reused.  Results do not
-// depend on what else runs: every request owns its state.
+// memory and its slot and memory range are reused.  Results do not depend on
+// what else runs: every request owns its state.
+//
+// Nothing on the serving path allocates or frees device memory: the server
+// takes one device pool of the whole budget at creation and carves each
+// admitted request's state from a contiguous range of it (first fit,
+// neighbouring free ranges merged on release), and every slot owns its
+// stream, event and pinned result buffers.  hipFree would wait for the whole
+// device, i.e. for every other request's work in flight.  Device state is
+// uploaded by the worker threads outside the server lock, so admission,
+// submission and polling never wait for a copy.
 //
 // hip_device = -1 selects a host-only executor (no GPU): requests are
 // prepared, admitted and retired exactly as above, but a chunk "runs" for a
@@ -50,11 +59,12 @@ struct Request {
     std::string err;
     clk::time_point arrival, done_time;
     sim_t *h = nullptr;
-    bool prepared = false, preparing = false, cancel = false, finishing = false;
+    bool prepared = false, preparing = false, cancel = false, finishing = false, attaching = false;
     size_t footprint = 0;
+    size_t range_off = 0, range_len = 0;   // the request's part of the device pool
     int slot = -1;
     int steps_done = 0;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev = nullptr;               // the slot's event, stream and pinned buffers
     clk::time_point fake_ready;
     float *counts = nullptr;
     double *ttt = nullptr;
@@ -92,6 +102,19 @@ struct srv_t {
     std::vector<std::shared_ptr<Request>> running;
     std::vector<hipStream_t> streams;
     std::vector<char> slot_used;
+    // per slot: completion event and pinned result buffers (grown when a larger request arrives)
+    std::vector<hipEvent_t> slot_ev;
+    std::vector<float *> slot_counts;
+    std::vector<double *> slot_ttt;
+    std::vector<int64_t *> slot_vsteps;
+    std::vector<size_t> slot_nc, slot_ns;
+    // device pool of `budget` bytes and its free ranges (offset -> length); with no device the same
+    // bookkeeping runs on offsets alone
+    void *pool = nullptr;
+    std::map<size_t, size_t> free_ranges;
+    std::deque<std::shared_ptr<Request>> attach_q;   // admitted, waiting for a worker to upload them
+    std::vector<sim_t *> graveyard;                  // handles of retired requests, freed outside the lock
+    int attaching = 0;
     size_t used = 0;
     int64_t next_id = 1;
     bool stop = false;
@@ -103,17 +126,64 @@ struct srv_t {
     bool any_arrival = false;
     std::string create_error;
 
+    // first fit of `need` bytes (multiple of 256) in the pool; false when no free range holds it
+    bool range_alloc(size_t need, size_t *off)
+    {
+        for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+            if (it->second < need) continue;
+            *off = it->first;
+            const size_t rest = it->second - need, at = it->first + need;
+            free_ranges.erase(it);
+            if (rest) free_ranges[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void range_free(size_t off, size_t len)
+    {
+        auto it = free_ranges.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_ranges.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_ranges.erase(nx);
+        }
+        if (it != free_ranges.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_ranges.erase(it);
+            }
+        }
+    }
+
+    // called with mu held; the request's stream has no work left
     void retire(const std::shared_ptr<Request> &r, int state)
     {
-        if (r->h) { sim::destroy_handle(r->h); r->h = nullptr; }
-        if (r->ev) { (void)hipEventDestroy(r->ev); r->ev = nullptr; }
-        if (r->counts) { (void)hipHostFree(r->counts); r->counts = nullptr; }
-        if (r->ttt) { (void)hipHostFree(r->ttt); r->ttt = nullptr; }
-        if (r->vsteps) { (void)hipHostFree(r->vsteps); r->vsteps = nullptr; }
-        if (r->slot >= 0) { slot_used[r->slot] = 0; used -= r->footprint; r->slot = -1; }
+        if (r->h) { graveyard.push_back(r->h); r->h = nullptr; }
+        if (r->slot >= 0) {
+            slot_used[r->slot] = 0;
+            range_free(r->range_off, r->range_len);
+            used -= r->range_len;
+            r->slot = -1;
+        }
+        r->ev = nullptr;
+        r->counts = nullptr;
+        r->ttt = nullptr;
+        r->vsteps = nullptr;
         r->state = state;
         r->done_time = clk::now();
         done_cv.notify_all();
+    }
+
+    // host state of retired requests, freed with mu released
+    void bury(std::unique_lock<std::mutex> &lk)
+    {
+        if (graveyard.empty()) return;
+        std::vector<sim_t *> g;
+        g.swap(graveyard);
+        lk.unlock();
+        for (sim_t *h : g) sim::release_handle(h);
+        lk.lock();
     }
 
     bool chunk_done(const std::shared_ptr<Request> &r)
@@ -159,31 +229,54 @@ struct srv_t {
                 if (r->cancel) { retire(r, SRV_CANCELLED); it = queue.erase(it); progress = true; continue; }
                 if (r->state == SRV_FAILED) { it = queue.erase(it); progress = true; continue; }
                 if (!r->prepared) { ++it; continue; }
-                if ((int)running.size() >= max_slots || used + r->footprint > budget) { ++it; continue; }
+                if ((int)running.size() + attaching >= max_slots) { ++it; continue; }
+                const size_t need = (r->footprint + 255) & ~(size_t)255;
+                size_t off = 0;
+                if (!range_alloc(need, &off)) { ++it; continue; }
                 int slot = 0;
                 while (slot_used[slot]) ++slot;
                 slot_used[slot] = 1;
                 r->slot = slot;
-                used += r->footprint;
-                int rc = SIM_OK;
-                if (device >= 0) {
-                    rc = sim::device_attach(r->h, streams[slot], &r->err);
-                    const size_t nc = (size_t)std::max(1, sim::counts_size(r->h));
-                    const size_t ns = (size_t)std::max(1, sim::scenarios_of(r->h));
-                    if (rc == SIM_OK && (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess ||
-                                         hipHostMalloc((void **)&r->counts, nc * 4) != hipSuccess ||
-                                         hipHostMalloc((void **)&r->ttt, ns * 8) != hipSuccess ||
-                                         hipHostMalloc((void **)&r->vsteps, ns * 8) != hipSuccess)) {
-                        rc = SIM_ENOMEM;
-                        r->err = "could not allocate the request's events or pinned buffers";
-                    }
-                }
+                r->range_off = off;
+                r->range_len = need;
+                used += need;
                 it = queue.erase(it);
                 progress = true;
-                if (rc == SIM_OK) rc = advance(r);
+                int rc = SIM_OK;
+                if (device >= 0) {
+                    // the slot's pinned result buffers, grown if this request needs more
+                    const size_t nc = (size_t)std::max(1, sim::counts_size(r->h));
+                    const size_t ns = (size_t)std::max(1, sim::scenarios_of(r->h));
+                    if (nc > slot_nc[slot]) {
+                        if (slot_counts[slot]) (void)hipHostFree(slot_counts[slot]);
+                        slot_counts[slot] = nullptr;
+                        slot_nc[slot] = 0;
+                        if (hipHostMalloc((void **)&slot_counts[slot], nc * 4) == hipSuccess) slot_nc[slot] = nc;
+                    }
+                    if (ns > slot_ns[slot]) {
+                        if (slot_ttt[slot]) (void)hipHostFree(slot_ttt[slot]);
+                        if (slot_vsteps[slot]) (void)hipHostFree(slot_vsteps[slot]);
+                        slot_ttt[slot] = nullptr;
+                        slot_vsteps[slot] = nullptr;
+                        slot_ns[slot] = 0;
+                        if (hipHostMalloc((void **)&slot_ttt[slot], ns * 8) == hipSuccess &&
+                            hipHostMalloc((void **)&slot_vsteps[slot], ns * 8) == hipSuccess)
+                            slot_ns[slot] = ns;
+                    }
+                    if (slot_nc[slot] < nc || slot_ns[slot] < ns) {
+                        rc = SIM_ENOMEM;
+                        r->err = "could not allocate the slot's pinned result buffers";
+                    }
+                    r->ev = slot_ev[slot];
+                    r->counts = slot_counts[slot];
+                    r->ttt = slot_ttt[slot];
+                    r->vsteps = slot_vsteps[slot];
+                }
                 if (rc != SIM_OK) { r->code = rc; retire(r, SRV_FAILED); continue; }
-                r->state = SRV_RUNNING;
-                running.push_back(r);
+                // device state is uploaded by a worker thread, outside the lock
+                r->attaching = true;
+                ++attaching;
+                attach_q.push_back(r);
             }
             max_running = std::max<int64_t>(max_running, (int64_t)running.size());
             // ---- progress of running requests ----
@@ -229,14 +322,57 @@ struct srv_t {
                 if (remove) running.erase(running.begin() + k);
                 else ++k;
             }
-            if (!progress) cv.wait_for(lk, std::chrono::microseconds(100));
+            bury(lk);
+            if (progress) cv.notify_all();
+            else cv.wait_for(lk, std::chrono::microseconds(100));
         }
+    }
+
+    // worker side of an admission: device state and the first chunk, then the running set
+    void attach(std::unique_lock<std::mutex> &lk, const std::shared_ptr<Request> &r)
+    {
+        lk.unlock();
+        int rc = SIM_OK;
+        std::string err;
+        if (device >= 0) {
+            (void)hipSetDevice(device);
+            rc = sim::device_attach(r->h, streams[r->slot], static_cast<char *>(pool) + r->range_off, r->range_len,
+                                    &err);
+        }
+        if (rc == SIM_OK) rc = advance(r);
+        const bool cancelled_meanwhile = r->cancel;
+        if (cancelled_meanwhile && device >= 0) (void)hipStreamSynchronize(streams[r->slot]);
+        lk.lock();
+        r->attaching = false;
+        --attaching;
+        if (rc != SIM_OK) {
+            r->code = rc;
+            if (r->err.empty()) r->err = err;
+            retire(r, SRV_FAILED);
+        } else if (r->cancel) {
+            if (!cancelled_meanwhile && device >= 0) {
+                lk.unlock();
+                (void)hipStreamSynchronize(streams[r->slot]);
+                lk.lock();
+            }
+            retire(r, SRV_CANCELLED);
+        } else {
+            r->state = SRV_RUNNING;
+            running.push_back(r);
+        }
+        cv.notify_all();
     }
 
     void prepare_worker()
     {
         std::unique_lock<std::mutex> lk(mu);
         while (!stop) {
+            if (!attach_q.empty()) {
+                auto a = attach_q.front();
+                attach_q.pop_front();
+                attach(lk, a);
+                continue;
+            }
             std::shared_ptr<Request> r;
             for (auto &q : queue)
                 if (!q->prepared && !q->preparing && !q->cancel && q->state == SRV_QUEUED) { r = q; break; }
@@ -260,7 +396,7 @@ struct srv_t {
                 r->h = h;
                 r->footprint = sim::footprint_of(h);
                 r->prepared = true;
-                if (r->footprint > budget) {
+                if (((r->footprint + 255) & ~(size_t)255) > (budget & ~(size_t)255)) {
                     r->code = SIM_ENOMEM;
                     r->err = "request footprint " + std::to_string(r->footprint) + " B exceeds the server budget";
                     retire(r, SRV_FAILED);
@@ -291,13 +427,31 @@ int srv_create(int hip_device, size_t mem_budget_bytes, int32_t max_slots, int32
             return SIM_EDEVICE;
         }
         s->streams.resize(max_slots, nullptr);
-        for (auto &st : s->streams)
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-                for (auto x : s->streams) if (x) (void)hipStreamDestroy(x);
-                delete s;
-                return SIM_EDEVICE;
-            }
+        s->slot_ev.resize(max_slots, nullptr);
+        bool ok = true;
+        for (int k = 0; k < max_slots && ok; ++k)
+            ok = hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&s->slot_ev[k], hipEventDisableTiming) == hipSuccess;
+        int code = SIM_EDEVICE;
+        if (ok && hipMalloc(&s->pool, mem_budget_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            s->pool = nullptr;
+            ok = false;
+            code = SIM_ENOMEM;
+        }
+        if (!ok) {
+            for (auto x : s->streams) if (x) (void)hipStreamDestroy(x);
+            for (auto e : s->slot_ev) if (e) (void)hipEventDestroy(e);
+            delete s;
+            return code;
+        }
     }
+    s->slot_counts.assign(max_slots, nullptr);
+    s->slot_ttt.assign(max_slots, nullptr);
+    s->slot_vsteps.assign(max_slots, nullptr);
+    s->slot_nc.assign(max_slots, 0);
+    s->slot_ns.assign(max_slots, 0);
+    s->free_ranges[0] = mem_budget_bytes & ~(size_t)255;
     s->loop = std::thread([s] { s->run(); });
     const unsigned np = std::max(1u, std::min(4u, std::thread::hardware_concurrency()));
     for (unsigned k = 0; k < np; ++k) s->preps.emplace_back([s] { s->prepare_worker(); });
@@ -451,13 +605,15 @@ int srv_destroy(srv_t *s)
     }
     for (auto &kv : s->reqs) {
         auto &r = kv.second;
-        if (r->h) { sim::destroy_handle(r->h); r->h = nullptr; }
-        if (r->ev) (void)hipEventDestroy(r->ev);
-        if (r->counts) (void)hipHostFree(r->counts);
-        if (r->ttt) (void)hipHostFree(r->ttt);
-        if (r->vsteps) (void)hipHostFree(r->vsteps);
+        if (r->h) { sim::release_handle(r->h); r->h = nullptr; }
     }
+    for (sim_t *h : s->graveyard) sim::release_handle(h);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
+    for (auto e : s->slot_ev) (void)hipEventDestroy(e);
+    for (auto p : s->slot_counts) if (p) (void)hipHostFree(p);
+    for (auto p : s->slot_ttt) if (p) (void)hipHostFree(p);
+    for (auto p : s->slot_vsteps) if (p) (void)hipHostFree(p);
+    if (s->pool) (void)hipFree(s->pool);
     delete s;
     return SIM_OK;
 }

@@ -490,10 +490,12 @@ class Simulator:
         self._chk(self._L.sim_set_timing(self._h, int(on)))
 
     def timing(self, reset: bool = True):
-        ms = np.zeros(4, np.float64)
-        n = np.zeros(4, np.int64)
-        self._chk(self._L.sim_get_timing(self._h, _p(ms), _p(n), 4, int(reset)))
-        names = ("link", "node", "reverse", "copy")
+        """(ms, launches) per kind: link, node, reverse (each launch's own wave stamps), copy, and
+        link_ev, node_ev, reverse_ev (the same launches between HIP events on their stream)."""
+        ms = np.zeros(7, np.float64)
+        n = np.zeros(7, np.int64)
+        self._chk(self._L.sim_get_timing(self._h, _p(ms), _p(n), 7, int(reset)))
+        names = ("link", "node", "reverse", "copy", "link_ev", "node_ev", "reverse_ev")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
 
 
