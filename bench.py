@@ -408,7 +408,7 @@ def profile_pass(args):
         return
     w = make_workload(args.workload, args.sim_steps)
     T = w.cfg.steps
-    sim = Simulator(w, record=True, max_steps=T)
+    sim = Simulator(w, record=True, max_steps=T, tape_windows=(T + w.cfg.ckpt_every - 1) // w.cfg.ckpt_every)
     gQ = torch.ones((1, w.net.n_detectors, sim.n_count_bins), dtype=torch.float32, device=dev)
     gT = torch.ones(1, dtype=torch.float64, device=dev)
     if args.schedule:
@@ -459,8 +459,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--profile-pass", action="store_true", help="one forward+adjoint pass only")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tape-windows", type=int, default=16,
-                    help="windows of replay tape kept on the device (the forward tapes the last ones)")
+    ap.add_argument("--tape-windows", type=int, default=-1,
+                    help="windows of replay tape kept on the device (the forward tapes the last ones); "
+                         "-1: every window of the rollout, so the backward replays none")
     ap.add_argument("--no-control", action="store_true", help="skip the batched-control leg")
     ap.add_argument("--no-calibration", action="store_true", help="skip the calibration and cost-control legs")
     ap.add_argument("--schedule", default="", help="g_link,g_node,g_rev instead of the autotuner's choice")
@@ -487,6 +488,8 @@ def main():
     gen_s = time.perf_counter() - t_gen
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.tape_windows < 0:   # 288 GB of HBM hold every window's tape (about 2 GB each at 1M agents)
+        args.tape_windows = (T + w.cfg.ckpt_every - 1) // w.cfg.ckpt_every
     sim = Simulator(w, record=True, max_steps=T, tape_windows=args.tape_windows)
     fwd = Simulator(w, record=False)
     S, L, Nn, O = 1, w.net.n_links, w.net.n_nodes, w.net.n_origins

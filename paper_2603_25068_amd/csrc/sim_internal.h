@@ -35,6 +35,24 @@ enum { ERR_RING_OVERFLOW = 0, ERR_CAND_OVERFLOW = 1, ERR_N = 4 };
 enum { TIE_CHOICE = SIM_TIE_CHOICE, TIE_MERGE = SIM_TIE_MERGE };
 constexpr int kTieLogMax = SIM_TIE_LOG_MAX;
 
+// Per (scenario, link) state the link and node phases exchange, one 32-byte record, so that a
+// phase touches one cache line per link instead of one per field.  Writers: the link phase (B,
+// slots, nheads of its segment), the node phase at the link's head node (B, E, rhead) and at its
+// tail node (rtail); different fields of one record are never written by two items of a launch.
+struct __align__(32) LinkSt {
+    double B;          // token bucket (before this step's idle cap)
+    int64_t E;         // cumulative outflow
+    int32_t rhead, rtail;    // ring counters (rtail is the next entry sequence number)
+    int32_t slots, nheads;   // entry slots and heads found by this step's link phase
+};
+// Per (scenario, link) constants of the node phase, derived when parameters change (one record
+// per out-link or in-link lane instead of six scattered arrays).
+struct __align__(32) LinkNd {
+    double util;       // beta / cost
+    float alpha;       // merge priority
+    int32_t head, tail, ring_base, cap, lanes;
+};
+
 struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
@@ -83,11 +101,9 @@ struct Dev {
     float *ring_pos;
     int32_t *ring_agent;
     int2 *ring_aux;                  // [S * ring_total] (destination node, table row) of each slot's agent
-    int32_t *rhead, *rtail;          // [S*L]
-    double *B;                       // token bucket [S*L]
+    LinkSt *ls;                      // [S*L] bucket, outflow, ring counters, entry slots, heads
+    const LinkNd *lnd;               // [S*L] node-phase constants
     double *dB;                      // [S*L] dB/d cap_mult (recording handles only, else null)
-    int64_t *E;                      // cumulative outflow [S*L]
-    int32_t *slots, *nheads;         // [S*L]
     int4 *head_rec;                  // [S*L*maxl] (agent, destination, table row, -) of each head
     uint8_t *status;                 // [S*N]
     double *tstar;                   // [S*N] release time (rate mode)
@@ -172,7 +188,7 @@ int segsort_scratch_init(int device);
 int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
                            int32_t *perm, int32_t *seg_off, int32_t *status, hipStream_t st);
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
-                   const float *cost, double *util, double *acc, float *vfree, float *spacing,
+                   const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
                    hipStream_t st);
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st);
 void launch_counts(const Dev &d, float *out, hipStream_t st);

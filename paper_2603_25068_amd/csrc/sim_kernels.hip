@@ -236,7 +236,9 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     const int gl = g.gl;
     const int s = seg / d.L, j = seg - s * d.L;
     const int cap = d.cap[j], ln = d.lanes[j];
-    const int h0 = d.rhead[seg], n_raw = d.rtail[seg] - h0;
+    // ring counters, this link's entry slots and heads: one record (rhead, rtail, slots, nheads)
+    const int4 rc4 = *reinterpret_cast<const int4 *>(&d.ls[seg].rhead);
+    const int h0 = rc4.x, n_raw = rc4.y - h0;
     const int n = min(n_raw, cap);   // an overflowing ring (flagged below) is never read past its end
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
     const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j], thr = d.thr[j];
@@ -254,10 +256,10 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     double Bv = 0.0, accv = 0.0, dBv = 0.0;
     int64_t Ev = 0;
     if (gl == 0) {
-        Bv = d.B[seg];
+        Bv = d.ls[seg].B;
         accv = d.acc[seg];
         if (d.dB) dBv = d.dB[seg];
-        if (sample_b >= 0) Ev = d.E[seg];
+        if (sample_b >= 0) Ev = d.ls[seg].E;
     }
     int64_t tb = -1;
     if (TAPE) {   // a recording step (tape_k >= 0)
@@ -329,11 +331,10 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     }
     const int h = min(nh, min(ln, d.maxl));
     if (gl == 0) {
-        d.B[seg] = (Bv > 1.0 ? 1.0 : Bv) + accv;
+        d.ls[seg].B = (Bv > 1.0 ? 1.0 : Bv) + accv;
         // tangent of the level in the multiplier; the idle cap clears it
         if (d.dB) d.dB[seg] = (Bv > 1.0 ? 0.0 : dBv) + (double)d.capacity[j] * (double)ln * d.dt;
-        d.slots[seg] = max(0, ln - nocc);
-        d.nheads[seg] = h;
+        *reinterpret_cast<int2 *>(&d.ls[seg].slots) = make_int2(max(0, ln - nocc), h);
         if (viol)
             atomicAdd((unsigned long long *)&d.ctr[((int64_t)s * kCtrSlots) * CTR_N + CTR_ORDER_VIOL],
                       (unsigned long long)viol);
@@ -484,14 +485,16 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     // ---- out-link lanes ----
     int om = -1, ohead = -1, oslots = 0, otail = 0, obase = 0, ocap = 1;
     double outil = 0.0;
-    if (gl < dego) {
+    if (gl < dego) {   // two records: the out-link's constants and its (rhead, rtail, slots, nheads)
         om = om_raw;
-        ohead = d.head[om];
-        outil = d.util[sL + om];
-        oslots = d.slots[sL + om];
-        otail = d.rtail[sL + om];
-        obase = d.ring_base[om];
-        ocap = d.cap[om];
+        const LinkNd c = d.lnd[sL + om];
+        const int4 q = *reinterpret_cast<const int4 *>(&d.ls[sL + om].rhead);
+        ohead = c.head;
+        outil = c.util;
+        oslots = q.z;
+        otail = q.y;
+        obase = c.ring_base;
+        ocap = c.cap;
     }
     // ---- in-link lanes (resolve) ----
     int64_t sjq = -1;
@@ -501,10 +504,11 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     const bool graft = tape_k >= 0 && d.tape_dstg != nullptr;   // admission-graft tape (recording replay)
     if (gl < deg) {   // everything this lane updates at the end is read here, with the first loads
         sjq = sL + jin_res;
-        Bj = d.B[sjq];
-        nhq = d.nheads[sjq];
-        hq0 = d.rhead[sjq];
-        Eq0 = d.E[sjq];
+        const LinkSt st = d.ls[sjq];
+        Bj = st.B;
+        nhq = st.nheads;
+        hq0 = st.rhead;
+        Eq0 = st.E;
         if (graft) dBj = d.dB[sjq];
     }
     const double Bacc = Bj;   // accrued level before this step's tokens
@@ -515,10 +519,11 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         const int r = hr_r;
         const int jj = jin_cand;
         const int64_t sj = sL + jj;
-        const int nh = d.nheads[sj];
+        const int nh = d.ls[sj].nheads;
         const int4 hr = d.head_rec[sj * maxl + r];
-        const float al = d.alpha[sj];
-        const int tl = d.tail[jj];
+        const LinkNd c = d.lnd[sj];
+        const float al = c.alpha;
+        const int tl = c.tail;
         if (r < nh) { ag = hr.x; dst = hr.y; didx = hr.z; from = jj; alpha = (double)al; ftail = tl; }
     } else if (gl < nc) {
         const int2 oq = d.org_pad[(int64_t)v * d.max_org + (gl - ncin)];
@@ -731,10 +736,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         }
     }
     if (gl < deg) {
-        if (consumed) d.B[sjq] = Bj;   // the idle cap min(B, 1) is applied at the next accrual
+        if (consumed) d.ls[sjq].B = Bj;   // the idle cap min(B, 1) is applied at the next accrual
         if (np) {
-            d.E[sjq] = Eq0 + np;
-            d.rhead[sjq] = hq0 + np;
+            d.ls[sjq].E = Eq0 + np;
+            d.ls[sjq].rhead = hq0 + np;
         }
     }
     const int q_of_lane = qi;
@@ -756,7 +761,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
             if (o.key > key || (o.key == key && o.ag < ag)) ++erank;
         }
     }
-    if (gl < dego && nent) d.rtail[sL + om] = otail + nent;
+    if (gl < dego && nent) d.ls[sL + om].rtail = otail + nent;
     int tbase = 0, rbase = 0, rcap = 1;
     if (ch >= 0) {
         const OutRec o = orc[argk];
@@ -886,7 +891,7 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
     const int seg = xcd_tile() * kWavesPerBlock + (threadIdx.x >> 6);
     if (seg >= d.S * d.L) return;
     const int s = seg / d.L, j = seg - s * d.L;
-    const int h0 = d.rhead[seg], n = d.rtail[seg] - h0, cap = d.cap[j];
+    const int h0 = d.ls[seg].rhead, n = d.ls[seg].rtail - h0, cap = d.cap[j];
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
     const int64_t tb = (int64_t)tape_k * d.S * d.ring_total + base;
     if (lane == 0) {
@@ -1362,7 +1367,7 @@ __global__ __launch_bounds__(256) void k_rate_grad(Dev d, float *g)
 
 // Derived per-(scenario, link) constants.
 __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, const float *beta,
-                         const float *cost, double *util, double *acc, float *vfree, float *spacing)
+                         const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)d.S * d.L) return;
@@ -1371,6 +1376,15 @@ __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, co
     spacing[i] = __fdiv_rn((float)d.platoon, d.kappa[i]);
     util[i] = (double)beta[i] / (double)cost[i];
     acc[i] = (double)cap_mult[i] * (double)capacity[j] * (double)d.lanes[j] * d.dt;
+    LinkNd c;
+    c.util = (double)beta[i] / (double)cost[i];
+    c.alpha = d.alpha[i];
+    c.head = d.head[j];
+    c.tail = d.tail[j];
+    c.ring_base = d.ring_base[j];
+    c.cap = d.cap[j];
+    c.lanes = d.lanes[j];
+    lnd[i] = c;
 }
 
 // Total travel time and vehicle-steps per scenario: dt * sum over released
@@ -1817,11 +1831,12 @@ void launch_rate_grad(const Dev &d, float *g, hipStream_t st)
     hipLaunchKernelGGL(k_rate_grad, dim3(blocks_for((int64_t)d.S * d.O)), dim3(256), 0, st, d, g);
 }
 void launch_derive(const Dev &d, const float *cap_mult, const float *capacity, const float *beta,
-                   const float *cost, double *util, double *acc, float *vfree, float *spacing, hipStream_t st)
+                   const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
+                   hipStream_t st)
 {
     const int64_t n = (int64_t)d.S * d.L;
     hipLaunchKernelGGL(k_derive, dim3((int)((n + 255) / 256)), dim3(256), 0, st, d, cap_mult, capacity, beta, cost,
-                       util, acc, vfree, spacing);
+                       util, acc, vfree, spacing, lnd);
 }
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st)
 {

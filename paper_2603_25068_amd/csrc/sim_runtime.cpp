@@ -53,9 +53,8 @@ struct Ckpt {
     float *ring_pos = nullptr;
     int32_t *ring_agent = nullptr;
     int2 *ring_aux = nullptr;
-    int32_t *rhead = nullptr, *rtail = nullptr;
-    double *B = nullptr, *dB = nullptr;
-    int64_t *E = nullptr;
+    sim::LinkSt *ls = nullptr;
+    double *dB = nullptr;
     double *Dacc = nullptr;
     int32_t *rel_ptr = nullptr, *dep_ptr = nullptr;
     int64_t *ctr = nullptr;
@@ -135,6 +134,7 @@ struct sim_t {
     int32_t *tune_tie_n = nullptr;
     float *vfree = nullptr, *spacing = nullptr;
     double *util = nullptr, *acc = nullptr;
+    sim::LinkNd *lnd_dev = nullptr;
     // mutable queue buffers
     int32_t *q_off_dev = nullptr, *q_list_dev = nullptr, *q_dest_dev = nullptr, *q_didx_dev = nullptr;
     int64_t *q_rstep_dev = nullptr;
@@ -398,13 +398,8 @@ void zero_state(sim_t *h)
     Dev &d = h->d;
     const hipStream_t st = h->stream;
     const size_t SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N, SO = (size_t)h->S * h->O;
-    HIPCHK(hipMemsetAsync(d.rhead, 0, SL * 4, st));
-    HIPCHK(hipMemsetAsync(d.rtail, 0, SL * 4, st));
-    HIPCHK(hipMemsetAsync(d.B, 0, SL * 8, st));
+    HIPCHK(hipMemsetAsync(d.ls, 0, SL * sizeof(sim::LinkSt), st));
     if (d.dB) HIPCHK(hipMemsetAsync(d.dB, 0, SL * 8, st));
-    HIPCHK(hipMemsetAsync(d.E, 0, SL * 8, st));
-    HIPCHK(hipMemsetAsync(d.slots, 0, SL * 4, st));
-    HIPCHK(hipMemsetAsync(d.nheads, 0, SL * 4, st));
     HIPCHK(hipMemsetAsync(d.status, 0, SN, st));
     HIPCHK(hipMemsetAsync(d.tstar, 0, SN * 8, st));
     HIPCHK(hipMemsetAsync(d.rel_t, 0xff, SN * 4, st));
@@ -569,12 +564,15 @@ void build_classes(sim_t *h)
 void derive(sim_t *h)
 {
     sim::launch_derive(h->d, h->p_capm, h->capacity_dev, h->p_beta, h->p_cost, h->util, h->acc, h->vfree, h->spacing,
-                       h->stream);
+                       h->lnd_dev, h->stream);
     HIPCHK(hipGetLastError());
 }
 
 void check_device_errors(sim_t *h)
 {
+    // under stream capture nothing may wait: the flags are read by the next call outside capture
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (h->stream && hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
     int32_t e[sim::ERR_N];
     HIPCHK(hipMemcpyAsync(e, h->d.err, sizeof(e), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -589,11 +587,8 @@ void ckpt_alloc(sim_t *h, Ckpt &c)
     c.ring_pos = h->dalloc<float>(SR);
     c.ring_agent = h->dalloc<int32_t>(SR);
     c.ring_aux = h->dalloc<int2>(SR);
-    c.rhead = h->dalloc<int32_t>(SL);
-    c.rtail = h->dalloc<int32_t>(SL);
-    c.B = h->dalloc<double>(SL);
+    c.ls = h->dalloc<sim::LinkSt>(SL);
     c.dB = h->dalloc<double>(SL);
-    c.E = h->dalloc<int64_t>(SL);
     c.Dacc = h->dalloc<double>(SO);
     c.rel_ptr = h->dalloc<int32_t>(SO);
     c.dep_ptr = h->dalloc<int32_t>(SO);
@@ -613,11 +608,8 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save, Dev *target = nullptr, hipStream_t 
     cp(c.ring_pos, d.ring_pos, SR * 4);
     cp(c.ring_agent, d.ring_agent, SR * 4);
     cp(c.ring_aux, d.ring_aux, SR * 8);
-    cp(c.rhead, d.rhead, SL * 4);
-    cp(c.rtail, d.rtail, SL * 4);
-    cp(c.B, d.B, SL * 8);
+    cp(c.ls, d.ls, SL * sizeof(sim::LinkSt));
     if (d.dB) cp(c.dB, d.dB, SL * 8);
-    cp(c.E, d.E, SL * 8);
     cp(c.Dacc, d.Dacc, SO * 8);
     cp(c.rel_ptr, d.rel_ptr, SO * 4);
     cp(c.dep_ptr, d.dep_ptr, SO * 4);
@@ -629,8 +621,7 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save, Dev *target = nullptr, hipStream_t 
 void with_state(Dev &dst, const Dev &src)
 {
     dst.ring_pos = src.ring_pos; dst.ring_agent = src.ring_agent; dst.ring_aux = src.ring_aux;
-    dst.rhead = src.rhead; dst.rtail = src.rtail; dst.B = src.B; dst.dB = src.dB; dst.E = src.E;
-    dst.slots = src.slots; dst.nheads = src.nheads; dst.head_rec = src.head_rec;
+    dst.ls = src.ls; dst.dB = src.dB; dst.head_rec = src.head_rec;
     dst.status = src.status; dst.tstar = src.tstar; dst.rel_t = src.rel_t; dst.dep_t = src.dep_t;
     dst.exit_t = src.exit_t; dst.Dacc = src.Dacc; dst.rel_ptr = src.rel_ptr; dst.dep_ptr = src.dep_ptr;
     dst.ctr = src.ctr; dst.cum = src.cum;
@@ -896,7 +887,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     // (the serving pool carves a request's state with that alignment)
     const size_t nQ = (size_t)h->S * h->D * std::max(h->nb, 1);
     size_t bytes = SR * 16                                   // ring positions, agents, (destination, row)
-                   + SL * (24 + 8 + 16 + 32 + maxl * 16)     // parameters, derived, state, head records
+                   + SL * (24 + 8 + 16 + 32 + 32 + maxl * 16)   // parameters, derived, state, node constants, heads
                    + SN * (1 + 8 + 12) + SO * 16             // per agent and per origin state
                    + (size_t)h->S * h->O * std::max(h->B, 1) * 4
                    + (size_t)L * 56 + (size_t)Nn * 32        // link constants, node offsets and words
@@ -909,7 +900,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     if (h->record) {
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
         h->W = h->ckpt_every;
-        bytes += (size_t)n_ck * (SR * 16 + SL * 32 + SO * 16 + SN);
+        bytes += (size_t)n_ck * (SR * 16 + SL * 40 + SO * 16 + SN);
         // one tape set: positions and agents per slot, head/tail per segment, entry slot and graft factor
         // per leaving head, and a straight-through record per node candidate, for W + 1 states
         const size_t per_set = (size_t)(h->W + 1) *
@@ -993,9 +984,9 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.vfree = h->vfree; d.spacing = h->spacing; d.util = h->util; d.acc = h->acc;
     // state
     d.ring_pos = h->dalloc<float>(SR); d.ring_agent = h->dalloc<int32_t>(SR); d.ring_aux = h->dalloc<int2>(SR);
-    d.rhead = h->dalloc<int32_t>(SL); d.rtail = h->dalloc<int32_t>(SL);
-    d.B = h->dalloc<double>(SL); d.E = h->dalloc<int64_t>(SL);
-    d.slots = h->dalloc<int32_t>(SL); d.nheads = h->dalloc<int32_t>(SL);
+    d.ls = h->dalloc<sim::LinkSt>(SL);
+    h->lnd_dev = h->dalloc<sim::LinkNd>(SL);
+    d.lnd = h->lnd_dev;
     d.head_rec = h->dalloc<int4>(SL * maxl);
     d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
     d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
@@ -1031,9 +1022,8 @@ void allocate_device(sim_t *h, const sim_config *cfg)
             r.tie_log = nullptr;     // a replay repeats decisions already logged by the forward
             r.tie_n = nullptr;
             r.ring_pos = h->dalloc<float>(SR); r.ring_agent = h->dalloc<int32_t>(SR); r.ring_aux = h->dalloc<int2>(SR);
-            r.rhead = h->dalloc<int32_t>(SL); r.rtail = h->dalloc<int32_t>(SL);
-            r.B = h->dalloc<double>(SL); r.dB = h->dalloc<double>(SL); r.E = h->dalloc<int64_t>(SL);
-            r.slots = h->dalloc<int32_t>(SL); r.nheads = h->dalloc<int32_t>(SL); r.head_rec = h->dalloc<int4>(SL * maxl);
+            r.ls = h->dalloc<sim::LinkSt>(SL);
+            r.dB = h->dalloc<double>(SL); r.head_rec = h->dalloc<int4>(SL * maxl);
             r.status = h->dalloc<uint8_t>(SN); r.tstar = h->dalloc<double>(SN);
             r.rel_t = h->dalloc<int32_t>(SN); r.dep_t = h->dalloc<int32_t>(SN); r.exit_t = h->dalloc<int32_t>(SN);
             r.Dacc = h->dalloc<double>(SO); r.rel_ptr = h->dalloc<int32_t>(SO); r.dep_ptr = h->dalloc<int32_t>(SO);
@@ -1386,11 +1376,11 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         // current (empty, t = 0) rings and per-agent arrays
         const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
         std::vector<float> rp(SR, 0.f);
-        std::vector<int32_t> ra(SR, 0), rt(SL, 0), rh(SL, 0);
+        std::vector<int32_t> ra(SR, 0);
+        std::vector<sim::LinkSt> ls(SL);
         std::vector<int2> rx(SR);
         HIPCHK(hipMemcpyAsync(rx.data(), h->d.ring_aux, SR * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(rh.data(), h->d.rhead, SL * 4, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(rt.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ls.data(), h->d.ls, SL * sizeof(sim::LinkSt), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(rp.data(), h->d.ring_pos, SR * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(ra.data(), h->d.ring_agent, SR * 4, hipMemcpyDeviceToHost, h->stream));
         std::vector<uint8_t> st(SN);
@@ -1405,11 +1395,11 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
             for (int k = 0; k < n; ++k) {
                 const int j = lk[k];
                 const size_t seg = (size_t)s * h->L + j;
-                const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (rt[seg] % h->cap[j]);
+                const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (ls[seg].rtail % h->cap[j]);
                 ra[slot] = agent[k];
                 rx[slot] = make_int2(h->agent_dest[agent[k]], h->agent_didx[agent[k]]);
                 rp[slot] = pos[k];
-                rt[seg] += 1;
+                ls[seg].rtail += 1;
                 const size_t ga = (size_t)s * h->N + agent[k];
                 st[ga] = sim::AG_ON;
                 relt[ga] = 0;
@@ -1418,7 +1408,7 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
             ctr[(size_t)s * sim::kCtrSlots * sim::CTR_N + sim::CTR_RELEASED] += n;
             ctr[(size_t)s * sim::kCtrSlots * sim::CTR_N + sim::CTR_DEPARTED] += n;
         }
-        HIPCHK(hipMemcpyAsync(h->d.rtail, rt.data(), SL * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.ls, ls.data(), SL * sizeof(sim::LinkSt), hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ring_pos, rp.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ring_agent, ra.data(), SR * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ring_aux, rx.data(), SR * 8, hipMemcpyHostToDevice, h->stream));
@@ -1660,12 +1650,12 @@ int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t 
     return guarded(h, [&] {
         const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SN = (size_t)h->S * h->N;
         std::vector<float> rp(SR);
-        std::vector<int32_t> ra(SR), rh(SL), rt(SL);
+        std::vector<int32_t> ra(SR);
+        std::vector<sim::LinkSt> ls(SL);
         std::vector<uint8_t> st(SN);
         HIPCHK(hipMemcpyAsync(rp.data(), h->d.ring_pos, SR * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(ra.data(), h->d.ring_agent, SR * 4, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(rh.data(), h->d.rhead, SL * 4, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(rt.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ls.data(), h->d.ls, SL * sizeof(sim::LinkSt), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(st.data(), h->d.status, SN, hipMemcpyDeviceToHost, h->stream));
         std::vector<int64_t> ctr((size_t)h->S * sim::kCtrSlots * sim::CTR_N);
         HIPCHK(hipMemcpyAsync(ctr.data(), h->d.ctr, ctr.size() * 8, hipMemcpyDeviceToHost, h->stream));
@@ -1677,7 +1667,7 @@ int sim_get_state(sim_t *h, int32_t *status, int32_t *link, float *pos, int32_t 
         for (int s = 0; s < h->S; ++s)
             for (int j = 0; j < h->L; ++j) {
                 const size_t seg = (size_t)s * h->L + j;
-                for (int q = rh[seg]; q < rt[seg]; ++q) {
+                for (int q = ls[seg].rhead; q < ls[seg].rtail; ++q) {
                     const size_t slot = (size_t)s * h->ring_total + h->ring_base[j] + (q % h->cap[j]);
                     const size_t ga = (size_t)s * h->N + ra[slot];
                     if (link) link[ga] = h->lperm[j];
@@ -1728,8 +1718,8 @@ std::vector<std::pair<void *, size_t>> state_arrays(sim_t *h)
     const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
     const size_t SN = (size_t)h->S * h->N, nc = (size_t)h->S * h->D * std::max(h->nb, 1);
     std::vector<std::pair<void *, size_t>> a = {
-        {d.ring_pos, SR * 4}, {d.ring_agent, SR * 4}, {d.ring_aux, SR * 8}, {d.rhead, SL * 4}, {d.rtail, SL * 4}, {d.B, SL * 8},
-        {d.E, SL * 8}, {d.Dacc, SO * 8}, {d.rel_ptr, SO * 4}, {d.dep_ptr, SO * 4},
+        {d.ring_pos, SR * 4}, {d.ring_agent, SR * 4}, {d.ring_aux, SR * 8}, {d.ls, SL * sizeof(sim::LinkSt)},
+        {d.Dacc, SO * 8}, {d.rel_ptr, SO * 4}, {d.dep_ptr, SO * 4},
         {d.ctr, (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8}, {d.status, SN}, {d.tstar, SN * 8},
         {d.rel_t, SN * 4}, {d.dep_t, SN * 4}, {d.exit_t, SN * 4}, {d.cum, nc * 4}};
     if (d.dB) a.push_back({d.dB, SL * 8});
@@ -1847,20 +1837,16 @@ int sim_get_link_state(sim_t *h, double *B, int64_t *E, int32_t *next_seq)
 {
     return guarded(h, [&] {
         const size_t SL = (size_t)h->S * h->L;
-        std::vector<double> b(SL);
-        std::vector<int64_t> e(SL);
-        std::vector<int32_t> ns(SL);
-        HIPCHK(hipMemcpyAsync(b.data(), h->d.B, SL * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(e.data(), h->d.E, SL * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(ns.data(), h->d.rtail, SL * 4, hipMemcpyDeviceToHost, h->stream));
+        std::vector<sim::LinkSt> ls(SL);
+        HIPCHK(hipMemcpyAsync(ls.data(), h->d.ls, SL * sizeof(sim::LinkSt), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         for (int s = 0; s < h->S; ++s)
             for (int jo = 0; jo < h->L; ++jo) {
                 const size_t o = (size_t)s * h->L + jo, i = (size_t)s * h->L + h->linv[jo];
                 // the device keeps the bucket before the end-of-step idle cap min(B, 1)
-                if (B) B[o] = b[i] > 1.0 ? 1.0 : b[i];
-                if (E) E[o] = e[i];
-                if (next_seq) next_seq[o] = ns[i];
+                if (B) B[o] = ls[i].B > 1.0 ? 1.0 : ls[i].B;
+                if (E) E[o] = ls[i].E;
+                if (next_seq) next_seq[o] = ls[i].rtail;
             }
     });
 }

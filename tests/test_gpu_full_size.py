@@ -68,7 +68,7 @@ def test_metro_full_horizon_with_tie_adoption():
     w = W.metro()
     T, Th = w.cfg.steps, w.cfg.steps // 2
     t0 = time.perf_counter()
-    s = Simulator(w, record=True, max_steps=T, tape_windows=16)
+    s = Simulator(w, record=True, max_steps=T, tape_windows=T // w.cfg.ckpt_every)   # every window taped
     s.rollout()
     s.autotune(probe_steps=30)          # as the benchmark: tuned on the end-of-rollout state
     s.reset()
