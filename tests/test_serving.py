@@ -65,6 +65,27 @@ def test_memory_budget_bounds_concurrency():
         assert s.stats()["max_running"] == 2
 
 
+def test_pool_ranges_are_reused_across_sizes():
+    """Requests of two sizes share the server's pool: each takes a contiguous range of its
+    footprint (first fit), freed ranges merge with their neighbours, so a large request waits for
+    adjacent small ones to finish and then runs; every request completes and no more run at once
+    than the pool holds."""
+    from paper_2603_25068_amd.sim import SRV_DONE, footprint
+    small = W.random_small(4, nx=4, ny=4, n_agents=1500, steps=100)
+    big = W.random_small(5, nx=8, ny=8, n_agents=40000, steps=100)
+    fs = (footprint(small, steps=100) + 255) // 256 * 256
+    fb = (footprint(big, steps=100) + 255) // 256 * 256
+    assert fb > 2 * fs
+    budget = fb + fs
+    order = [small, small, big, small, big, small, small, big]
+    with _srv(device=-1, mem_budget_bytes=budget, max_slots=8, chunk_steps=10) as s:
+        ts = [s.submit(w, steps=100) for w in order]
+        assert all(s.wait(t, 60.0) == SRV_DONE for t in ts)
+        st = s.stats()
+        assert st["completed"] == len(order)
+        assert 2 <= st["max_running"] <= budget // fs
+
+
 def test_oversize_request_fails_alone():
     from paper_2603_25068_amd.sim import SRV_DONE, SRV_FAILED, SIM_ENOMEM, SimError, footprint
     small = W.random_small(5, nx=4, ny=4, n_agents=300, steps=100)
