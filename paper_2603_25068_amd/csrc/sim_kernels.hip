@@ -242,7 +242,8 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
     const int n = min(n_raw, cap);   // an overflowing ring (flagged below) is never read past its end
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
     const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j], thr = d.thr[j];
-    const int d0 = d.det_off[j], nd = d.det_off[j + 1] - d0;
+    // detector crossings are needed on sampling steps only: skip their loads and counts otherwise
+    const int d0 = sample_b >= 0 ? d.det_off[j] : 0, nd = sample_b >= 0 ? d.det_off[j + 1] - d0 : 0;
     const int hm = h0 % cap;
     auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     // head records (speculatively, lanes below the lane count)
@@ -306,14 +307,14 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
             }
         }
         wave_lds_sync();
-        float prev_last = INFINITY;
         for (int r0 = lo; r0 < hi; r0 += G) {
             const int r = r0 + gl;
             const bool v = r < hi;
-            float x = 0.f, xl = 0.f;
+            float x = 0.f, xl = 0.f, xp = INFINITY;
             if (v) {
                 x = buf[r - slo];
                 if (r >= ln) xl = buf[r - ln - slo];
+                if (r > slo) xp = buf[r - 1 - slo];   // the rank ahead, for the order check
             }
             const float xh = cf_update(x, xl, r >= ln, vf, sp, Lj);
             if (v) d.ring_pos[base + slot_of(r)] = xh;
@@ -322,10 +323,8 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
 #pragma unroll
             for (int k = 0; k < kMaxDetPerLink; ++k)
                 if (k < nd) dcnt[k] += g.count(v && xh >= dpos[k]);
-            float up = __shfl_up(xh, 1, G);
-            if (gl == 0) up = prev_last;
-            viol += g.count(v && r > lo && up < xh);
-            prev_last = __shfl(xh, G - 1, G);
+            // the step's input order (entrants of the previous step included): position descending
+            viol += g.count(v && xp < x);
         }
         wave_lds_sync();
     }
