@@ -131,7 +131,9 @@ typedef struct sim_t sim_t;
 /* Validate, copy the inputs, compute shortest free-flow times to every
  * destination (route-choice term), allocate device state on `hip_device`.
  * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all
- * later device work.  On error *out is NULL and nothing is leaked. */
+ * later device work.  On error *out is NULL and nothing is leaked.
+ * SIM_EUNSUPPORTED for more than 4 detectors on one link or 2^24 or more
+ * detectors in all. */
 int sim_create(const sim_network *net, const sim_demand *dem, const sim_config *cfg,
                int hip_device, void *hip_stream, sim_t **out);
 

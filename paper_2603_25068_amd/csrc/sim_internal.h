@@ -53,6 +53,14 @@ struct __align__(32) LinkNd {
     int32_t head, tail, ring_base, cap, lanes;
 };
 
+// Per (scenario, link) constants of the link and reverse phases, derived when parameters change
+// (one record per segment instead of nine arrays).
+struct __align__(32) LinkCf {
+    float vf, sp, L, thr;        // u * dt, jam spacing dn / kappa, length, arrival threshold L - 0.01
+    int32_t cap, lanes, ring_base;
+    int32_t det;                 // first detector (bits 0-23) | detectors on the link << 24
+};
+
 struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
@@ -103,6 +111,7 @@ struct Dev {
     int2 *ring_aux;                  // [S * ring_total] (destination node, table row) of each slot's agent
     LinkSt *ls;                      // [S*L] bucket, outflow, ring counters, entry slots, heads
     const LinkNd *lnd;               // [S*L] node-phase constants
+    const LinkCf *lcf;               // [S*L] link- and reverse-phase constants
     double *dB;                      // [S*L] dB/d cap_mult (recording handles only, else null)
     int4 *head_rec;                  // [S*L*maxl] (agent, destination, table row, -) of each head
     uint8_t *status;                 // [S*N]
@@ -189,7 +198,7 @@ int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, con
                            int32_t *perm, int32_t *seg_off, int32_t *status, hipStream_t st);
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
-                   hipStream_t st);
+                   LinkCf *lcf, hipStream_t st);
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st);
 void launch_counts(const Dev &d, float *out, hipStream_t st);
 void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st);

@@ -235,15 +235,16 @@ __device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg,
 {
     const int gl = g.gl;
     const int s = seg / d.L, j = seg - s * d.L;
-    const int cap = d.cap[j], ln = d.lanes[j];
+    const LinkCf lc = d.lcf[seg];
+    const int cap = lc.cap, ln = lc.lanes;
     // ring counters, this link's entry slots and heads: one record (rhead, rtail, slots, nheads)
     const int4 rc4 = *reinterpret_cast<const int4 *>(&d.ls[seg].rhead);
     const int h0 = rc4.x, n_raw = rc4.y - h0;
     const int n = min(n_raw, cap);   // an overflowing ring (flagged below) is never read past its end
-    const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
-    const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j], thr = d.thr[j];
+    const int64_t base = (int64_t)s * d.ring_total + lc.ring_base;
+    const float vf = lc.vf, sp = lc.sp, Lj = lc.L, thr = lc.thr;
     // detector crossings are needed on sampling steps only: skip their loads and counts otherwise
-    const int d0 = sample_b >= 0 ? d.det_off[j] : 0, nd = sample_b >= 0 ? d.det_off[j + 1] - d0 : 0;
+    const int d0 = lc.det & 0xffffff, nd = sample_b >= 0 ? (lc.det >> 24) : 0;
     const int hm = h0 % cap;
     auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     // head records (speculatively, lanes below the lane count)
@@ -933,16 +934,17 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
                                                 float *buf, int bufcap)
 {
     const int gl = g.gl;
-    const int s = seg / d.L, j = seg - s * d.L;
+    const int s = seg / d.L;
     const int64_t SL = (int64_t)d.S * d.L;
-    const int cap = d.cap[j], ln = d.lanes[j];
+    const LinkCf lc = d.lcf[seg];
+    const int cap = lc.cap, ln = lc.lanes;
     const int hk = d.tape_head[tape_k * SL + seg];
     const int n = min(d.tape_tail[tape_k * SL + seg] - hk, cap);
     const int npass = init ? 0 : d.tape_head[(tape_k + 1) * SL + seg] - hk;
-    const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
+    const int64_t base = (int64_t)s * d.ring_total + lc.ring_base;
     const int64_t RTS = (int64_t)d.S * d.ring_total;
     const int64_t tb = (int64_t)tape_k * RTS + base;
-    const float vf = d.vfree[seg], sp = d.spacing[seg], Lj = d.length[j];
+    const float vf = lc.vf, sp = lc.sp, Lj = lc.L;
     const float uj = d.u[seg], kap = d.kappa[seg];
     const double dkap = (double)d.platoon / ((double)kap * (double)kap);
     const double gTs = d.gT ? d.gT[s] : 0.0;
@@ -952,7 +954,7 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
     auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     int sb = -1;
     if (d.gQ && d.cbs > 0 && t > 0 && t % d.cbs == 0 && t / d.cbs <= d.nb) sb = t / d.cbs - 1;
-    const int d0 = d.det_off[j], nd = d.det_off[j + 1] - d0;
+    const int d0 = lc.det & 0xffffff, nd = lc.det >> 24;
     const float sc = 5.0f / Lj;
     const int P = bufcap / 2;
     float *xb = buf, *pb = buf + P;
@@ -1366,7 +1368,8 @@ __global__ __launch_bounds__(256) void k_rate_grad(Dev d, float *g)
 
 // Derived per-(scenario, link) constants.
 __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, const float *beta,
-                         const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd)
+                         const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
+                         LinkCf *lcf)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)d.S * d.L) return;
@@ -1384,6 +1387,16 @@ __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, co
     c.cap = d.cap[j];
     c.lanes = d.lanes[j];
     lnd[i] = c;
+    LinkCf f;
+    f.vf = vfree[i];
+    f.sp = spacing[i];
+    f.L = d.length[j];
+    f.thr = d.thr[j];
+    f.cap = d.cap[j];
+    f.lanes = d.lanes[j];
+    f.ring_base = d.ring_base[j];
+    f.det = d.det_off[j] | ((d.det_off[j + 1] - d.det_off[j]) << 24);
+    lcf[i] = f;
 }
 
 // Total travel time and vehicle-steps per scenario: dt * sum over released
@@ -1831,11 +1844,11 @@ void launch_rate_grad(const Dev &d, float *g, hipStream_t st)
 }
 void launch_derive(const Dev &d, const float *cap_mult, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
-                   hipStream_t st)
+                   LinkCf *lcf, hipStream_t st)
 {
     const int64_t n = (int64_t)d.S * d.L;
     hipLaunchKernelGGL(k_derive, dim3((int)((n + 255) / 256)), dim3(256), 0, st, d, cap_mult, capacity, beta, cost,
-                       util, acc, vfree, spacing, lnd);
+                       util, acc, vfree, spacing, lnd, lcf);
 }
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st)
 {

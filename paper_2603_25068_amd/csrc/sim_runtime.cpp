@@ -135,6 +135,7 @@ struct sim_t {
     float *vfree = nullptr, *spacing = nullptr;
     double *util = nullptr, *acc = nullptr;
     sim::LinkNd *lnd_dev = nullptr;
+    sim::LinkCf *lcf_dev = nullptr;
     // mutable queue buffers
     int32_t *q_off_dev = nullptr, *q_list_dev = nullptr, *q_dest_dev = nullptr, *q_didx_dev = nullptr;
     int64_t *q_rstep_dev = nullptr;
@@ -564,7 +565,7 @@ void build_classes(sim_t *h)
 void derive(sim_t *h)
 {
     sim::launch_derive(h->d, h->p_capm, h->capacity_dev, h->p_beta, h->p_cost, h->util, h->acc, h->vfree, h->spacing,
-                       h->lnd_dev, h->stream);
+                       h->lnd_dev, h->lcf_dev, h->stream);
     HIPCHK(hipGetLastError());
 }
 
@@ -720,6 +721,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
         if (h->origin_node[k] < 0 || h->origin_node[k] >= Nn) fail(SIM_EINVAL, "origin node out of range");
     h->D = net->n_detectors;
     if (h->D < 0 || (h->D > 0 && (!net->detector_link || !net->detector_pos))) fail(SIM_EINVAL, "bad detectors");
+    if (h->D >= (1 << 24)) fail(SIM_EUNSUPPORTED, "at most 2^24 - 1 detectors");
     h->det_link.assign(net->detector_link, net->detector_link + h->D);
     h->det_pos.assign(net->detector_pos, net->detector_pos + h->D);
     for (int k = 0; k < h->D; ++k) {
@@ -887,7 +889,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     // (the serving pool carves a request's state with that alignment)
     const size_t nQ = (size_t)h->S * h->D * std::max(h->nb, 1);
     size_t bytes = SR * 16                                   // ring positions, agents, (destination, row)
-                   + SL * (24 + 8 + 16 + 32 + 32 + maxl * 16)   // parameters, derived, state, node constants, heads
+                   + SL * (24 + 8 + 16 + 32 + 64 + maxl * 16)   // parameters, derived, state, link records, heads
                    + SN * (1 + 8 + 12) + SO * 16             // per agent and per origin state
                    + (size_t)h->S * h->O * std::max(h->B, 1) * 4
                    + (size_t)L * 56 + (size_t)Nn * 32        // link constants, node offsets and words
@@ -987,6 +989,8 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.ls = h->dalloc<sim::LinkSt>(SL);
     h->lnd_dev = h->dalloc<sim::LinkNd>(SL);
     d.lnd = h->lnd_dev;
+    h->lcf_dev = h->dalloc<sim::LinkCf>(SL);
+    d.lcf = h->lcf_dev;
     d.head_rec = h->dalloc<int4>(SL * maxl);
     d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
     d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
