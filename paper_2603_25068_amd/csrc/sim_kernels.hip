@@ -102,31 +102,36 @@ __device__ __forceinline__ double gumbel_of(uint32_t w)
 }
 
 
-// The same draw in single precision.  With k = w >> 8, U = (k + 1/2) 2^-24.
-// For U < 1/2 the inner value y = -ln U is at least ln 2, so the rounding of
-// U to float (2^-24 relative) and a few-ulp log keep y within ~1e-6 relative.
-// For U >= 1/2, 1 - U = (2^25 - 2k - 1) 2^-25 is an odd integer below 2^24
-// times a power of two, exact in float, and y = -log1p(-(1 - U)) keeps full
-// relative accuracy however close U is to 1.  The outer log then adds a few
-// ulp of |g| <= 18, so |g - g_double| < 1e-5 (checked exhaustively over all
-// 2^24 values of k).  A decision compares two scores, each within that bound
-// of its double value, and is taken on them only when it wins by kFastMargin
+// The same draw in single precision, without branches.  With k = w >> 8,
+// U = (k + 1/2) 2^-24.  For U < 1/2 the inner value y = -ln U is at least
+// ln 2, and U is exact in float, so the hardware log2 (a few ulp) keeps y
+// within ~3e-7 relative.  For U >= 1/2, e = 1 - U = (2^25 - 2k - 1) 2^-25 is
+// an odd integer below 2^24 times a power of two, exact in float, and
+// y = -ln(1 - e) takes Kahan's log1p correction (Goldberg, "What every
+// computer scientist should know about floating-point arithmetic", 1991,
+// Theorem 4): with u = fl(1 - e), whose distance 1 - u to one is exact,
+// -ln(1 - e) = -ln(u) e / (1 - u) to a few ulp, and y = e when u rounds to
+// one.  Both halves share one log of u.  The outer log then adds a few ulp of
+// |g| <= 18, so |g - g_double| < 1e-5 (checked exhaustively over all 2^24
+// values of k).  A decision compares two scores, each within that bound of
+// its double value, and is taken on them only when it wins by kFastMargin
 // (five times the largest possible error of the difference); otherwise it is
 // recomputed with gumbel_of, so every decision equals the double-precision one.
 __device__ __forceinline__ float gumbel_fast(uint32_t w)
 {
+    constexpr float kLn2 = 0.693147180559945f;
     const uint32_t k = w >> 8;
-    float y;
-    if (k < (1u << 23)) {
-        y = -__logf(((float)k + 0.5f) * (1.0f / 16777216.0f));
-    } else {
-        const float e = (float)((1u << 25) - 2u * k - 1u) * (1.0f / 33554432.0f);
-        y = -log1pf(-e);
-    }
-    return -__logf(y);
+    const bool lower = k < (1u << 23);
+    const float U = ((float)k + 0.5f) * (1.0f / 16777216.0f);
+    const float e = (float)((1u << 25) - 2u * k - 1u) * (1.0f / 33554432.0f);   // 1 - U on the upper half
+    const float u = lower ? U : 1.0f - e;
+    const float lnu = __builtin_amdgcn_logf(u) * kLn2;
+    const float r = lower ? 1.0f : e * __builtin_amdgcn_rcpf(1.0f - u);
+    const float y = (!lower && u == 1.0f) ? e : -lnu * r;
+    return -__builtin_amdgcn_logf(y) * kLn2;
 }
 constexpr double kFastMargin = 1e-4;
-constexpr int kChoiceChunk = 16;   // out-links whose route entries and noise are requested together
+constexpr int kChoiceChunk = 8;    // out-links whose route entries, noise and records are requested together
 
 // ---------------------------------------------------------------------------
 // Lane groups: a work item (segment or node) is served by G consecutive
@@ -461,7 +466,7 @@ struct CandRec { double key; int ch, ag; };                               // can
 
 template <int G>
 __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k,
-                                          OutRec *orc, CandRec *crc, int *ent)
+                                          OutRec *orc, CandRec *crc)
 {
     const int gl = g.gl;
     const int maxl = d.maxl;
@@ -601,13 +606,14 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
         second = -INFINITY;
         arg = CH_STUCK;
         argk = 0;
-        for (int c0 = 0; c0 < dego; c0 += kChoiceChunk) {
-            double rt[kChoiceChunk];
-            uint32_t w[kChoiceChunk];
+        constexpr int CC = G < kChoiceChunk ? G : kChoiceChunk;
+        for (int c0 = 0; c0 < dego; c0 += CC) {
+            double rt[CC];
+            uint32_t w[CC];
 #pragma unroll
-            for (int q = 0; q < kChoiceChunk; ++q) rt[q] = (chooser && c0 + q < dego) ? route[c0 + q] : INFINITY;
+            for (int q = 0; q < CC; ++q) rt[q] = (chooser && c0 + q < dego) ? route[c0 + q] : INFINITY;
 #pragma unroll
-            for (int b = 0; b < kChoiceChunk / 4; ++b) {
+            for (int b = 0; b < CC / 4; ++b) {
                 if (chooser && c0 + 4 * b < dego) {
                     draw4(seed, ag, t, 0, (c0 >> 2) + b, w + 4 * b);
                 } else {
@@ -616,15 +622,23 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
                 }
             }
             if (!chooser) continue;
+            // the chunk's out-link records, all LDS reads issued before the first score
+            double ou[CC];
+            int oh[CC], oo[CC];
 #pragma unroll
-            for (int q = 0; q < kChoiceChunk; ++q) {
+            for (int q = 0; q < CC; ++q) {
+                const OutRec &o = orc[min(c0 + q, G - 1)];
+                ou[q] = o.util;
+                oh[q] = o.head;
+                oo[q] = o.om;
+            }
+#pragma unroll
+            for (int q = 0; q < CC; ++q) {
                 if (c0 + q >= dego) break;
-                const OutRec o = orc[c0 + q];
-                if (!d.allow_uturn && from >= 0 && o.head == ftail) continue;
-                if (!(rt[q] < INFINITY)) continue;
-                const double sc = o.util - d.theta * rt[q] + (double)gumbel_fast(w[q]);
-                if (sc > best) { second = best; best = sc; arg = o.om; argk = c0 + q; }
-                else if (sc > second) second = sc;
+                const bool ok = !(!d.allow_uturn && from >= 0 && oh[q] == ftail) && rt[q] < INFINITY;
+                const double sc = ou[q] - d.theta * rt[q] + (double)gumbel_fast(w[q]);
+                if (ok && sc > best) { second = best; best = sc; arg = oo[q]; argk = c0 + q; }
+                else if (ok && sc > second) second = sc;
             }
         }
     };
@@ -695,17 +709,26 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     bool knear = false;
     crc[gl] = CandRec{key, ag >= 0 ? ch : CH_NONE, ag};
     wave_lds_sync();
+    // fixed trip count over the group's lanes (a lane that holds no candidate published CH_NONE),
+    // branch-free, so that the broadcast LDS reads of several lanes are in flight together
+    constexpr int kUnrollG = G <= 16 ? G : 8;
     auto rank_pass = [&]() {
-        rank = 0;
-        close = 0;
-        if (ag < 0 || ch < 0) return;
-        for (int e = 0; e < nc; ++e) {
+        const bool act = ag >= 0 && ch >= 0;
+        const double tol = 1e-12 * (1.0 + fabs(key));
+        int rk = 0, cl = 0, kn = 0;
+#pragma unroll kUnrollG
+        for (int e = 0; e < G; ++e) {
             const CandRec o = crc[e];
-            if (e == gl || o.ch != ch) continue;
-            if (o.key > key || (o.key == key && o.ag < ag)) ++rank;
-            else if (key - o.key < 1e-12 * (1.0 + fabs(key))) close = 1;
-            knear |= fabs(o.key - key) < kFastMargin;
+            const bool rival = act && e != gl && o.ch == ch;
+            const double diff = o.key - key;   // exact in sign: o.key > key iff diff > 0
+            const bool ahead = diff > 0.0 || (diff == 0.0 && o.ag < ag);
+            rk += rival && ahead;
+            cl |= rival && !ahead && -diff < tol;
+            kn |= rival && fabs(diff) < kFastMargin;
         }
+        rank = rk;
+        close = cl;
+        knear |= kn != 0;
     };
     rank_pass();
     if (g.count(knear)) {   // keys of competing candidates too close for the fast noise: all exact
@@ -725,10 +748,11 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     // ---- resolve: lane q < deg walks in-link q's heads in rank order ----
     int np = 0;
     bool stop = false, consumed = false;
-    for (int r = 0; r < maxl; ++r) {
-        const int src = min(off_res + r, G - 1);
-        const int c2 = __shfl(ch, src, G);
-        const int w2 = __shfl(won, src, G);
+    const int cw = ch * 2 + won;   // choice and merge outcome in one word (one shuffle per head)
+#pragma unroll
+    for (int r = 0; r < kMaxLanes; ++r) {   // nhq <= maxl <= kMaxLanes
+        const int x = __shfl(cw, min(off_res + r, G - 1), G);
+        const int c2 = x >> 1, w2 = x & 1;
         if (gl < deg && !stop && r < nhq) {
             if (c2 == CH_EXIT) ++np;
             else if (c2 >= 0 && w2 && Bj >= 1.0) { Bj -= 1.0; ++np; consumed = true; }
@@ -749,17 +773,19 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
     else passed = (origin >= 0 && ag >= 0 && won);
 
     // ---- entrants per out-link (lane k < dego counts link k's) and each entrant's place in key order ----
-    ent[gl] = (passed && ch >= 0) ? ch : CH_NONE;
+    // each lane republishes its choice as an entrant's (CH_NONE if it does not enter); om is -1 on
+    // lanes without an out-link, which no entry matches
+    const bool entering = passed && ch >= 0;
+    wave_lds_sync();
+    crc[gl].ch = entering ? ch : CH_NONE;
     wave_lds_sync();
     int nent = 0, erank = 0;
-    if (gl < dego)
-        for (int e = 0; e < nc; ++e) nent += ent[e] == om;
-    if (passed && ch >= 0) {
-        for (int e = 0; e < nc; ++e) {
-            if (e == gl || ent[e] != ch) continue;
-            const CandRec o = crc[e];
-            if (o.key > key || (o.key == key && o.ag < ag)) ++erank;
-        }
+#pragma unroll kUnrollG
+    for (int e = 0; e < G; ++e) {
+        const CandRec o = crc[e];
+        nent += o.ch == om;
+        const double diff = o.key - key;
+        erank += entering && e != gl && o.ch == ch && (diff > 0.0 || (diff == 0.0 && o.ag < ag));
     }
     if (gl < dego && nent) d.ls[sL + om].rtail = otail + nent;
     int tbase = 0, rbase = 0, rcap = 1;
@@ -839,7 +865,7 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
 // neighbouring nodes share an XCD.
 template <int G>
 __device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t, int tape_k, OutRec *orc,
-                                          CandRec *crc, int *ent)
+                                          CandRec *crc)
 {
     const Group<G> g;
     const int per = 256 / G;
@@ -848,7 +874,7 @@ __device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t,
     if (item >= n) return true;
     const int s = item / d.nd_n[c];
     const int o = (int)threadIdx.x & ~(G - 1);
-    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k, orc + o, crc + o, ent + o);
+    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k, orc + o, crc + o);
     return true;
 }
 
@@ -863,18 +889,17 @@ __device__ __forceinline__ void node_launch(Dev &d, int t, int tape_k)
 {
     __shared__ OutRec orc[256];
     __shared__ CandRec crc[256];
-    __shared__ int ent[256];
     int b = (int)blockIdx.x;
     const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
-    if (b < b8) { node_role<8>(d, 0, b, b8, t, tape_k, orc, crc, ent); return; }
+    if (b < b8) { node_role<8>(d, 0, b, b8, t, tape_k, orc, crc); return; }
     b -= b8;
     const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
-    if (b < b16) { node_role<16>(d, 1, b, b16, t, tape_k, orc, crc, ent); return; }
+    if (b < b16) { node_role<16>(d, 1, b, b16, t, tape_k, orc, crc); return; }
     b -= b16;
     const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
-    if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k, orc, crc, ent); return; }
+    if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k, orc, crc); return; }
     b -= b32;
-    node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc, ent);
+    node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc);
 }
 
 __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
