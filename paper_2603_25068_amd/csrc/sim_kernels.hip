@@ -166,6 +166,26 @@ struct Group {
 };
 
 
+// The kernels take the state descriptor by value as their first argument, so
+// it sits at offset 0 of the kernel argument segment, and split their blocks
+// into roles, one per lane-group size, each an inlined copy of the same code.
+// Loads of one field in several roles would be merged into one load at the
+// kernel's entry and kept live, in spilled scalar registers, through every
+// role.  Each role therefore reads the descriptor through its own copy of the
+// argument segment pointer, passed through an empty asm statement the
+// optimiser cannot see through, so that a role's loads stay inside the role.
+// The pointer comes from the segment itself, never from the address of the
+// by-value parameter: that address would escape into the asm and force a
+// private copy of the descriptor.  Only for kernels whose first argument is
+// the descriptor, unmodified.
+__device__ __forceinline__ const Dev &role_args()
+{
+    using ArgDev = const __attribute__((address_space(4))) Dev;
+    ArgDev *p = (ArgDev *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const Dev *)p;
+}
+
 // Counter increments of one node: releases, and five small counts packed as
 // 8-bit fields of one word (each at most 2 per lane, so at most 128 per
 // group), summed over the lane group, then one atomic per non-zero counter
@@ -175,7 +195,7 @@ enum { NF_DEPARTED = 0, NF_EXITED, NF_TRANSFERS, NF_TIES, NF_STUCK, NF_N };
 __device__ __forceinline__ uint64_t nf_one(int f) { return 1ull << (8 * f); }
 
 template <int G>
-__device__ __forceinline__ void add_node_counters(Dev &d, const Group<G> &g, int s, int item, int released,
+__device__ __forceinline__ void add_node_counters(const Dev &d, const Group<G> &g, int s, int item, int released,
                                                   uint64_t small)
 {
     released = g.sum(released);
@@ -235,7 +255,7 @@ __device__ __forceinline__ float cf_update(float x, float xl, bool has_leader, f
 }
 
 template <int G, bool TAPE>
-__device__ __forceinline__ void link_segment(Dev &d, const Group<G> &g, int seg, int t, int sample_b, int tape_k,
+__device__ __forceinline__ void link_segment(const Dev &d, const Group<G> &g, int seg, int t, int sample_b, int tape_k,
                                              float *buf, int bufcap)
 {
     const int gl = g.gl;
@@ -404,8 +424,10 @@ __device__ __forceinline__ int ring_role(const Dev &d, int G, int &b, int &nblk)
 }
 
 template <int GC, bool TAPE>
-__device__ __forceinline__ void link_role(Dev &d, int c, int b, int nblk, int t, int sample_b, int tape_k, float *lds)
+__device__ __forceinline__ void link_role(int c, int b, int nblk, int t, int sample_b, int tape_k,
+                                          float *lds)
 {
+    const Dev &d = role_args();
     const Group<GC> g;
     constexpr int per = 256 / GC;
     constexpr int sbuf = 4 * kBigLds / per;
@@ -420,15 +442,15 @@ __device__ __forceinline__ void link_role(Dev &d, int c, int b, int nblk, int t,
 }
 
 template <int G, bool TAPE>
-__device__ __forceinline__ void link_launch(Dev &d, int t, int sample_b, int tape_k)
+__device__ __forceinline__ void link_launch(const Dev &d, int t, int sample_b, int tape_k)
 {
     __shared__ float lds[4 * kBigLds];
     int b, nblk;
     const int c = ring_role(d, G, b, nblk);
-    if (c == 0) link_role<ring_lanes(0, G), TAPE>(d, 0, b, nblk, t, sample_b, tape_k, lds);
-    else if (c == 1) link_role<ring_lanes(1, G), TAPE>(d, 1, b, nblk, t, sample_b, tape_k, lds);
-    else if (c == 2) link_role<ring_lanes(2, G), TAPE>(d, 2, b, nblk, t, sample_b, tape_k, lds);
-    else link_role<ring_lanes(3, G), TAPE>(d, 3, b, nblk, t, sample_b, tape_k, lds);
+    if (c == 0) link_role<ring_lanes(0, G), TAPE>(0, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 1) link_role<ring_lanes(1, G), TAPE>(1, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 2) link_role<ring_lanes(2, G), TAPE>(2, b, nblk, t, sample_b, tape_k, lds);
+    else link_role<ring_lanes(3, G), TAPE>(3, b, nblk, t, sample_b, tape_k, lds);
 }
 
 template <int G, bool TAPE>
@@ -465,7 +487,7 @@ struct OutRec { double util; int om, head, slots, tail, base, cap; };   // out-l
 struct CandRec { double key; int ch, ag; };                               // candidate lane e
 
 template <int G>
-__device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k,
+__device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k,
                                           OutRec *orc, CandRec *crc)
 {
     const int gl = g.gl;
@@ -864,9 +886,10 @@ __device__ __forceinline__ void node_work(Dev &d, const Group<G> &g, int s, int 
 // four classes as block roles, each role's block range remapped so that
 // neighbouring nodes share an XCD.
 template <int G>
-__device__ __forceinline__ bool node_role(Dev &d, int c, int b, int nblk, int t, int tape_k, OutRec *orc,
+__device__ __forceinline__ bool node_role(int c, int b, int nblk, int t, int tape_k, OutRec *orc,
                                           CandRec *crc)
 {
+    const Dev &d = role_args();
     const Group<G> g;
     const int per = 256 / G;
     const int n = d.S * d.nd_n[c];
@@ -885,21 +908,21 @@ __host__ __device__ __forceinline__ int node_role_blocks(int n, int G, bool last
     return last ? b : ((b + 7) & ~7);   // inner roles in multiples of 8 keep the XCD pattern
 }
 
-__device__ __forceinline__ void node_launch(Dev &d, int t, int tape_k)
+__device__ __forceinline__ void node_launch(const Dev &d, int t, int tape_k)
 {
     __shared__ OutRec orc[256];
     __shared__ CandRec crc[256];
     int b = (int)blockIdx.x;
     const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
-    if (b < b8) { node_role<8>(d, 0, b, b8, t, tape_k, orc, crc); return; }
+    if (b < b8) { node_role<8>(0, b, b8, t, tape_k, orc, crc); return; }
     b -= b8;
     const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
-    if (b < b16) { node_role<16>(d, 1, b, b16, t, tape_k, orc, crc); return; }
+    if (b < b16) { node_role<16>(1, b, b16, t, tape_k, orc, crc); return; }
     b -= b16;
     const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
-    if (b < b32) { node_role<32>(d, 2, b, b32, t, tape_k, orc, crc); return; }
+    if (b < b32) { node_role<32>(2, b, b32, t, tape_k, orc, crc); return; }
     b -= b32;
-    node_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc);
+    node_role<64>(3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc);
 }
 
 __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
@@ -955,7 +978,7 @@ constexpr int kRevBigLds = 1280;    // LDS words per wavefront (two arrays), spl
 constexpr int kRevUnroll = 4;       // staged ranks per lane and round of the reverse
 
 template <int G>
-__device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
+__device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
                                                 float *buf, int bufcap)
 {
     const int gl = g.gl;
@@ -1098,8 +1121,10 @@ __device__ __forceinline__ void reverse_segment(Dev &d, const Group<G> &g, int s
 }
 
 template <int GC>
-__device__ __forceinline__ void reverse_role(Dev &d, int c, int b, int nblk, int t, int tape_k, int init, float *lds)
+__device__ __forceinline__ void reverse_role(int c, int b, int nblk, int t, int tape_k, int init,
+                                             float *lds)
 {
+    const Dev &d = role_args();
     const Group<GC> g;
     constexpr int per = 256 / GC;
     constexpr int sbuf = 4 * kRevBigLds / per;
@@ -1115,15 +1140,15 @@ __device__ __forceinline__ void reverse_role(Dev &d, int c, int b, int nblk, int
 }
 
 template <int G>
-__device__ __forceinline__ void reverse_launch(Dev &d, int t, int tape_k, int init)
+__device__ __forceinline__ void reverse_launch(const Dev &d, int t, int tape_k, int init)
 {
     __shared__ float lds[4 * kRevBigLds];
     int b, nblk;
     const int c = ring_role(d, G, b, nblk);
-    if (c == 0) reverse_role<ring_lanes(0, G)>(d, 0, b, nblk, t, tape_k, init, lds);
-    else if (c == 1) reverse_role<ring_lanes(1, G)>(d, 1, b, nblk, t, tape_k, init, lds);
-    else if (c == 2) reverse_role<ring_lanes(2, G)>(d, 2, b, nblk, t, tape_k, init, lds);
-    else reverse_role<ring_lanes(3, G)>(d, 3, b, nblk, t, tape_k, init, lds);
+    if (c == 0) reverse_role<ring_lanes(0, G)>(0, b, nblk, t, tape_k, init, lds);
+    else if (c == 1) reverse_role<ring_lanes(1, G)>(1, b, nblk, t, tape_k, init, lds);
+    else if (c == 2) reverse_role<ring_lanes(2, G)>(2, b, nblk, t, tape_k, init, lds);
+    else reverse_role<ring_lanes(3, G)>(3, b, nblk, t, tape_k, init, lds);
 }
 
 template <int G>
@@ -1158,7 +1183,7 @@ __global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int i
 // deterministic.
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ __forceinline__ void ste_work(Dev &d, const Group<G> &g, int s, int v, int t, int tape_k,
+__device__ __forceinline__ void ste_work(const Dev &d, const Group<G> &g, int s, int v, int t, int tape_k,
                                          double *sy, double *sg, double *sd, int *sk, int *sr, int *sa)
 {
     const int gl = g.gl;
@@ -1308,9 +1333,10 @@ __device__ __forceinline__ void ste_work(Dev &d, const Group<G> &g, int s, int v
 }
 
 template <int G>
-__device__ __forceinline__ void ste_role(Dev &d, int c, int b, int nblk, int t, int tape_k, double *sy, double *sg,
-                                         double *sd, int *sk, int *sr, int *sa)
+__device__ __forceinline__ void ste_role(int c, int b, int nblk, int t, int tape_k, double *sy,
+                                         double *sg, double *sd, int *sk, int *sr, int *sa)
 {
+    const Dev &d = role_args();
     const Group<G> g;
     const int per = 256 / G;
     const int n = d.S * d.nd_n[c];
@@ -1328,15 +1354,15 @@ __global__ __launch_bounds__(256) void k_ste(Dev d, int t, int tape_k)
     __shared__ int sk[256], sr[256], sa[256];
     int b = (int)blockIdx.x;
     const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
-    if (b < b8) { ste_role<8>(d, 0, b, b8, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
+    if (b < b8) { ste_role<8>(0, b, b8, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
     b -= b8;
     const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
-    if (b < b16) { ste_role<16>(d, 1, b, b16, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
+    if (b < b16) { ste_role<16>(1, b, b16, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
     b -= b16;
     const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
-    if (b < b32) { ste_role<32>(d, 2, b, b32, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
+    if (b < b32) { ste_role<32>(2, b, b32, t, tape_k, sy, sg, sd, sk, sr, sa); return; }
     b -= b32;
-    ste_role<64>(d, 3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, sy, sg, sd, sk, sr, sa);
+    ste_role<64>(3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, sy, sg, sd, sk, sr, sa);
 }
 
 // theta gradient of each scenario: the per-node parts summed in node order by one wavefront
