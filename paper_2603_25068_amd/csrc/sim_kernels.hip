@@ -41,6 +41,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Scenario of work item `item` when items are numbered scenario-major, n per
+// scenario: a scalar branch skips the integer division (tens of instructions
+// per lane) in the common single-scenario case.
+__device__ __forceinline__ int scenario_of(int item, int n, int S)
+{
+    if (S == 1) return 0;
+    return item / n;
+}
+
 __device__ __forceinline__ int readlane_i(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
 
 __device__ __forceinline__ double readlane_d(double v, int src)
@@ -177,7 +186,8 @@ struct Group {
 // The pointer comes from the segment itself, never from the address of the
 // by-value parameter: that address would escape into the asm and force a
 // private copy of the descriptor.  Only for kernels whose first argument is
-// the descriptor, unmodified.
+// the descriptor, unmodified (the node, reverse and straight-through kernels;
+// the link kernel's roles need few fields and read the argument directly).
 __device__ __forceinline__ const Dev &role_args()
 {
     using ArgDev = const __attribute__((address_space(4))) Dev;
@@ -255,11 +265,11 @@ __device__ __forceinline__ float cf_update(float x, float xl, bool has_leader, f
 }
 
 template <int G, bool TAPE>
-__device__ __forceinline__ void link_segment(const Dev &d, const Group<G> &g, int seg, int t, int sample_b, int tape_k,
-                                             float *buf, int bufcap)
+__device__ __forceinline__ void link_segment(const Dev &d, const Group<G> &g, int s, int j, int t, int sample_b,
+                                             int tape_k, float *buf, int bufcap)
 {
     const int gl = g.gl;
-    const int s = seg / d.L, j = seg - s * d.L;
+    const int seg = s * d.L + j;
     const LinkCf lc = d.lcf[seg];
     const int cap = lc.cap, ln = lc.lanes;
     // ring counters, this link's entry slots and heads: one record (rhead, rtail, slots, nheads)
@@ -424,21 +434,20 @@ __device__ __forceinline__ int ring_role(const Dev &d, int G, int &b, int &nblk)
 }
 
 template <int GC, bool TAPE>
-__device__ __forceinline__ void link_role(int c, int b, int nblk, int t, int sample_b, int tape_k,
+__device__ __forceinline__ void link_role(const Dev &d, int c, int b, int nblk, int t, int sample_b, int tape_k,
                                           float *lds)
 {
-    const Dev &d = role_args();
     const Group<GC> g;
     constexpr int per = 256 / GC;
     constexpr int sbuf = 4 * kBigLds / per;
     const int n = d.S * d.lc_n[c];
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / GC;
     if (item >= n) return;
-    const int s = item / d.lc_n[c];
+    const int s = scenario_of(item, d.lc_n[c], d.S);
     int first = 0;
     for (int k = 0; k < c; ++k) first += d.lc_n[k];
-    const int seg = s * d.L + first + (item - s * d.lc_n[c]);
-    link_segment<GC, TAPE>(d, g, seg, t, sample_b, tape_k, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
+    link_segment<GC, TAPE>(d, g, s, first + (item - s * d.lc_n[c]), t, sample_b, tape_k,
+                           lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
 }
 
 template <int G, bool TAPE>
@@ -447,10 +456,10 @@ __device__ __forceinline__ void link_launch(const Dev &d, int t, int sample_b, i
     __shared__ float lds[4 * kBigLds];
     int b, nblk;
     const int c = ring_role(d, G, b, nblk);
-    if (c == 0) link_role<ring_lanes(0, G), TAPE>(0, b, nblk, t, sample_b, tape_k, lds);
-    else if (c == 1) link_role<ring_lanes(1, G), TAPE>(1, b, nblk, t, sample_b, tape_k, lds);
-    else if (c == 2) link_role<ring_lanes(2, G), TAPE>(2, b, nblk, t, sample_b, tape_k, lds);
-    else link_role<ring_lanes(3, G), TAPE>(3, b, nblk, t, sample_b, tape_k, lds);
+    if (c == 0) link_role<ring_lanes(0, G), TAPE>(d, 0, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 1) link_role<ring_lanes(1, G), TAPE>(d, 1, b, nblk, t, sample_b, tape_k, lds);
+    else if (c == 2) link_role<ring_lanes(2, G), TAPE>(d, 2, b, nblk, t, sample_b, tape_k, lds);
+    else link_role<ring_lanes(3, G), TAPE>(d, 3, b, nblk, t, sample_b, tape_k, lds);
 }
 
 template <int G, bool TAPE>
@@ -731,17 +740,19 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
     bool knear = false;
     crc[gl] = CandRec{key, ag >= 0 ? ch : CH_NONE, ag};
     wave_lds_sync();
-    // fixed trip count over the group's lanes (a lane that holds no candidate published CH_NONE),
-    // branch-free, so that the broadcast LDS reads of several lanes are in flight together
-    constexpr int kUnrollG = G <= 16 ? G : 8;
+    // the candidate lanes 0..nc-1 in chunks of up to sixteen, each chunk unrolled and branch-free so
+    // that its broadcast LDS reads are in flight together (lanes past nc are masked out of the sums)
+    constexpr int kCk = G <= 16 ? G : 8;
     auto rank_pass = [&]() {
         const bool act = ag >= 0 && ch >= 0;
         const double tol = 1e-12 * (1.0 + fabs(key));
         int rk = 0, cl = 0, kn = 0;
-#pragma unroll kUnrollG
-        for (int e = 0; e < G; ++e) {
-            const CandRec o = crc[e];
-            const bool rival = act && e != gl && o.ch == ch;
+        for (int e0 = 0; e0 < nc; e0 += kCk)
+#pragma unroll
+        for (int k = 0; k < kCk; ++k) {
+            const int e = e0 + k;
+            const CandRec o = crc[e & (G - 1)];
+            const bool rival = act && e < nc && e != gl && o.ch == ch;
             const double diff = o.key - key;   // exact in sign: o.key > key iff diff > 0
             const bool ahead = diff > 0.0 || (diff == 0.0 && o.ag < ag);
             rk += rival && ahead;
@@ -802,12 +813,15 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
     crc[gl].ch = entering ? ch : CH_NONE;
     wave_lds_sync();
     int nent = 0, erank = 0;
-#pragma unroll kUnrollG
-    for (int e = 0; e < G; ++e) {
-        const CandRec o = crc[e];
-        nent += o.ch == om;
+    for (int e0 = 0; e0 < nc; e0 += kCk)
+#pragma unroll
+    for (int k = 0; k < kCk; ++k) {
+        const int e = e0 + k;
+        const CandRec o = crc[e & (G - 1)];
+        const bool in = e < nc;
+        nent += in && o.ch == om;
         const double diff = o.key - key;
-        erank += entering && e != gl && o.ch == ch && (diff > 0.0 || (diff == 0.0 && o.ag < ag));
+        erank += in && entering && e != gl && o.ch == ch && (diff > 0.0 || (diff == 0.0 && o.ag < ag));
     }
     if (gl < dego && nent) d.ls[sL + om].rtail = otail + nent;
     int tbase = 0, rbase = 0, rcap = 1;
@@ -895,7 +909,7 @@ __device__ __forceinline__ bool node_role(int c, int b, int nblk, int t, int tap
     const int n = d.S * d.nd_n[c];
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / G;
     if (item >= n) return true;
-    const int s = item / d.nd_n[c];
+    const int s = scenario_of(item, d.nd_n[c], d.S);
     const int o = (int)threadIdx.x & ~(G - 1);
     node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k, orc + o, crc + o);
     return true;
@@ -978,11 +992,11 @@ constexpr int kRevBigLds = 1280;    // LDS words per wavefront (two arrays), spl
 constexpr int kRevUnroll = 4;       // staged ranks per lane and round of the reverse
 
 template <int G>
-__device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g, int seg, int t, int tape_k, int init,
-                                                float *buf, int bufcap)
+__device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g, int s, int j, int t, int tape_k,
+                                                int init, float *buf, int bufcap)
 {
     const int gl = g.gl;
-    const int s = seg / d.L;
+    const int seg = s * d.L + j;
     const int64_t SL = (int64_t)d.S * d.L;
     const LinkCf lc = d.lcf[seg];
     const int cap = lc.cap, ln = lc.lanes;
@@ -1132,11 +1146,11 @@ __device__ __forceinline__ void reverse_role(int c, int b, int nblk, int t, int 
     const int n = d.S * d.lc_n[c];
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / GC;
     if (item >= n) return;
-    const int s = item / d.lc_n[c];
+    const int s = scenario_of(item, d.lc_n[c], d.S);
     int first = 0;
     for (int k = 0; k < c; ++k) first += d.lc_n[k];
-    const int seg = s * d.L + first + (item - s * d.lc_n[c]);
-    reverse_segment<GC>(d, g, seg, t, tape_k, init, lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
+    reverse_segment<GC>(d, g, s, first + (item - s * d.lc_n[c]), t, tape_k, init,
+                        lds + ((int)threadIdx.x / GC) * sbuf, sbuf);
 }
 
 template <int G>
@@ -1342,7 +1356,7 @@ __device__ __forceinline__ void ste_role(int c, int b, int nblk, int t, int tape
     const int n = d.S * d.nd_n[c];
     const int item = xcd_remap(b, nblk) * per + (int)threadIdx.x / G;
     if (item >= n) return;
-    const int s = item / d.nd_n[c];
+    const int s = scenario_of(item, d.nd_n[c], d.S);
     const int o = (int)threadIdx.x & ~(G - 1);
     ste_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), t, tape_k, sy + o, sg + o, sd + o, sk + o, sr + o,
                 sa + o);
