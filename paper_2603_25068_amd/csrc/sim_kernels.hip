@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 // Per-group LDS tables of the node phase: what a lane group's out-link lanes and candidate lanes
 // publish for the others, read with plain LDS loads (no cross-lane shuffles inside branchy loops).
 struct OutRec { double util; int om, head, slots, tail, base, cap; };   // out-link k of the node
-struct CandRec { double key; int ch, ag; };                               // candidate lane e
+struct alignas(16) CandRec { double key; int ch, ag; };                     // candidate lane e
 
 template <int G>
 __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k,
@@ -666,10 +666,13 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
 #pragma unroll
             for (int q = 0; q < CC; ++q) {
                 if (c0 + q >= dego) break;
-                const bool ok = !(!d.allow_uturn && from >= 0 && oh[q] == ftail) && rt[q] < INFINITY;
+                const bool ok = !((!d.allow_uturn) & (from >= 0) & (oh[q] == ftail)) & (rt[q] < INFINITY);
                 const double sc = ou[q] - d.theta * rt[q] + (double)gumbel_fast(w[q]);
-                if (ok && sc > best) { second = best; best = sc; arg = oo[q]; argk = c0 + q; }
-                else if (ok && sc > second) second = sc;
+                const bool top = ok & (sc > best), sec = ok & !top & (sc > second);
+                second = top ? best : (sec ? sc : second);
+                best = top ? sc : best;
+                arg = top ? oo[q] : arg;
+                argk = top ? c0 + q : argk;
             }
         }
     };
@@ -740,8 +743,9 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
     bool knear = false;
     crc[gl] = CandRec{key, ag >= 0 ? ch : CH_NONE, ag};
     wave_lds_sync();
-    // the candidate lanes 0..nc-1 in chunks of up to sixteen, each chunk unrolled and branch-free so
-    // that its broadcast LDS reads are in flight together (lanes past nc are masked out of the sums)
+    // the candidate lanes 0..nc-1 in chunks of up to sixteen, each chunk unrolled and branch-free (the
+    // predicates combine with non-short-circuit & and |, so no record read is placed under a branch)
+    // so that its broadcast LDS reads are in flight together; lanes past nc are masked out of the sums
     constexpr int kCk = G <= 16 ? G : 8;
     auto rank_pass = [&]() {
         const bool act = ag >= 0 && ch >= 0;
@@ -752,12 +756,12 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
         for (int k = 0; k < kCk; ++k) {
             const int e = e0 + k;
             const CandRec o = crc[e & (G - 1)];
-            const bool rival = act && e < nc && e != gl && o.ch == ch;
+            const bool rival = act & (e < nc) & (e != gl) & (o.ch == ch);
             const double diff = o.key - key;   // exact in sign: o.key > key iff diff > 0
-            const bool ahead = diff > 0.0 || (diff == 0.0 && o.ag < ag);
-            rk += rival && ahead;
-            cl |= rival && !ahead && -diff < tol;
-            kn |= rival && fabs(diff) < kFastMargin;
+            const bool ahead = (diff > 0.0) | ((diff == 0.0) & (o.ag < ag));
+            rk += rival & ahead;
+            cl |= rival & !ahead & (-diff < tol);
+            kn |= rival & (fabs(diff) < kFastMargin);
         }
         rank = rk;
         close = cl;
@@ -819,9 +823,9 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
         const int e = e0 + k;
         const CandRec o = crc[e & (G - 1)];
         const bool in = e < nc;
-        nent += in && o.ch == om;
+        nent += in & (o.ch == om);
         const double diff = o.key - key;
-        erank += in && entering && e != gl && o.ch == ch && (diff > 0.0 || (diff == 0.0 && o.ag < ag));
+        erank += in & entering & (e != gl) & (o.ch == ch) & ((diff > 0.0) | ((diff == 0.0) & (o.ag < ag)));
     }
     if (gl < dego && nent) d.ls[sL + om].rtail = otail + nent;
     int tbase = 0, rbase = 0, rcap = 1;
