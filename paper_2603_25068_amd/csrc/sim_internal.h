@@ -87,9 +87,9 @@ struct Dev {
     const int32_t *node_cnt;         // per node: in-degree | out-degree << 8 | origins << 16
     const int32_t *in_pad, *out_pad; // [Nn x max_in], [Nn x max_out] link ids in CSR order
     const int32_t *in_loff;          // [Nn x max_in] first head lane of each in-link (prefix sum of lanes)
-    const int2 *cand;                // [Nn x max_cand] head lane -> (in-link, in-link index | rank << 8)
+    const int2 *cand;                // [Nn x max_cand] candidate lane -> head lane: (in-link, in-link index |
+                                     // rank << 8); then origin lane: (origin, first queue entry)
     int32_t max_cand;
-    const int2 *org_pad;             // [Nn x max_org] (origin, first queue entry)
     const int32_t *cbase;            // [Nn] first candidate record of each node (candidate lanes in order)
     int32_t n_cand;                  // candidate records per scenario and step (sum over nodes)
     int32_t max_in, max_out, max_org;

@@ -512,7 +512,8 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
 
     // first-level loads issued together (padded tables need no offsets)
     const int om_raw = d.out_pad[(int64_t)v * d.max_out + min(gl, d.max_out - 1)];
-    const int2 cm = d.cand[(int64_t)v * d.max_cand + min(gl, d.max_cand - 1)];   // (in-link, q | rank << 8)
+    // (in-link, q | rank << 8) on head lanes, (origin, first queue entry) on origin lanes
+    const int2 cm = d.cand[(int64_t)v * d.max_cand + min(gl, d.max_cand - 1)];
     const bool head_lane = gl < ncin;
     const int qi = head_lane ? (cm.y & 0xff) : 0, hr_r = head_lane ? (cm.y >> 8) : 0;
     const int jin_cand = cm.x;
@@ -562,9 +563,8 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
         const int tl = c.tail;
         if (r < nh) { ag = hr.x; dst = hr.y; didx = hr.z; from = jj; alpha = (double)al; ftail = tl; }
     } else if (gl < nc) {
-        const int2 oq = d.org_pad[(int64_t)v * d.max_org + (gl - ncin)];
-        origin = oq.x;
-        const int qb = oq.y, qn = d.q_off[origin + 1] - qb;
+        origin = cm.x;
+        const int qb = cm.y, qn = d.q_off[origin + 1] - qb;
         const int so = s * d.O + origin;
         const int rel = d.rel_ptr[so];
         dp0 = d.dep_ptr[so];

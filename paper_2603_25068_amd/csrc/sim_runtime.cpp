@@ -139,7 +139,7 @@ struct sim_t {
     // mutable queue buffers
     int32_t *q_off_dev = nullptr, *q_list_dev = nullptr, *q_dest_dev = nullptr, *q_didx_dev = nullptr;
     int64_t *q_rstep_dev = nullptr;
-    int2 *org_pad_dev = nullptr;
+    int2 *cand_dev = nullptr;
     std::vector<int32_t> node_cnt, in_pad, out_pad;
     int32_t max_in = 1, max_out = 1, max_org = 1, max_cand = 1;
     std::vector<int32_t> in_loff;
@@ -429,14 +429,17 @@ void upload_queues(sim_t *h)
         HIPCHK(hipMemcpyAsync(h->q_didx_dev, h->q_didx.data(), h->q_didx.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->q_rstep_dev, h->q_rstep.data(), h->q_rstep.size() * 8, hipMemcpyHostToDevice, h->stream));
     }
-    // per-node origin table (origin, first queue entry) follows the queue offsets
-    std::vector<int2> op((size_t)h->Nn * h->max_org, make_int2(-1, 0));
-    for (int v = 0; v < h->Nn; ++v)
+    // candidate lanes past a node's head lanes hold its origins as (origin, first queue entry), which
+    // follow the queue offsets
+    for (int v = 0; v < h->Nn; ++v) {
+        const int nl = (h->node_cnt[v] >> 24) & 0xff;
         for (int k = h->org_off[v]; k < h->org_off[v + 1]; ++k) {
             const int o = h->org_list[k];
-            op[(size_t)v * h->max_org + (k - h->org_off[v])] = make_int2(o, h->q_off[o]);
+            h->cand[(size_t)v * h->max_cand + nl + (k - h->org_off[v])] = make_int2(o, h->q_off[o]);
         }
-    HIPCHK(hipMemcpyAsync(h->org_pad_dev, op.data(), op.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(hipMemcpyAsync(h->cand_dev, h->cand.data(), h->cand.size() * sizeof(int2), hipMemcpyHostToDevice,
+                          h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
 }
 
@@ -803,8 +806,8 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
         h->max_org = std::max(h->max_org, h->org_off[v + 1] - h->org_off[v]);
     }
     if (h->max_in > 255 || h->max_out > 255 || h->max_org > 255) fail(SIM_EUNSUPPORTED, "node degree above 255");
-    for (int v = 0; v < Nn; ++v) {
-        int nl = 0;
+    for (int v = 0; v < Nn; ++v) {   // candidate lanes: the in-links' head lanes, then the origins
+        int nl = h->org_off[v + 1] - h->org_off[v];
         for (int k = h->in_off[v]; k < h->in_off[v + 1]; ++k) nl += h->lanes[h->in_lnk[k]];
         h->max_cand = std::max(h->max_cand, nl);
     }
@@ -894,7 +897,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
                    + (size_t)h->S * h->O * std::max(h->B, 1) * 4
                    + (size_t)L * 56 + (size_t)Nn * 32        // link constants, node offsets and words
                    + (h->in_pad.size() + h->in_loff.size() + h->out_pad.size()) * 4 + h->cand.size() * 8 +
-                   (size_t)Nn * h->max_org * 8 + (size_t)h->N * 44 + h->route.size() * 8 +
+                   (size_t)h->N * 44 + h->route.size() * 8 +
                    (size_t)h->D * 12 + (size_t)h->S * 8 +
                    (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8 + nQ * 8 + (size_t)6 * sim::kTieLogMax * 4 +
                    (size_t)h->S * 24 + 128 * 256;
@@ -958,12 +961,12 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     h->q_dest_dev = h->dalloc<int32_t>(h->q_list.size());
     h->q_didx_dev = h->dalloc<int32_t>(h->q_list.size());
     h->q_rstep_dev = h->dalloc<int64_t>(h->q_rstep.size());
-    h->org_pad_dev = h->dalloc<int2>((size_t)Nn * h->max_org);
+    h->cand_dev = h->dalloc<int2>(h->cand.size());
     upload_queues(h);
     d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
-    d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev; d.org_pad = h->org_pad_dev;
+    d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev;
     d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
-    d.in_loff = h->upload(h->in_loff); d.cand = h->upload(h->cand); d.max_cand = h->max_cand;
+    d.in_loff = h->upload(h->in_loff); d.cand = h->cand_dev; d.max_cand = h->max_cand;
     d.cbase = h->upload(h->cbase); d.n_cand = h->n_cand;
     d.max_in = h->max_in; d.max_out = h->max_out; d.max_org = h->max_org;
     d.seed = h->upload(h->seeds);
