@@ -514,60 +514,58 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
     const int om_raw = d.out_pad[(int64_t)v * d.max_out + min(gl, d.max_out - 1)];
     // (in-link, q | rank << 8) on head lanes, (origin, first queue entry) on origin lanes
     const int2 cm = d.cand[(int64_t)v * d.max_cand + min(gl, d.max_cand - 1)];
-    const bool head_lane = gl < ncin;
-    const int qi = head_lane ? (cm.y & 0xff) : 0, hr_r = head_lane ? (cm.y >> 8) : 0;
-    const int jin_cand = cm.x;
     const int jin_res = d.in_pad[(int64_t)v * d.max_in + min(gl, d.max_in - 1)];
     const int off_res = d.in_loff[(int64_t)v * d.max_in + min(gl, d.max_in - 1)];   // first head lane of in-link gl
-    // ---- out-link lanes ----
-    int om = -1, ohead = -1, oslots = 0, otail = 0, obase = 0, ocap = 1;
-    double outil = 0.0;
-    if (gl < dego) {   // two records: the out-link's constants and its (rhead, rtail, slots, nheads)
-        om = om_raw;
-        const LinkNd c = d.lnd[sL + om];
-        const int4 q = *reinterpret_cast<const int4 *>(&d.ls[sL + om].rhead);
-        ohead = c.head;
-        outil = c.util;
-        oslots = q.z;
-        otail = q.y;
-        obase = c.ring_base;
-        ocap = c.cap;
+    const bool head_lane = gl < ncin, org_lane = !head_lane && gl < nc;
+    const int qi = head_lane ? (cm.y & 0xff) : 0, hr_r = head_lane ? (cm.y >> 8) : 0;
+    // second-level loads of every role, issued together in straight-line code: a lane without the
+    // role reads a valid stand-in entry and its result is selected away.  Loads placed under the
+    // role branches would wait for one another (the memory counter is in order, so a branch that
+    // waits for its own load also waits for every load issued before it).
+    const int om_c = max(om_raw, 0), jin_c = max(jin_res, 0), jh_c = head_lane ? cm.x : 0;
+    const int org_c = org_lane ? cm.x : 0;
+    const int64_t sjh = sL + jh_c;
+    const LinkNd oc = d.lnd[sL + om_c];                                       // out-link constants
+    const int4 oq = *reinterpret_cast<const int4 *>(&d.ls[sL + om_c].rhead);   // (rhead, rtail, slots, nheads)
+    const LinkSt ist = d.ls[sL + jin_c];                                      // in-link state
+    const int hnh = d.ls[sjh].nheads;                                         // the head lane's in-link
+    const int4 hrec = d.head_rec[sjh * maxl + hr_r];
+    const float hal = d.lnd[sjh].alpha;
+    const int htl = d.lnd[sjh].tail;
+    int orel = 0, odep = 0, oqe = 0;
+    if (d.O > 0) {   // origin lanes: release and departure pointers, end of the queue
+        orel = d.rel_ptr[s * d.O + org_c];
+        odep = d.dep_ptr[s * d.O + org_c];
+        oqe = d.q_off[org_c + 1];
     }
-    // ---- in-link lanes (resolve) ----
-    int64_t sjq = -1;
-    double Bj = 0.0, dBj = 0.0;
-    int nhq = 0, hq0 = 0;
-    int64_t Eq0 = 0;
     const bool graft = tape_k >= 0 && d.tape_dstg != nullptr;   // admission-graft tape (recording replay)
-    if (gl < deg) {   // everything this lane updates at the end is read here, with the first loads
-        sjq = sL + jin_res;
-        const LinkSt st = d.ls[sjq];
-        Bj = st.B;
-        nhq = st.nheads;
-        hq0 = st.rhead;
-        Eq0 = st.E;
-        if (graft) dBj = d.dB[sjq];
-    }
+    double dBj = 0.0;
+    if (graft) dBj = gl < deg ? d.dB[sL + jin_c] : 0.0;
+    // ---- out-link lanes ----
+    const bool out_lane = gl < dego;
+    const int om = out_lane ? om_raw : -1, ohead = out_lane ? oc.head : -1;
+    const int oslots = out_lane ? oq.z : 0, otail = out_lane ? oq.y : 0;
+    const int obase = out_lane ? oc.ring_base : 0, ocap = out_lane ? oc.cap : 1;
+    const double outil = out_lane ? oc.util : 0.0;
+    // ---- in-link lanes (resolve): everything this lane updates at the end ----
+    const bool in_lane = gl < deg;
+    const int64_t sjq = in_lane ? sL + jin_c : -1;
+    double Bj = in_lane ? ist.B : 0.0;
+    const int nhq = in_lane ? ist.nheads : 0, hq0 = in_lane ? ist.rhead : 0;
+    const int64_t Eq0 = in_lane ? ist.E : 0;
     const double Bacc = Bj;   // accrued level before this step's tokens
     // ---- candidate of this lane ----
-    int ag = -1, dst = -1, didx = 0, origin = -1, from = -1, ftail = -1, dp0 = 0;
-    double alpha = 1.0;
-    if (head_lane) {
-        const int r = hr_r;
-        const int jj = jin_cand;
-        const int64_t sj = sL + jj;
-        const int nh = d.ls[sj].nheads;
-        const int4 hr = d.head_rec[sj * maxl + r];
-        const LinkNd c = d.lnd[sj];
-        const float al = c.alpha;
-        const int tl = c.tail;
-        if (r < nh) { ag = hr.x; dst = hr.y; didx = hr.z; from = jj; alpha = (double)al; ftail = tl; }
-    } else if (gl < nc) {
+    const bool hv = head_lane && hr_r < hnh;
+    int ag = hv ? hrec.x : -1, dst = hv ? hrec.y : -1, didx = hv ? hrec.z : 0;
+    const int from = hv ? jh_c : -1, ftail = hv ? htl : -1;
+    const double alpha = hv ? (double)hal : 1.0;
+    int origin = -1, dp0 = 0;
+    if (org_lane) {
         origin = cm.x;
-        const int qb = cm.y, qn = d.q_off[origin + 1] - qb;
+        const int qb = cm.y, qn = oqe - qb;
         const int so = s * d.O + origin;
-        const int rel = d.rel_ptr[so];
-        dp0 = d.dep_ptr[so];
+        const int rel = orel;
+        dp0 = odep;
         // the queue front is the entry at the departure pointer whether or not this step releases
         // it: load it before any release is written
         int fa = -1, fdst = -1, fdidx = 0;
