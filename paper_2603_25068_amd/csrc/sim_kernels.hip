@@ -493,11 +493,11 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 // Per-group LDS tables of the node phase: what a lane group's out-link lanes and candidate lanes
 // publish for the others, read with plain LDS loads (no cross-lane shuffles inside branchy loops).
 struct OutRec { double util; int om, head, slots, tail, base, cap; };   // out-link k of the node
-struct alignas(16) CandRec { double key; int ch, ag; };                     // candidate lane e
+struct alignas(16) CandRec { float kf; int ch, ag, pad; };                 // candidate lane e
 
 template <int G>
 __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s, int v, int item, int t, int tape_k,
-                                          OutRec *orc, CandRec *crc)
+                                          OutRec *orc, CandRec *crc, double *ckey)
 {
     const int gl = g.gl;
     const int maxl = d.maxl;
@@ -730,48 +730,60 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
     } else if (exiting) {
         ch = CH_EXIT;
     }
-    // merge key alpha_from + g' on the fast noise; exact below where two keys for one link are close
-    double key = 0.0;
-    if (ag >= 0) key = alpha + (double)gumbel_fast(wm[0]);
-
     // ---- merge: rank among candidates wanting the same link ----
-    // every candidate lane publishes (key, choice, agent); a chooser counts the candidates of its
-    // own out-link that precede it in key order
+    // Every candidate lane publishes (key, choice, agent); a chooser counts the candidates of its own
+    // out-link that precede it in key order.  Fast pass on single-precision keys alpha_from + g' (g'
+    // the fast noise): each lies within 1e-5 + 2^-24 |key| of the double-precision key, so while
+    // |key| < 512 a difference of two keys is off by less than 8.2e-5 and its sign is exact wherever
+    // it exceeds kFastMargin.  A group with a rival pair inside the margin, or a key of 512 or more,
+    // ranks again on double-precision keys (ties broken by agent id, and the near-tie log, live only
+    // there).  The candidate lanes 0..nc-1 go in chunks of four, each chunk unrolled and
+    // branch-free (predicates combine with non-short-circuit & and |, so no record read is placed
+    // under a branch) so that its broadcast LDS reads are in flight together; lanes past nc are
+    // masked out of the sums.
+    constexpr int kCk = 4;
+    const float kf = ag >= 0 ? (float)alpha + gumbel_fast(wm[0]) : 0.f;
+    const bool act = ag >= 0 && ch >= 0;
     int rank = 0, close = 0;
     bool knear = false;
-    crc[gl] = CandRec{key, ag >= 0 ? ch : CH_NONE, ag};
+    crc[gl] = CandRec{kf, ag >= 0 ? ch : CH_NONE, ag, 0};
     wave_lds_sync();
-    // the candidate lanes 0..nc-1 in chunks of up to sixteen, each chunk unrolled and branch-free (the
-    // predicates combine with non-short-circuit & and |, so no record read is placed under a branch)
-    // so that its broadcast LDS reads are in flight together; lanes past nc are masked out of the sums
-    constexpr int kCk = G <= 16 ? G : 8;
-    auto rank_pass = [&]() {
-        const bool act = ag >= 0 && ch >= 0;
-        const double tol = 1e-12 * (1.0 + fabs(key));
-        int rk = 0, cl = 0, kn = 0;
+    {
+        int rk = 0, kn = act & !(fabsf(kf) < 512.f);
         for (int e0 = 0; e0 < nc; e0 += kCk)
 #pragma unroll
         for (int k = 0; k < kCk; ++k) {
             const int e = e0 + k;
             const CandRec o = crc[e & (G - 1)];
             const bool rival = act & (e < nc) & (e != gl) & (o.ch == ch);
-            const double diff = o.key - key;   // exact in sign: o.key > key iff diff > 0
+            const float diff = o.kf - kf;
+            rk += rival & (diff > 0.f);
+            kn |= rival & (fabsf(diff) < (float)kFastMargin);
+        }
+        rank = rk;
+        knear = kn != 0;
+    }
+    const bool exact = g.count(knear) != 0;   // the group's ranks on double-precision keys
+    double key = 0.0;
+    if (exact) {
+        if (ag >= 0) key = alpha + gumbel_of(wm[0]);
+        ckey[gl] = key;
+        wave_lds_sync();
+        const double tol = 1e-12 * (1.0 + fabs(key));
+        int rk = 0, cl = 0;
+        for (int e0 = 0; e0 < nc; e0 += kCk)
+#pragma unroll
+        for (int k = 0; k < kCk; ++k) {
+            const int e = e0 + k;
+            const CandRec o = crc[e & (G - 1)];
+            const double diff = ckey[e & (G - 1)] - key;   // exact in sign: a key is ahead iff diff > 0
+            const bool rival = act & (e < nc) & (e != gl) & (o.ch == ch);
             const bool ahead = (diff > 0.0) | ((diff == 0.0) & (o.ag < ag));
             rk += rival & ahead;
             cl |= rival & !ahead & (-diff < tol);
-            kn |= rival & (fabs(diff) < kFastMargin);
         }
         rank = rk;
         close = cl;
-        knear |= kn != 0;
-    };
-    rank_pass();
-    if (g.count(knear)) {   // keys of competing candidates too close for the fast noise: all exact
-        if (ag >= 0) key = alpha + gumbel_of(wm[0]);
-        wave_lds_sync();
-        crc[gl].key = key;
-        wave_lds_sync();
-        rank_pass();
     }
     const int sl = ch >= 0 ? orc[argk].slots : 0;
     const int won = (ch >= 0) && rank < sl;
@@ -814,16 +826,30 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
     wave_lds_sync();
     crc[gl].ch = entering ? ch : CH_NONE;
     wave_lds_sync();
+    // (entrants onto one link are rivals of one another, so the fast keys order them unless the group
+    // ranked on double-precision keys)
     int nent = 0, erank = 0;
-    for (int e0 = 0; e0 < nc; e0 += kCk)
+    if (!exact) {
+        for (int e0 = 0; e0 < nc; e0 += kCk)
 #pragma unroll
-    for (int k = 0; k < kCk; ++k) {
-        const int e = e0 + k;
-        const CandRec o = crc[e & (G - 1)];
-        const bool in = e < nc;
-        nent += in & (o.ch == om);
-        const double diff = o.key - key;
-        erank += in & entering & (e != gl) & (o.ch == ch) & ((diff > 0.0) | ((diff == 0.0) & (o.ag < ag)));
+        for (int k = 0; k < kCk; ++k) {
+            const int e = e0 + k;
+            const CandRec o = crc[e & (G - 1)];
+            const bool in = e < nc;
+            nent += in & (o.ch == om);
+            erank += in & entering & (e != gl) & (o.ch == ch) & (o.kf - kf > 0.f);
+        }
+    } else {
+        for (int e0 = 0; e0 < nc; e0 += kCk)
+#pragma unroll
+        for (int k = 0; k < kCk; ++k) {
+            const int e = e0 + k;
+            const CandRec o = crc[e & (G - 1)];
+            const bool in = e < nc;
+            nent += in & (o.ch == om);
+            const double diff = ckey[e & (G - 1)] - key;
+            erank += in & entering & (e != gl) & (o.ch == ch) & ((diff > 0.0) | ((diff == 0.0) & (o.ag < ag)));
+        }
     }
     if (gl < dego && nent) d.ls[sL + om].rtail = otail + nent;
     int tbase = 0, rbase = 0, rcap = 1;
@@ -903,7 +929,7 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
 // neighbouring nodes share an XCD.
 template <int G>
 __device__ __forceinline__ bool node_role(int c, int b, int nblk, int t, int tape_k, OutRec *orc,
-                                          CandRec *crc)
+                                          CandRec *crc, double *ckey)
 {
     const Dev &d = role_args();
     const Group<G> g;
@@ -913,7 +939,7 @@ __device__ __forceinline__ bool node_role(int c, int b, int nblk, int t, int tap
     if (item >= n) return true;
     const int s = scenario_of(item, d.nd_n[c], d.S);
     const int o = (int)threadIdx.x & ~(G - 1);
-    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k, orc + o, crc + o);
+    node_work<G>(d, g, s, d.nd_begin[c] + (item - s * d.nd_n[c]), item, t, tape_k, orc + o, crc + o, ckey + o);
     return true;
 }
 
@@ -928,17 +954,18 @@ __device__ __forceinline__ void node_launch(const Dev &d, int t, int tape_k)
 {
     __shared__ OutRec orc[256];
     __shared__ CandRec crc[256];
+    __shared__ double ckey[256];   // double-precision merge keys (groups that rank exactly)
     int b = (int)blockIdx.x;
     const int b8 = node_role_blocks(d.S * d.nd_n[0], 8, false);
-    if (b < b8) { node_role<8>(0, b, b8, t, tape_k, orc, crc); return; }
+    if (b < b8) { node_role<8>(0, b, b8, t, tape_k, orc, crc, ckey); return; }
     b -= b8;
     const int b16 = node_role_blocks(d.S * d.nd_n[1], 16, false);
-    if (b < b16) { node_role<16>(1, b, b16, t, tape_k, orc, crc); return; }
+    if (b < b16) { node_role<16>(1, b, b16, t, tape_k, orc, crc, ckey); return; }
     b -= b16;
     const int b32 = node_role_blocks(d.S * d.nd_n[2], 32, false);
-    if (b < b32) { node_role<32>(2, b, b32, t, tape_k, orc, crc); return; }
+    if (b < b32) { node_role<32>(2, b, b32, t, tape_k, orc, crc, ckey); return; }
     b -= b32;
-    node_role<64>(3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc);
+    node_role<64>(3, b, (int)gridDim.x - b8 - b16 - b32, t, tape_k, orc, crc, ckey);
 }
 
 __global__ __launch_bounds__(256) void k_node(Dev d, int t, int tape_k)
