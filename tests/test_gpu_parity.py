@@ -102,6 +102,23 @@ def test_forward_parity_random(seed):
     assert np.array_equal(co.astype(np.float32), cg[0]) and to == tg[0]
 
 
+@pytest.mark.parametrize("seed", [5, 8])
+def test_merge_ranks_on_double_keys_parity(seed):
+    """Merge priorities near 600 put every merge key beyond the range of the
+    kernel's single-precision fast pass (|key| < 512), so every node group
+    with a chooser ranks its merge on double-precision keys; state and counts
+    still equal the oracle's bit for bit."""
+    w = W.random_small(seed, nx=5, ny=5, n_agents=900, rates=False, steps=400, lanes_max=3)
+    alpha = np.random.default_rng(seed).uniform(600.0, 601.0, w.net.n_links).astype(np.float32)
+    o = Oracle(w, params={"alpha": alpha}).run()
+    s = _sim(w, params={"alpha": alpha}).rollout()
+    _compare_state(o, s, ctx=f"{w.name} with alpha near 600")
+    assert o.counters()["transfers"] > 100
+    co, to = o.counts()
+    cg, tg = s.observables()
+    assert np.array_equal(co.astype(np.float32), cg[0]) and to == tg[0]
+
+
 def _grad_close(go, gg, name, rtol=1e-3):
     go = np.asarray(go, np.float64).ravel()
     gg = np.asarray(gg, np.float64).ravel()
