@@ -421,24 +421,29 @@ def profile_pass(args):
 
 
 def rocprof_avg_us(kernel: str, workload: str):
-    """Average duration (us) of `kernel` in the committed rocprofv3 kernel-trace summary of this
-    workload, when its kernel-source digest is the current one; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_kernel_trace.txt")
-    if not os.path.exists(path):
+    """Average duration (us) of `kernel` in a committed rocprofv3 kernel-trace summary of this
+    workload (profiles/*_<workload>_kernel_trace.txt, one table of every step kernel), when the
+    summary's kernel-source digest is the current one; else None."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
         return None
-    text = open(path).read()
-    dig = None
-    for line in text.splitlines():
-        if line.startswith("kernel_source_digest:"):
-            dig = line.split(":", 1)[1].strip()
-    if dig != kernel_source_digest():
-        return None
-    for line in text.splitlines():
-        parts = line.split()
-        if parts and parts[0].startswith(f"sim::{kernel}("):
-            nums = [x for x in parts if x.replace(".", "", 1).isdigit()]
-            if len(nums) >= 3:
-                return float(nums[2])      # calls, total ms, avg us, ...
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(f"_{workload}_kernel_trace.txt"):
+            continue
+        text = open(os.path.join(pdir, name)).read()
+        dig = None
+        for line in text.splitlines():
+            if line.startswith("kernel_source_digest:"):
+                dig = line.split(":", 1)[1].strip()
+        if dig != kernel_source_digest():
+            continue
+        for line in text.splitlines():
+            parts = line.split()
+            if (f"sim::{kernel}(" in line or f"sim::{kernel}<" in line) and len(parts) >= 7:
+                try:
+                    return float(parts[-4])    # ... calls, total ms, avg us, %, min us, max us
+                except ValueError:
+                    continue
     return None
 
 
@@ -572,12 +577,27 @@ def main():
     moves_r = cr["transfers"] + cr["exited"] + cr["departed"]
     # hot-path byte model (28 B per agent-step forward, 68 B per head that moves, 48 B per link or
     # origin and step; 92 B per agent-step for forward+adjoint with every step replayed)
-    if dom == "node":
-        alg = (48.0 * (L + O) * (T + R) + 68.0 * (moves + moves_r)) / launches
-    elif dom == "link":
-        alg = (28.0 * (vs + vs_r) + 48.0 * L * (T + R)) / launches
-    else:
-        alg = (24.0 * vs) / launches
+    def alg_of(kind, n_launch):
+        if kind == "node":
+            return (48.0 * (L + O) * (T + R) + 68.0 * (moves + moves_r)) / n_launch
+        if kind == "link":
+            return (28.0 * (vs + vs_r) + 48.0 * L * (T + R)) / n_launch
+        return (24.0 * vs) / n_launch   # reverse: tape read 12 + adjoint read/write 8 + follower gather 4
+    alg = alg_of(dom, launches)
+    # every step kernel against its own hot-path byte model, with the trace's duration when the
+    # committed summary is current, else the live HIP-event figure
+    by_kernel = {}
+    for kind, (k_ms, k_n) in kinds.items():
+        k_ev = tm.get(kind + "_ev", (0.0, 0))
+        k_us = rocprof_avg_us(f"k_{kind}", w.name)
+        k_src = "rocprofv3 kernel trace (profiles/)"
+        if k_us is None:
+            k_us = 1000.0 * k_ev[0] / k_ev[1] if k_ev[1] else 1000.0 * k_ms / k_n
+            k_src = "HIP events (live)" if k_ev[1] else "wave stamps (live)"
+        k_alg = alg_of(kind, k_n)
+        by_kernel[f"k_{kind}"] = {"alg_bytes_per_launch": int(k_alg), "avg_launch_us": round(k_us, 3),
+                                  "source": k_src, "frac": round(k_alg / (k_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 5),
+                                  "traffic": measured_traffic(f"k_{kind}", w.name)}
     alg_kernel_model = byte_model(dom, S, L, Nn, O, T, vs, moves, launches, R, vs_r, moves_r)
     dur_us, src = (rp_us, "rocprofv3 kernel trace (profiles/)") if rp_us else (ev_us, "HIP events (live)")
     if dur_us is None:
@@ -590,8 +610,13 @@ def main():
                               "wave_stamps_live": round(self_us, 3),
                               "rocprof_kernel_trace": rp_us},
                 "alg_bytes_per_launch": int(alg),
-                "alg_model": ("node phase: 48 B per link or origin and step + 68 B per moving head (transfer, "
-                              "exit, departure), forward and replayed steps" if dom == "node" else "per-agent model"),
+                "alg_model": {"node": "node phase: 48 B per link or origin and step + 68 B per moving head "
+                                      "(transfer, exit, departure), forward and replayed steps",
+                              "link": "link phase: 28 B per agent-step + 48 B per link and step, forward and "
+                                      "replayed steps",
+                              "reverse": "reverse sweep: 24 B per agent-step (tape read 12, adjoint read and "
+                                         "write 8, follower-adjoint gather 4)"}[dom],
+                "by_kernel": by_kernel,
                 "alg_bytes_per_launch_kernel_model": int(alg_kernel_model),
                 "kernel_ms": {k: [round(v[0], 3), v[1]] for k, v in tm.items()}}
     # whole passes
