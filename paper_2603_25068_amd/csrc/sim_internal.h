@@ -61,6 +61,14 @@ struct __align__(32) LinkCf {
     int32_t det;                 // first detector (bits 0-23) | detectors on the link << 24
 };
 
+// Per (scenario, link) factors of the reverse sweep, derived when parameters change: dn / kappa^2
+// (congested-branch gradient in kappa) and 1 / u in double, u in float.
+struct __align__(16) RevCf {
+    double dkap, inv_u;
+    float u;
+    int32_t pad;
+};
+
 struct Dev {
     // sizes
     int32_t S, L, Nn, O, N, D, nb, cbs, n_dest, maxl, n_rate_bins, fixed_mode, allow_uturn, platoon;
@@ -112,6 +120,7 @@ struct Dev {
     LinkSt *ls;                      // [S*L] bucket, outflow, ring counters, entry slots, heads
     const LinkNd *lnd;               // [S*L] node-phase constants
     const LinkCf *lcf;               // [S*L] link- and reverse-phase constants
+    const RevCf *rcf;                // [S*L] reverse-sweep factors
     double *dB;                      // [S*L] dB/d cap_mult (recording handles only, else null)
     int4 *head_rec;                  // [S*L*maxl] (agent, destination, table row, -) of each head
     uint8_t *status;                 // [S*N]
@@ -130,6 +139,7 @@ struct Dev {
     float *tape_pos;                 // [(W+1) * S * ring_total]
     int32_t *tape_agent;             // same
     int32_t *tape_head, *tape_tail;  // [(W+1) * S * L]
+    int32_t *tape_hslot;             // [(W+1) * S * L] ring slot of the head (tape_head mod capacity)
     int32_t *tape_dst;               // [(W+1) * S * L * maxl] entry slot of each leaving head (-1: exit)
     float *tape_dstg;                // same shape as tape_dst: admission-graft factor -u_to dt_tok/dm
     int4 *tape_ste;                  // [(W+1) * S * n_cand] per node candidate: (agent, chosen out-link index |
@@ -198,7 +208,7 @@ int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, con
                            int32_t *perm, int32_t *seg_off, int32_t *status, hipStream_t st);
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
-                   LinkCf *lcf, hipStream_t st);
+                   LinkCf *lcf, RevCf *rcf, hipStream_t st);
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st);
 void launch_counts(const Dev &d, float *out, hipStream_t st);
 void launch_d2f(const double *src, float *dst, int64_t n, hipStream_t st);

@@ -304,6 +304,7 @@ __device__ __forceinline__ void link_segment(const Dev &d, const Group<G> &g, in
         if (gl == 0) {
             d.tape_head[(int64_t)tape_k * d.S * d.L + seg] = h0;
             d.tape_tail[(int64_t)tape_k * d.S * d.L + seg] = h0 + n;
+            d.tape_hslot[(int64_t)tape_k * d.S * d.L + seg] = hm;
         }
     }
     // a ring keeps `lanes` slots free, so an entry slot never aliases a slot live one step earlier
@@ -988,6 +989,7 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
     if (lane == 0) {
         d.tape_head[(int64_t)tape_k * d.S * d.L + seg] = h0;
         d.tape_tail[(int64_t)tape_k * d.S * d.L + seg] = h0 + n;
+        d.tape_hslot[(int64_t)tape_k * d.S * d.L + seg] = h0 % cap;
     }
     for (int r = lane; r < n; r += kWave) {
         const int slot = (h0 + r) % cap;
@@ -1036,12 +1038,13 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
     const int64_t RTS = (int64_t)d.S * d.ring_total;
     const int64_t tb = (int64_t)tape_k * RTS + base;
     const float vf = lc.vf, sp = lc.sp, Lj = lc.L;
-    const float uj = d.u[seg], kap = d.kappa[seg];
-    const double dkap = (double)d.platoon / ((double)kap * (double)kap);
+    const RevCf rc = d.rcf[seg];
+    const float uj = rc.u;
+    const double dkap = rc.dkap;
     const double gTs = d.gT ? d.gT[s] : 0.0;
-    const float exit_adj = (float)(-gTs / (double)uj);
+    const float exit_adj = (float)(-gTs * rc.inv_u);
     const int64_t sN = (int64_t)s * d.N;
-    const int hm = hk % cap;
+    const int hm = d.tape_hslot[tape_k * SL + seg];   // hk mod cap, taped by the forward
     auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     int sb = -1;
     if (d.gQ && d.cbs > 0 && t > 0 && t % d.cbs == 0 && t / d.cbs <= d.nb) sb = t / d.cbs - 1;
@@ -1463,7 +1466,7 @@ __global__ __launch_bounds__(256) void k_rate_grad(Dev d, float *g)
 // Derived per-(scenario, link) constants.
 __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, const float *beta,
                          const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
-                         LinkCf *lcf)
+                         LinkCf *lcf, RevCf *rcf)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)d.S * d.L) return;
@@ -1491,6 +1494,13 @@ __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, co
     f.ring_base = d.ring_base[j];
     f.det = d.det_off[j] | ((d.det_off[j + 1] - d.det_off[j]) << 24);
     lcf[i] = f;
+    RevCf rv;
+    const double kd = (double)d.kappa[i];
+    rv.dkap = (double)d.platoon / (kd * kd);
+    rv.inv_u = 1.0 / (double)d.u[i];
+    rv.u = d.u[i];
+    rv.pad = 0;
+    rcf[i] = rv;
 }
 
 // Total travel time and vehicle-steps per scenario: dt * sum over released
@@ -1938,11 +1948,11 @@ void launch_rate_grad(const Dev &d, float *g, hipStream_t st)
 }
 void launch_derive(const Dev &d, const float *cap_mult, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
-                   LinkCf *lcf, hipStream_t st)
+                   LinkCf *lcf, RevCf *rcf, hipStream_t st)
 {
     const int64_t n = (int64_t)d.S * d.L;
     hipLaunchKernelGGL(k_derive, dim3((int)((n + 255) / 256)), dim3(256), 0, st, d, cap_mult, capacity, beta, cost,
-                       util, acc, vfree, spacing, lnd, lcf);
+                       util, acc, vfree, spacing, lnd, lcf, rcf);
 }
 void launch_ttt(const Dev &d, int T, double *out, int64_t *vsteps, unsigned long long *acc, hipStream_t st)
 {

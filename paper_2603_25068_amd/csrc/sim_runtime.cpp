@@ -109,7 +109,7 @@ struct sim_t {
     // others, on their own streams; the recording forward fills the sets of the last windows
     struct TapeSet {
         float *pos = nullptr, *dstg = nullptr;
-        int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *dst = nullptr;
+        int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *hslot = nullptr, *dst = nullptr;
         int4 *ste = nullptr;   // node candidates' choices and outcomes (straight-through gradients)
     };
     std::vector<TapeSet> tapes;              // n_tape_sets sets
@@ -136,6 +136,7 @@ struct sim_t {
     double *util = nullptr, *acc = nullptr;
     sim::LinkNd *lnd_dev = nullptr;
     sim::LinkCf *lcf_dev = nullptr;
+    sim::RevCf *rcf_dev = nullptr;
     // mutable queue buffers
     int32_t *q_off_dev = nullptr, *q_list_dev = nullptr, *q_dest_dev = nullptr, *q_didx_dev = nullptr;
     int64_t *q_rstep_dev = nullptr;
@@ -568,7 +569,7 @@ void build_classes(sim_t *h)
 void derive(sim_t *h)
 {
     sim::launch_derive(h->d, h->p_capm, h->capacity_dev, h->p_beta, h->p_cost, h->util, h->acc, h->vfree, h->spacing,
-                       h->lnd_dev, h->lcf_dev, h->stream);
+                       h->lnd_dev, h->lcf_dev, h->rcf_dev, h->stream);
     HIPCHK(hipGetLastError());
 }
 
@@ -892,7 +893,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
     // (the serving pool carves a request's state with that alignment)
     const size_t nQ = (size_t)h->S * h->D * std::max(h->nb, 1);
     size_t bytes = SR * 16                                   // ring positions, agents, (destination, row)
-                   + SL * (24 + 8 + 16 + 32 + 64 + maxl * 16)   // parameters, derived, state, link records, heads
+                   + SL * (24 + 8 + 16 + 32 + 96 + maxl * 16)   // parameters, derived, state, link records, heads
                    + SN * (1 + 8 + 12) + SO * 16             // per agent and per origin state
                    + (size_t)h->S * h->O * std::max(h->B, 1) * 4
                    + (size_t)L * 56 + (size_t)Nn * 32        // link constants, node offsets and words
@@ -909,7 +910,7 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
         // one tape set: positions and agents per slot, head/tail per segment, entry slot and graft factor
         // per leaving head, and a straight-through record per node candidate, for W + 1 states
         const size_t per_set = (size_t)(h->W + 1) *
-                               (SR * 8 + SL * 8 + SL * maxl * 8 + (size_t)h->S * std::max(h->n_cand, 1) * 16);
+                               (SR * 8 + SL * 12 + SL * maxl * 8 + (size_t)h->S * std::max(h->n_cand, 1) * 16);
         const int min_sets = h->n_replay + 1, windows = std::max(n_ck - 1, 1);
         int sets = cfg->tape_windows > 0 ? std::max(min_sets, (int)cfg->tape_windows)
                                          : (int)std::min<size_t>(16, ((size_t)32 << 30) / std::max<size_t>(per_set, 1));
@@ -994,6 +995,8 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     d.lnd = h->lnd_dev;
     h->lcf_dev = h->dalloc<sim::LinkCf>(SL);
     d.lcf = h->lcf_dev;
+    h->rcf_dev = h->dalloc<sim::RevCf>(SL);
+    d.rcf = h->rcf_dev;
     d.head_rec = h->dalloc<int4>(SL * maxl);
     d.status = h->dalloc<uint8_t>(SN); d.tstar = h->dalloc<double>(SN);
     d.rel_t = h->dalloc<int32_t>(SN); d.dep_t = h->dalloc<int32_t>(SN); d.exit_t = h->dalloc<int32_t>(SN);
@@ -1016,12 +1019,13 @@ void allocate_device(sim_t *h, const sim_config *cfg)
             ts.agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
             ts.head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
             ts.tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+            ts.hslot = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
             ts.dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
             ts.dstg = h->dalloc<float>((size_t)(h->W + 1) * SL * maxl);
             ts.ste = h->dalloc<int4>((size_t)(h->W + 1) * h->S * std::max(h->n_cand, 1));
         }
         d.tape_pos = h->tapes[0].pos; d.tape_agent = h->tapes[0].agent;
-        d.tape_head = h->tapes[0].head; d.tape_tail = h->tapes[0].tail;
+        d.tape_head = h->tapes[0].head; d.tape_tail = h->tapes[0].tail; d.tape_hslot = h->tapes[0].hslot;
         h->rp_dev.assign((size_t)h->n_replay, d);
         h->rp_stream.assign((size_t)h->n_replay, nullptr);
         for (int k = 0; k < h->n_replay; ++k) {
@@ -1468,6 +1472,7 @@ int sim_rollout(sim_t *h, int32_t T)
                 Dev dt = h->d;
                 const auto &ts = h->tapes[set];
                 dt.tape_pos = ts.pos; dt.tape_agent = ts.agent; dt.tape_head = ts.head; dt.tape_tail = ts.tail;
+                dt.tape_hslot = ts.hslot;
                 dt.tape_dst = ts.dst; dt.tape_dstg = nullptr; dt.tape_ste = nullptr;
                 step_on(h, dt, h->stream, h->t, contiguous ? kw : -1);
                 h->t += 1;
@@ -1556,6 +1561,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         auto use_tapes = [&](Dev &dv, int set) {
             const auto &ts = h->tapes[set];
             dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_head = ts.head; dv.tape_tail = ts.tail;
+            dv.tape_hslot = ts.hslot;
             dv.tape_dst = ts.dst;
             dv.tape_dstg = want_m ? ts.dstg : nullptr;
             dv.tape_ste = want_ste ? ts.ste : nullptr;
