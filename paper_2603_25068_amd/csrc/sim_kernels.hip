@@ -1102,29 +1102,33 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
         wave_lds_sync();
         for (int r0 = lo; r0 < hi; r0 += G) {
             const int r = r0 + gl;
-            if (r >= hi) continue;
-            const float x = xb[r - slo];
-            const float ap = pb[r - slo];
+            const bool v = r < hi;
+            // every LDS read of the rank is issued unconditionally (a lane without the leader,
+            // follower or rank reads its own staged entry instead and selects the value away), so the
+            // reads are in flight together rather than one wait per branch; the leader (r - ln >= slo)
+            // and the follower (r + ln < n <= shi) always lie in the staged piece when they exist
+            const int ir = v ? r - slo : 0;
+            const bool hl = v & (r >= ln), hf = v & (r + ln < n);
+            const int il = hl ? r - ln - slo : ir, ifl = hf ? r + ln - slo : ir;
+            const float x = xb[ir], ap = pb[ir], xl = xb[il], xfol = xb[ifl], apf = pb[ifl];
             float anew;
             if (!init) {
                 int br = 0;  // 0 free, 1 congested, 2 stopped
-                if (r >= ln) {
-                    const float xl = xb[r - ln - slo];
+                {
                     const float xf = x + vf, xc = xl - sp;
                     const float cc = (x > xc) ? x : xc;
-                    br = (xf <= cc) ? 0 : ((x > xc) ? 2 : 1);
+                    const int b = (xf <= cc) ? 0 : ((x > xc) ? 2 : 1);
+                    br = hl ? b : 0;
                 }
                 float af = 0.f;
-                const int fr = r + ln;
-                if (fr < n) {
-                    const float xfol = xb[fr - slo];
+                {
                     const float ff = xfol + vf, xc = x - sp;
                     const float cc = (xfol > xc) ? xfol : xc;
-                    if (!(ff <= cc) && !(xfol > xc)) af = pb[fr - slo];
+                    af = (hf & !(ff <= cc) & !(xfol > xc)) ? apf : 0.f;
                 }
                 anew = (br != 1 ? ap : 0.f) + af;
-                if (br == 0) gu += d.dt * (double)ap;
-                if (br == 1) gk += dkap * (double)ap;
+                gu += (v & (br == 0)) ? d.dt * (double)ap : 0.0;
+                gk += (v & (br == 1)) ? dkap * (double)ap : 0.0;
             } else {
                 anew = ap;
             }
@@ -1140,7 +1144,7 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
                     anew += gC * sc * sg * (1.0f - sg);
                 }
             }
-            d.adj_ring[base + slot_of(r)] = anew;
+            if (v) d.adj_ring[base + slot_of(r)] = anew;
         }
         wave_lds_sync();
     }
