@@ -206,6 +206,11 @@ constexpr int kMaxDevices = 64;
 int segsort_scratch_init(int device);
 int launch_segsort_noalloc(int device, int n, int n_seg, const int32_t *seg, const float *pos, const int32_t *seq,
                            int32_t *perm, int32_t *seg_off, int32_t *status, hipStream_t st);
+// Several device-to-device copies in one launch (16-byte aligned arrays; any byte count).
+constexpr int kMaxCopyJobs = 12;
+struct CopyJob { const void *src; void *dst; uint64_t bytes; };
+struct CopyJobs { CopyJob job[kMaxCopyJobs]; int32_t n; };
+void launch_copy_multi(const CopyJobs &jobs, hipStream_t st);
 void launch_derive(const Dev &d, const float *cap_mult_scen, const float *capacity, const float *beta,
                    const float *cost, double *util, double *acc, float *vfree, float *spacing, LinkNd *lnd,
                    LinkCf *lcf, RevCf *rcf, hipStream_t st);

@@ -1515,6 +1515,23 @@ __global__ void k_derive(Dev d, const float *cap_mult, const float *capacity, co
 // Total travel time and vehicle-steps: integer sums over agents of (exit or T) - release and
 // (exit or T) - departure, exact in int64 whatever the order; each block adds its sum with one
 // atomic, and k_ttt_final scales by dt.
+// The checkpoint's arrays in one launch: 16-byte chunks grid-strided over each array, then its
+// byte tail (all arrays start on 256-byte boundaries).
+__global__ __launch_bounds__(256) void k_copy_multi(CopyJobs jobs)
+{
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < jobs.n; ++k) {
+        const uint4 *src = static_cast<const uint4 *>(jobs.job[k].src);
+        uint4 *dst = static_cast<uint4 *>(jobs.job[k].dst);
+        const uint64_t nv = jobs.job[k].bytes / 16, rem = jobs.job[k].bytes - nv * 16;
+        for (uint64_t i = tid; i < nv; i += nth) dst[i] = src[i];
+        if (tid < rem)
+            static_cast<char *>(jobs.job[k].dst)[nv * 16 + tid] =
+                static_cast<const char *>(jobs.job[k].src)[nv * 16 + tid];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_ttt(Dev d, int T, unsigned long long *acc)
 {
     const int s = blockIdx.y;
@@ -1923,6 +1940,14 @@ void launch_node(const Dev &d, int t, int tape_k, hipStream_t st)
     const int blocks = node_role_blocks(d.S * d.nd_n[0], 8, false) + node_role_blocks(d.S * d.nd_n[1], 16, false) +
                        node_role_blocks(d.S * d.nd_n[2], 32, false) + node_role_blocks(d.S * d.nd_n[3], 64, true);
     launch(k_node, std::max(blocks, 1), st, d, t, tape_k);
+}
+void launch_copy_multi(const CopyJobs &jobs, hipStream_t st)
+{
+    uint64_t total = 0;
+    for (int k = 0; k < jobs.n; ++k) total += jobs.job[k].bytes / 16;
+    const uint64_t want = (total + 255) / 256;
+    const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, 2048));
+    hipLaunchKernelGGL(k_copy_multi, dim3(blocks), dim3(256), 0, st, jobs);
 }
 void launch_tape_snapshot(const Dev &d, int tape_k, hipStream_t st)
 {

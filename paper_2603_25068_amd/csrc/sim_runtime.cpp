@@ -606,9 +606,11 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save, Dev *target = nullptr, hipStream_t 
     Dev &d = target ? *target : h->d;
     const size_t SR = (size_t)h->S * h->ring_total, SL = (size_t)h->S * h->L, SO = (size_t)h->S * h->O;
     const hipStream_t st = on ? on : h->stream;
+    // every array of the checkpoint in one copy launch (ten separate copies cost a launch each)
+    sim::CopyJobs jobs{};
     auto cp = [&](void *ck, void *live, size_t bytes) {
-        if (save) HIPCHK(hipMemcpyAsync(ck, live, bytes, hipMemcpyDeviceToDevice, st));
-        else HIPCHK(hipMemcpyAsync(live, ck, bytes, hipMemcpyDeviceToDevice, st));
+        if (bytes == 0) return;
+        jobs.job[jobs.n++] = save ? sim::CopyJob{live, ck, bytes} : sim::CopyJob{ck, live, bytes};
     };
     cp(c.ring_pos, d.ring_pos, SR * 4);
     cp(c.ring_agent, d.ring_agent, SR * 4);
@@ -620,6 +622,8 @@ void ckpt_copy(sim_t *h, Ckpt &c, bool save, Dev *target = nullptr, hipStream_t 
     cp(c.dep_ptr, d.dep_ptr, SO * 4);
     cp(c.ctr, d.ctr, (size_t)h->S * sim::kCtrSlots * sim::CTR_N * 8);
     cp(c.status, d.status, (size_t)h->S * h->N);
+    sim::launch_copy_multi(jobs, st);
+    HIPCHK(hipGetLastError());
 }
 
 // the mutable state arrays of `src`, put into `dst` (parameters, tables, tape stay dst's)
