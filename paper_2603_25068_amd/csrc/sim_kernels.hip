@@ -482,14 +482,16 @@ __global__ __launch_bounds__(256) void k_link(Dev d, int t, int sample_b, int ta
 //   of each in-link's heads against its token bucket; grafted transfer:
 //   leavers pop from the in-link ring, entrants push at position 0 onto the
 //   out-link ring (SI-B eq. transfer; the graft itself lives in the adjoint).
-// Candidate lanes: the heads of in-link q take lanes [off_q, off_q + lanes_q)
-// (a per-node table gives each lane its in-link and head rank); then origins.
-// Out-link lanes k < out-degree load the out-link's data and publish it in the
-// group's LDS table; candidates publish (key, choice, agent) the same way, so
-// choice, merge ranks and entry order are plain LDS reads.  A chooser requests
-// all route entries and Philox words of 16 out-links before its first score.
+// Candidate lanes: the heads of in-link q take lanes [off_q, off_q + lanes_q),
+// then the node's origins (one per-node table gives each lane its in-link and
+// head rank, or its origin and first queue entry).  Out-link lanes k <
+// out-degree load the out-link's data and publish it in the group's LDS table;
+// candidates publish (key, choice, agent) the same way, so choice, merge ranks
+// and entry order are plain LDS reads.  A chooser requests the route entries,
+// Philox words and out-link records of 8 out-links before its first score.
 // Per-node link lists are padded node-major tables, so every lane finds its
-// link in the first load.  `item` only spreads the counter atomics.
+// link in the first load, and the second-level loads of all lane roles go out
+// as one straight-line batch.  `item` only spreads the counter atomics.
 // ---------------------------------------------------------------------------
 // Per-group LDS tables of the node phase: what a lane group's out-link lanes and candidate lanes
 // publish for the others, read with plain LDS loads (no cross-lane shuffles inside branchy loops).
