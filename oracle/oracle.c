@@ -1244,7 +1244,7 @@ int orc_frozen_eval(orc_t *o, const double *u_in, const double *kappa_in, const 
                     ++pim_k;
                 }
             }
-            /* candidates that stayed on their link: X - (M + x) I_remove */
+            /* candidates that stayed on their link: the X - (M + x) I_remove term of the SI-B transfer update */
             for (int32_t c = 0; c < g->n; ++c) {
                 const ch_rec *cr = &o->chs.p[o->mgc.p[g->c0 + c]];
                 if (!o->mgmv.p[g->c0 + c] && cr->from >= 0) x[cr->agent] -= (bigm + x[cr->agent]) * dA[cr->agent];

@@ -851,8 +851,8 @@ def test_straight_through_adjoint_matches_frozen_surrogate_fd(seed):
 
 @pytest.mark.parametrize("alpha,seed", [((1.0, 1.0), 0), ((1.3, 0.6), 5), ((0.8, 1.1), 9)])
 def test_merge_priority_gradient_closed_form(alpha, seed):
-    """Two heads, one entry slot.  In the paper's transfer update X - (M + x)
-    I_remove + (M + x - sg x) I_add with a = onehot(p') + p' - sg(p'),
+    """Two heads, one entry slot.  In the transfer update of SI-B
+    (differentiable vehicle transfer), X - (M + x) I_remove + (M + x - sg x) I_add with a = onehot(p') + p' - sg(p'),
     p' = softmax((alpha_from + g')/tau) over the two heads, the winner w moved
     (its share of the update is M adj_w) and the loser l stayed at its link
     end x = L (share -(M + L) adj_l), so
