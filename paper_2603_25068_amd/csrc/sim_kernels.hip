@@ -1031,22 +1031,33 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
     const int gl = g.gl;
     const int seg = s * d.L + j;
     const int64_t SL = (int64_t)d.S * d.L;
+    const int64_t ek = tape_k * SL + seg;          // tape entry of time t
+    const int64_t ek1 = init ? ek : ek + SL;       // of time t+1 (the final state has none)
+    // every per-segment value in one straight-line batch: link records, tape counters at t and
+    // t+1, and the entry slots of the heads that left, read speculatively by the lanes below maxl
+    // (a head that left has rank < lanes <= maxl <= G, so rank gl's is lane gl's)
     const LinkCf lc = d.lcf[seg];
+    const RevCf rc = d.rcf[seg];
+    const int hk = d.tape_head[ek], tk = d.tape_tail[ek];
+    const int hm = d.tape_hslot[ek];               // hk mod cap, taped by the forward
+    const int hk1 = d.tape_head[ek1], tk1 = d.tape_tail[ek1];
+    const int ds_l = init ? -1 : d.tape_dst[ek * d.maxl + min(gl, d.maxl - 1)];
+    const double gTs = d.gT ? d.gT[s] : 0.0;
     const int cap = lc.cap, ln = lc.lanes;
-    const int hk = d.tape_head[tape_k * SL + seg];
-    const int n = min(d.tape_tail[tape_k * SL + seg] - hk, cap);
-    const int npass = init ? 0 : d.tape_head[(tape_k + 1) * SL + seg] - hk;
+    const int n = min(tk - hk, cap);
+    const int npass = init ? 0 : min(hk1 - hk, ln);
+    // lane gl's head: its entry slot if it left during step t (-1: it left the network), else -2
+    const int dsx = gl < npass ? ds_l : -2;
+    // agents that entered during step t hold ranks n .. n + ne - 1 at t+1 (the ring's free slots)
+    const int ne = init ? 0 : max(0, min(tk1 - tk, cap - n));
     const int64_t base = (int64_t)s * d.ring_total + lc.ring_base;
     const int64_t RTS = (int64_t)d.S * d.ring_total;
     const int64_t tb = (int64_t)tape_k * RTS + base;
     const float vf = lc.vf, sp = lc.sp, Lj = lc.L;
-    const RevCf rc = d.rcf[seg];
     const float uj = rc.u;
     const double dkap = rc.dkap;
-    const double gTs = d.gT ? d.gT[s] : 0.0;
     const float exit_adj = (float)(-gTs * rc.inv_u);
     const int64_t sN = (int64_t)s * d.N;
-    const int hm = d.tape_hslot[tape_k * SL + seg];   // hk mod cap, taped by the forward
     auto slot_of = [&](int r) { const int q = hm + r; return q >= cap ? q - cap : q; };
     int sb = -1;
     if (d.gQ && d.cbs > 0 && t > 0 && t % d.cbs == 0 && t / d.cbs <= d.nb) sb = t / d.cbs - 1;
@@ -1055,51 +1066,41 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
     const int P = bufcap / 2;
     float *xb = buf, *pb = buf + P;
     const int piece = P - 2 * kMaxLanes;
-    const int64_t dst0 = ((int64_t)tape_k * SL + seg) * d.maxl;
     double gu = 0.0, gk = 0.0, gm = 0.0;
     for (int lo = 0; lo < n; lo += piece) {
         const int hi = min(n, lo + piece);
         const int slo = max(0, lo - ln), shi = min(n, hi + ln);
         // taped positions of [slo, shi) and the adjoints of the x_hat of [lo, shi): kRevUnroll ranks
-        // per lane per round with their direct loads in flight together; the few heads that left
-        // (r < npass) then read their adjoint at the entry slot the tape names
+        // per lane per round with their direct loads in flight together.  A head that left (rank <
+        // npass <= lanes <= G: the first round of the first piece, rank gl) reads its adjoint at the
+        // entry slot the tape names, or takes the exit term, in the same batch; a piece holds more
+        // than G ranks, so no such head lies in a follower halo
         for (int r = slo + gl; r < shi; r += kRevUnroll * G) {
-            float x4[kRevUnroll], a4[kRevUnroll];
+            float x4[kRevUnroll], a4[kRevUnroll], g0 = 0.f;
+            // rank r < G: the first round of the first piece, where rank r is lane gl's head
+            const bool left = (r < G) & (dsx >= 0), gone = (r < G) & (dsx == -1);
 #pragma unroll
             for (int q = 0; q < kRevUnroll; ++q) {
                 const int rr = r + q * G;
                 const bool in = rr < shi;
                 const int sl = in ? slot_of(rr) : 0;
+                const int64_t ai = (q == 0 && left) ? (int64_t)dsx : base + sl;
                 x4[q] = in ? d.tape_pos[tb + sl] : 0.f;
-                a4[q] = (in && rr >= lo && !init && rr >= npass) ? d.adj_ring[base + sl] : 0.f;
+                const float a = (in && rr >= lo && !init && (q > 0 || !gone)) ? d.adj_ring[ai] : 0.f;
+                a4[q] = (q == 0 && gone) ? exit_adj : a;
             }
+            // admission-graft factor of a head that left on a token
+            if (d.gm && left) g0 = d.tape_dstg[ek * d.maxl + gl];
 #pragma unroll
             for (int q = 0; q < kRevUnroll; ++q) {
                 const int rr = r + q * G;
                 if (rr < shi) xb[rr - slo] = x4[q];
                 if (rr < shi && rr >= lo) pb[rr - slo] = a4[q];
             }
+            if (d.gm && left) gm += (double)a4[0] * (double)g0;
         }
-        // heads that left, and the final state's cotangents
-        for (int r = lo + gl; r < hi && (init || r < npass); r += G) {
-            float ap;
-            if (init) {
-                ap = d.gx ? d.gx[sN + d.tape_agent[tb + slot_of(r)]] : 0.f;
-            } else {
-                const int ds = d.tape_dst[dst0 + r];
-                ap = ds < 0 ? exit_adj : d.adj_ring[ds];
-                // admission graft of a head that left on a token
-                if (d.gm && ds >= 0) gm += (double)ap * (double)d.tape_dstg[dst0 + r];
-            }
-            pb[r - slo] = ap;
-        }
-        if (init) {   // the follower halo [hi, shi) of the final state
-            for (int r = hi + gl; r < shi; r += G) pb[r - slo] = d.gx ? d.gx[sN + d.tape_agent[tb + slot_of(r)]] : 0.f;
-        } else {      // heads that left in the follower halo (only when a piece ends inside them)
-            for (int r = hi + gl; r < min(shi, npass); r += G) {
-                const int ds = d.tape_dst[dst0 + r];
-                pb[r - slo] = ds < 0 ? exit_adj : d.adj_ring[ds];
-            }
+        if (init) {   // the final state's cotangents, follower halo [hi, shi) included
+            for (int r = lo + gl; r < shi; r += G) pb[r - slo] = d.gx ? d.gx[sN + d.tape_agent[tb + slot_of(r)]] : 0.f;
         }
         wave_lds_sync();
         for (int r0 = lo; r0 < hi; r0 += G) {
@@ -1151,13 +1152,17 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
         wave_lds_sync();
     }
     // departure grafts of the agents that entered this link during step t
-    if (!init && d.depg) {
-        const int e0 = d.tape_tail[tape_k * SL + seg], e1 = d.tape_tail[(tape_k + 1) * SL + seg];
+    if (d.depg) {   // entrants (counted from the taped tails read with the segment's header)
         const int64_t tb1 = (int64_t)(tape_k + 1) * RTS + base;
-        for (int q = e0 + gl; q < e1; q += G) {
-            const int sl = q % cap;
+        for (int q = n + gl; q < n + ne; q += G) {
+            const int sl = slot_of(q);
+            // the slot's adjoint does not depend on the agent: it goes out first, in flight with the
+            // agent load, and is pinned there (the empty asm) rather than sunk into the branch below
+            float ae = d.adj_ring[base + sl];
             const int a = d.tape_agent[tb1 + sl];
-            if (d.dep_t[sN + a] == t) d.depg[sN + a] = d.adj_ring[base + sl] * uj;
+            const int dta = d.dep_t[sN + a];
+            asm volatile("" : "+v"(ae));
+            if (dta == t) d.depg[sN + a] = ae * uj;
         }
     }
     gu = g.sum(gu);
@@ -1165,10 +1170,13 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
     if (d.gm) gm = g.sum(gm);
     // one non-returning atomic per accumulator: this group is the segment's only writer in the
     // launch, so the sum is the plain accumulator + contribution, without a read held in registers
+    // (a 32-bit byte offset, so the tail holds one register, not a 64-bit index: every link has at
+    // least four ring slots and scenarios x ring slots stay below 2^31, so seg < 2^29)
     if (gl == 0 && !init) {
-        unsafeAtomicAdd(&d.gu[seg], gu);
-        unsafeAtomicAdd(&d.gk[seg], gk);
-        if (d.gm) unsafeAtomicAdd(&d.gm[seg], gm);
+        const uint32_t off = (uint32_t)seg * 8u;
+        unsafeAtomicAdd((double *)((char *)d.gu + off), gu);
+        unsafeAtomicAdd((double *)((char *)d.gk + off), gk);
+        if (d.gm) unsafeAtomicAdd((double *)((char *)d.gm + off), gm);
     }
 }
 
@@ -1203,8 +1211,10 @@ __device__ __forceinline__ void reverse_launch(const Dev &d, int t, int tape_k, 
     else reverse_role<ring_lanes(3, G)>(3, b, nblk, t, tape_k, init, lds);
 }
 
+// six waves per SIMD (at most 80 VGPRs) keep a whole 1M-agent reverse step resident at once
 template <int G>
-__global__ __launch_bounds__(256) void k_reverse(Dev d, int t, int tape_k, int init)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G < 64 ? 6 : 1)))
+void k_reverse(Dev d, int t, int tape_k, int init)
 {
     const unsigned long long t0 = stamp_begin(d);
     reverse_launch<G>(d, t, tape_k, init);
