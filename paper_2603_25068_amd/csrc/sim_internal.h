@@ -138,8 +138,10 @@ struct Dev {
     // tape (replay window) and adjoint
     float *tape_pos;                 // [(W+1) * S * ring_total]
     int32_t *tape_agent;             // same
-    int32_t *tape_head, *tape_tail;  // [(W+1) * S * L]
-    int32_t *tape_hslot;             // [(W+1) * S * L] ring slot of the head (tape_head mod capacity)
+    int4 *tape_seg;                  // [(W+1) * S * L] per segment and state: (head counter, tail counter,
+                                     // ring slot of the head, departure mask: bit e set when the link's
+                                     // entrant of entry order e in this step left an origin; entrants per
+                                     // step <= lanes <= 8)
     int32_t *tape_dst;               // [(W+1) * S * L * maxl] entry slot of each leaving head (-1: exit)
     float *tape_dstg;                // same shape as tape_dst: admission-graft factor -u_to dt_tok/dm
     int4 *tape_ste;                  // [(W+1) * S * n_cand] per node candidate: (agent, chosen out-link index |

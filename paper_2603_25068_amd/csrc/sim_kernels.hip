@@ -301,11 +301,8 @@ __device__ __forceinline__ void link_segment(const Dev &d, const Group<G> &g, in
     int64_t tb = -1;
     if (TAPE) {   // a recording step (tape_k >= 0)
         tb = (int64_t)tape_k * d.S * d.ring_total + base;
-        if (gl == 0) {
-            d.tape_head[(int64_t)tape_k * d.S * d.L + seg] = h0;
-            d.tape_tail[(int64_t)tape_k * d.S * d.L + seg] = h0 + n;
-            d.tape_hslot[(int64_t)tape_k * d.S * d.L + seg] = hm;
-        }
+        // (head, tail, head slot, departure mask): the node phase sets the mask's bits
+        if (gl == 0) d.tape_seg[(int64_t)tape_k * d.S * d.L + seg] = make_int4(h0, h0 + n, hm, 0);
     }
     // a ring keeps `lanes` slots free, so an entry slot never aliases a slot live one step earlier
     if (gl == 0 && n_raw > cap - ln) atomicOr(&d.err[ERR_RING_OVERFLOW], 1);
@@ -911,6 +908,9 @@ __device__ __forceinline__ void node_work(const Dev &d, const Group<G> &g, int s
             if (origin >= 0) {
                 d.status[ga] = AG_ON;
                 d.dep_t[ga] = t;
+                // a departure: its entry order on the link, for the reverse's departure grafts
+                // (erank < entry slots <= lanes <= kMaxLanes)
+                if (tape_k >= 0) atomicOr(&d.tape_seg[(int64_t)tape_k * d.S * d.L + sL + ch].w, 1 << erank);
                 d.dep_ptr[s * d.O + origin] = dp0 + 1;
                 small += nf_one(NF_DEPARTED);
             } else {
@@ -988,11 +988,7 @@ __global__ __launch_bounds__(256) void k_tape_snapshot(Dev d, int tape_k)
     const int h0 = d.ls[seg].rhead, n = d.ls[seg].rtail - h0, cap = d.cap[j];
     const int64_t base = (int64_t)s * d.ring_total + d.ring_base[j];
     const int64_t tb = (int64_t)tape_k * d.S * d.ring_total + base;
-    if (lane == 0) {
-        d.tape_head[(int64_t)tape_k * d.S * d.L + seg] = h0;
-        d.tape_tail[(int64_t)tape_k * d.S * d.L + seg] = h0 + n;
-        d.tape_hslot[(int64_t)tape_k * d.S * d.L + seg] = h0 % cap;
-    }
+    if (lane == 0) d.tape_seg[(int64_t)tape_k * d.S * d.L + seg] = make_int4(h0, h0 + n, h0 % cap, 0);
     for (int r = lane; r < n; r += kWave) {
         const int slot = (h0 + r) % cap;
         d.tape_pos[tb + slot] = d.ring_pos[base + slot];
@@ -1038,9 +1034,10 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
     // (a head that left has rank < lanes <= maxl <= G, so rank gl's is lane gl's)
     const LinkCf lc = d.lcf[seg];
     const RevCf rc = d.rcf[seg];
-    const int hk = d.tape_head[ek], tk = d.tape_tail[ek];
-    const int hm = d.tape_hslot[ek];               // hk mod cap, taped by the forward
-    const int hk1 = d.tape_head[ek1], tk1 = d.tape_tail[ek1];
+    const int4 ts = d.tape_seg[ek];                // (head, tail, head slot = head mod cap, departures)
+    const int hk = ts.x, tk = ts.y, hm = ts.z;
+    const int depm = init ? 0 : ts.w;              // entry orders of this step's departures
+    const int hk1 = d.tape_seg[ek1].x;
     const int ds_l = init ? -1 : d.tape_dst[ek * d.maxl + min(gl, d.maxl - 1)];
     const double gTs = d.gT ? d.gT[s] : 0.0;
     const int cap = lc.cap, ln = lc.lanes;
@@ -1048,8 +1045,6 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
     const int npass = init ? 0 : min(hk1 - hk, ln);
     // lane gl's head: its entry slot if it left during step t (-1: it left the network), else -2
     const int dsx = gl < npass ? ds_l : -2;
-    // agents that entered during step t hold ranks n .. n + ne - 1 at t+1 (the ring's free slots)
-    const int ne = init ? 0 : max(0, min(tk1 - tk, cap - n));
     const int64_t base = (int64_t)s * d.ring_total + lc.ring_base;
     const int64_t RTS = (int64_t)d.S * d.ring_total;
     const int64_t tb = (int64_t)tape_k * RTS + base;
@@ -1152,18 +1147,12 @@ __device__ __forceinline__ void reverse_segment(const Dev &d, const Group<G> &g,
         wave_lds_sync();
     }
     // departure grafts of the agents that entered this link during step t
-    if (d.depg) {   // entrants (counted from the taped tails read with the segment's header)
-        const int64_t tb1 = (int64_t)(tape_k + 1) * RTS + base;
-        for (int q = n + gl; q < n + ne; q += G) {
-            const int sl = slot_of(q);
-            // the slot's adjoint does not depend on the agent: it goes out first, in flight with the
-            // agent load, and is pinned there (the empty asm) rather than sunk into the branch below
-            float ae = d.adj_ring[base + sl];
-            const int a = d.tape_agent[tb1 + sl];
-            const int dta = d.dep_t[sN + a];
-            asm volatile("" : "+v"(ae));
-            if (dta == t) d.depg[sN + a] = ae * uj;
-        }
+    // an entrant of entry order e holds rank n + e at t+1 (the ring's free slots); the departures
+    // among them are marked in the taped mask, so the agent and its adjoint are read together
+    if (d.depg && gl < kMaxLanes && ((depm >> gl) & 1)) {
+        const int sl = slot_of(n + gl);
+        const int a = d.tape_agent[(int64_t)(tape_k + 1) * RTS + base + sl];
+        d.depg[sN + a] = d.adj_ring[base + sl] * uj;
     }
     gu = g.sum(gu);
     gk = g.sum(gk);

@@ -109,7 +109,8 @@ struct sim_t {
     // others, on their own streams; the recording forward fills the sets of the last windows
     struct TapeSet {
         float *pos = nullptr, *dstg = nullptr;
-        int32_t *agent = nullptr, *head = nullptr, *tail = nullptr, *hslot = nullptr, *dst = nullptr;
+        int32_t *agent = nullptr, *dst = nullptr;
+        int4 *seg = nullptr;   // (head, tail, head slot, departure mask) per segment
         int4 *ste = nullptr;   // node candidates' choices and outcomes (straight-through gradients)
     };
     std::vector<TapeSet> tapes;              // n_tape_sets sets
@@ -911,10 +912,11 @@ void prepare_host(sim_t *h, const sim_network *net, const sim_demand *dem, const
         n_ck = (h->max_steps + h->ckpt_every - 1) / h->ckpt_every + 1;
         h->W = h->ckpt_every;
         bytes += (size_t)n_ck * (SR * 16 + SL * 40 + SO * 16 + SN);
-        // one tape set: positions and agents per slot, head/tail per segment, entry slot and graft factor
+        // one tape set: positions and agents per slot, head/tail/head slot/departure mask per segment,
+        // entry slot and graft factor
         // per leaving head, and a straight-through record per node candidate, for W + 1 states
         const size_t per_set = (size_t)(h->W + 1) *
-                               (SR * 8 + SL * 12 + SL * maxl * 8 + (size_t)h->S * std::max(h->n_cand, 1) * 16);
+                               (SR * 8 + SL * 16 + SL * maxl * 8 + (size_t)h->S * std::max(h->n_cand, 1) * 16);
         const int min_sets = h->n_replay + 1, windows = std::max(n_ck - 1, 1);
         int sets = cfg->tape_windows > 0 ? std::max(min_sets, (int)cfg->tape_windows)
                                          : (int)std::min<size_t>(16, ((size_t)32 << 30) / std::max<size_t>(per_set, 1));
@@ -1021,15 +1023,13 @@ void allocate_device(sim_t *h, const sim_config *cfg)
         for (auto &ts : h->tapes) {
             ts.pos = h->dalloc<float>((size_t)(h->W + 1) * SR);
             ts.agent = h->dalloc<int32_t>((size_t)(h->W + 1) * SR);
-            ts.head = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
-            ts.tail = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
-            ts.hslot = h->dalloc<int32_t>((size_t)(h->W + 1) * SL);
+            ts.seg = h->dalloc<int4>((size_t)(h->W + 1) * SL);
             ts.dst = h->dalloc<int32_t>((size_t)(h->W + 1) * SL * maxl);
             ts.dstg = h->dalloc<float>((size_t)(h->W + 1) * SL * maxl);
             ts.ste = h->dalloc<int4>((size_t)(h->W + 1) * h->S * std::max(h->n_cand, 1));
         }
         d.tape_pos = h->tapes[0].pos; d.tape_agent = h->tapes[0].agent;
-        d.tape_head = h->tapes[0].head; d.tape_tail = h->tapes[0].tail; d.tape_hslot = h->tapes[0].hslot;
+        d.tape_seg = h->tapes[0].seg;
         h->rp_dev.assign((size_t)h->n_replay, d);
         h->rp_stream.assign((size_t)h->n_replay, nullptr);
         for (int k = 0; k < h->n_replay; ++k) {
@@ -1475,8 +1475,7 @@ int sim_rollout(sim_t *h, int32_t T)
                 const bool contiguous = h->tape_win[set] == w && h->tape_steps[set] == kw;
                 Dev dt = h->d;
                 const auto &ts = h->tapes[set];
-                dt.tape_pos = ts.pos; dt.tape_agent = ts.agent; dt.tape_head = ts.head; dt.tape_tail = ts.tail;
-                dt.tape_hslot = ts.hslot;
+                dt.tape_pos = ts.pos; dt.tape_agent = ts.agent; dt.tape_seg = ts.seg;
                 dt.tape_dst = ts.dst; dt.tape_dstg = nullptr; dt.tape_ste = nullptr;
                 step_on(h, dt, h->stream, h->t, contiguous ? kw : -1);
                 h->t += 1;
@@ -1564,8 +1563,7 @@ int sim_backward(sim_t *h, const float *dL_dcounts, const double *dL_dttt, const
         hipEvent_t start = h->bw_events[2 * (size_t)nw];
         auto use_tapes = [&](Dev &dv, int set) {
             const auto &ts = h->tapes[set];
-            dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_head = ts.head; dv.tape_tail = ts.tail;
-            dv.tape_hslot = ts.hslot;
+            dv.tape_pos = ts.pos; dv.tape_agent = ts.agent; dv.tape_seg = ts.seg;
             dv.tape_dst = ts.dst;
             dv.tape_dstg = want_m ? ts.dstg : nullptr;
             dv.tape_ste = want_ste ? ts.ste : nullptr;
