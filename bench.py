@@ -562,7 +562,13 @@ def main():
     sim.set_timing(False)
     moves = st["transfers"] + st["exited"] + st["departed"]
     kinds = {k: v for k, v in tm.items() if k in ("link", "node", "reverse") and v[1] > 0}
-    dom = max(kinds, key=lambda k: kinds[k][0])
+    # the kernel with the largest share of device time: HIP events around each launch on its stream
+    # (the ordering rocprofv3's trace totals give too); the waves' own stamps, which leave out each
+    # launch's dispatch and drain, only when no events were taken
+    def device_ms(k):
+        ev = tm.get(k + "_ev", (0.0, 0))
+        return ev[0] if ev[1] else kinds[k][0]
+    dom = max(kinds, key=device_ms)
     ms_tot, launches = kinds[dom]
     self_us = 1000.0 * ms_tot / launches
     ev_ms, ev_n = tm.get(dom + "_ev", (0.0, 0))
