@@ -168,6 +168,9 @@ struct sim_t {
     int W = 0;                // tape window (= ckpt_every)
     bool rec_valid = false;
     std::vector<uint8_t> placed;  // agents put on links by sim_place (not in the origin queues)
+    // the host and device origin queues hold every agent (no placement): a reset then has nothing
+    // to rebuild, since the queues depend only on the demand fixed at create and the placed mask
+    bool queues_unplaced = false;
 
     // timing
     bool timing = false;
@@ -970,6 +973,7 @@ void allocate_device(sim_t *h, const sim_config *cfg)
     h->q_rstep_dev = h->dalloc<int64_t>(h->q_rstep.size());
     h->cand_dev = h->dalloc<int2>(h->cand.size());
     upload_queues(h);
+    h->queues_unplaced = h->placed.empty();   // the queues of create: every agent waits at its origin
     d.q_off = h->q_off_dev; d.q_list = h->q_list_dev; d.q_rstep = h->q_rstep_dev;
     d.q_dest = h->q_dest_dev; d.q_didx = h->q_didx_dev;
     d.node_cnt = h->upload(h->node_cnt); d.in_pad = h->upload(h->in_pad); d.out_pad = h->upload(h->out_pad);
@@ -1365,8 +1369,11 @@ int sim_reset(sim_t *h)
 {
     return guarded(h, [&] {
         h->placed.clear();
-        build_queues(h, nullptr);
-        upload_queues(h);
+        if (!h->queues_unplaced) {
+            build_queues(h, nullptr);
+            upload_queues(h);
+            h->queues_unplaced = true;
+        }
         zero_state(h);
         HIPCHK(hipStreamSynchronize(h->stream));
     });
@@ -1432,6 +1439,7 @@ int sim_place(sim_t *h, int32_t n, const int32_t *agent, const int32_t *link, co
         HIPCHK(hipMemcpyAsync(h->d.dep_t, dept.data(), SN * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.ctr, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice, h->stream));
         h->placed = placed;
+        h->queues_unplaced = false;
         build_queues(h, &h->placed);
         upload_queues(h);
         HIPCHK(hipStreamSynchronize(h->stream));
@@ -1811,8 +1819,10 @@ int sim_set_full_state(sim_t *h, const void *blob, size_t n)
         for (int i = 0; i < h->N; ++i) any |= pl[i] != 0;
         if (any) h->placed.assign(pl, pl + h->N);
         else h->placed.clear();
+        h->queues_unplaced = false;
         build_queues(h, any ? &h->placed : nullptr);
         upload_queues(h);
+        h->queues_unplaced = !any;
         HIPCHK(hipMemsetAsync(h->d.tie_n, 0, 4, h->stream));   // the log restarts with the restored run
         h->t = hd.t;
         h->rec_valid = h->record && hd.t == 0;

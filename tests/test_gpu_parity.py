@@ -685,6 +685,36 @@ def test_full_state_round_trip():
     assert np.array_equal(p.state()["pos"], q.state()["pos"])
 
 
+
+@pytest.mark.parametrize("mk", [W.small_grid_fixed,
+                                lambda: W.random_small(11, nx=4, ny=4, n_agents=400, rates=True, steps=300)])
+def test_reset_after_placement_restores_the_origin_queues(mk):
+    """A reset keeps the origin queues it built while no agent was placed and
+    rebuilds them once a placement (sim_place, or a restored state carrying
+    placed agents) has taken agents out of them: every rollout after a reset
+    equals the oracle's rollout without placement."""
+    w = mk()
+    T = min(w.cfg.steps, 300)
+    o = Oracle(w)
+    for _ in range(T):
+        o.step()
+    s = _sim(w)
+    s.step(T)
+    _compare_state(o, s, ctx=f"{w.name} first rollout")
+    for case in ("reset", "place", "reset", "restore", "reset"):
+        if case == "place":
+            s.reset()
+            s.place([0, 1], [0, 1], [0.0, 0.0])
+            s.step(20)
+        elif case == "restore":
+            p = _sim(w)
+            p.place([0, 1], [0, 1], [0.0, 0.0])
+            s.set_full_state(p.full_state())
+            s.step(20)
+        s.reset()
+        s.step(T)
+        _compare_state(o, s, ctx=f"{w.name} rollout after {case}")
+
 def test_fast_gumbel_error_bound_exhaustive():
     """The single-precision Gumbel transform behind the fast decisions,
     against -log(-log U) in double for every one of the 2^24 values of
