@@ -157,7 +157,10 @@ int sim_set_params(sim_t *h, int which, const float *values, int64_t n, int on_d
 int sim_get_params(sim_t *h, int which, float *values, int64_t n, int on_device);
 
 /* Back to t = 0: empty network, all agents waiting, counters, buckets and
- * observables cleared.  Parameters are kept. */
+ * observables cleared.  Parameters are kept.  The origin queues are rebuilt
+ * on the host and uploaded only when a placement (sim_place, or a restored
+ * state with placed agents) has changed them since the last reset; otherwise
+ * the reset clears device state only and waits for the stream. */
 int sim_reset(sim_t *h);
 
 /* At t = 0 only: put agents on links at given positions (every scenario),
